@@ -1,0 +1,554 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (CPU only).
+
+Each test names the passage it pins.  None of them re-types the oracle's own formulas: they use
+values printed in the paper, closed forms, invariants, a library FFT, or an FFT-free dense
+Galerkin brute force (dense_galerkin.py).
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import dense_galerkin as dg
+from oracle import orc
+from paper_1508_02045_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+def _square_problem(N, rho):
+    ph = I.paper_square(N)
+    return I.phase_to_full(ph, I.iso_tables(len(N), [1.0, rho]))
+
+
+def _random_spd_field(N, rng, lo=1.0, hi=10.0):
+    return I.anisotropic_field(N, rng, lo, hi)
+
+
+# ------------------------------------------------------------------------------------------
+# DFT (eq:DFT): special case that reduces to a library routine
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(5, 7), (3, 5, 9), (15, 15)])
+def test_dft_matches_library_fft(shape):
+    rng = _rng(1)
+    c = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    n = np.prod(shape)
+    fw = orc.dft(c)
+    assert np.allclose(fw, np.fft.fftn(c) / n, rtol=0, atol=1e-14 * np.abs(c).max())
+    bw = orc.dft(c, inverse=True)
+    assert np.allclose(bw, np.fft.ifftn(c) * n, rtol=0, atol=1e-12 * np.abs(c).max() * n)
+
+
+# ------------------------------------------------------------------------------------------
+# Projection G (eq:proj, eq:discrete_proj): closed forms on trigonometric polynomials
+# ------------------------------------------------------------------------------------------
+def _trig_potential(N, n_grid, rng, extra_band=0):
+    """A random real trig polynomial phi with frequencies |k_a| <= (N_a-1)/2 + extra_band,
+    and its exact gradient, both sampled at the grid n_grid (signed index / n)."""
+    d = len(N)
+    rngs = [np.arange(-(n // 2) - extra_band, n // 2 + extra_band + 1) for n in N]
+    pts = dg.grid_points(n_grid)
+    phi = np.zeros(pts.shape[0])
+    grad = np.zeros((d, pts.shape[0]))
+    for k in itertools.product(*rngs):
+        k = np.array(k)
+        if not k.any():
+            continue
+        a, b = rng.standard_normal(2)
+        arg = 2 * np.pi * pts @ k
+        phi += a * np.cos(arg) + b * np.sin(arg)
+        for al in range(d):
+            grad[al] += 2 * np.pi * k[al] * (-a * np.sin(arg) + b * np.cos(arg))
+    return phi.reshape(n_grid), grad.reshape((d,) + tuple(n_grid))
+
+
+@pytest.mark.parametrize("N", [(5, 7), (5, 3, 7)])
+def test_projection_keeps_gradients_kills_rotations(N):
+    rng = _rng(2)
+    d = len(N)
+    _, grad = _trig_potential(N, N, rng)
+    assert np.allclose(orc.project(N, orc.GANI, grad), grad, atol=1e-11 * np.abs(grad).max())
+    # constant fields are killed (zero-mean constraint)
+    const = np.ones((d,) + N) * rng.standard_normal((d,) + (1,) * d)
+    assert np.abs(orc.project(N, orc.GANI, const)).max() < 1e-13
+    # a divergence-free rotation field (2D: (d2 psi, -d1 psi)) is killed
+    if d == 2:
+        psi_grad = grad
+        rot = np.stack([psi_grad[1], -psi_grad[0]])
+        assert np.abs(orc.project(N, orc.GANI, rot)).max() < 1e-11 * np.abs(rot).max()
+
+
+def test_projection_idempotent_selfadjoint_trace():
+    N = (5, 7)
+    d = 2
+    n = d * 35
+    Gm = np.empty((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        Gm[:, j] = orc.project(N, orc.GANI, e.reshape((d,) + N)).reshape(-1)
+    assert np.allclose(Gm @ Gm, Gm, atol=1e-13)
+    assert np.allclose(Gm, Gm.T, atol=1e-14)  # self-adjoint for the (1/|N|)-weighted product
+    assert abs(np.trace(Gm) - (35 - 1)) < 1e-10  # rank |N| - 1: gradients of zero-mean potentials
+
+
+def test_ga_projection_band_mask():
+    """G_{N,2N-1} keeps gradients of potentials in T_N sampled on the double grid and kills
+    frequencies outside Z_N (eq:discrete_proj)."""
+    rng = _rng(3)
+    N = (5, 7)
+    M = orc.double_grid(N)
+    _, grad = _trig_potential(N, M, rng)
+    assert np.allclose(orc.project(N, orc.GA, grad), grad, atol=1e-11 * np.abs(grad).max())
+    # a gradient made only of frequencies just outside Z_N (but inside Z_M) is removed
+    _, g_all = _trig_potential(N, M, _rng(4), extra_band=1)
+    _, g_in = _trig_potential(N, M, _rng(5))
+    y = orc.project(N, orc.GA, g_all)
+    # the projection of g_all lies in the band: projecting again changes nothing
+    assert np.allclose(orc.project(N, orc.GA, y), y, atol=1e-11 * np.abs(y).max())
+    assert np.linalg.norm(y) < np.linalg.norm(g_all)
+    del g_in
+
+
+# ------------------------------------------------------------------------------------------
+# Ga coefficients (eq:Ga_exact_integration, eq:Ga_eval)
+# ------------------------------------------------------------------------------------------
+def test_printed_double_grid_coefficient_range():
+    """Sec. 4.1: A_{2N-1} of the square inclusion at N = 15 has eigenvalues in [-3.89, 108.89]."""
+    g = _golden("paper_values.json")["double_grid_coefficient_range_N15"]
+    N = (15, 15)
+    AM = orc.ga_assemble(N, _square_problem(N, 100.0))
+    lo, hi = AM[..., 0, 0].min(), AM[..., 0, 0].max()
+    assert abs(lo - g["min"]) <= g["tol_min"]
+    assert abs(hi - g["max"]) <= g["tol_max"]
+    assert np.abs(AM[..., 0, 1]).max() == 0.0 and np.allclose(AM[..., 1, 1], AM[..., 0, 0])
+
+
+def test_ga_assembly_matches_pixel_integrals():
+    """Double-grid values equal the truncated exact Fourier series of the pixel-wise function,
+    with the coefficients integrated pixel by pixel in closed form (no DFT)."""
+    rng = _rng(6)
+    N = (5, 7)
+    A = _random_spd_field(N, rng)
+    AM = orc.ga_assemble(N, A)
+    M = orc.double_grid(N)
+    nv = np.array(list(itertools.product(range(-(N[0] - 1), N[0]), range(-(N[1] - 1), N[1]))))
+    Ah = dg.pixel_fourier_coeffs(N, A, nv)
+    pts = dg.grid_points(M)
+    for j in [0, 5, 17, 40, len(pts) - 1]:
+        val = np.einsum("v,vab->ab", np.exp(2j * np.pi * nv @ pts[j]), Ah).real
+        idx = np.unravel_index(j, M)
+        assert np.allclose(AM[idx], val, atol=1e-12 * np.abs(A).max())
+
+
+def test_double_grid_rule_integrates_exactly():
+    """eq:Ga_eval: int A u v = (A_{2N-1} I[u], I[v]) on the double grid for u, v in T_N."""
+    rng = _rng(7)
+    N = (5, 3)
+    d = 2
+    A = _random_spd_field(N, rng)
+    M = orc.double_grid(N)
+    # random trig polynomials (vector valued) with frequencies in Z_N
+    K = np.array(list(itertools.product(range(-2, 3), range(-1, 2))))
+    cu = rng.standard_normal((len(K), d)) + 1j * rng.standard_normal((len(K), d))
+    cv = rng.standard_normal((len(K), d)) + 1j * rng.standard_normal((len(K), d))
+
+    def real_field(c, pts):
+        return (np.exp(2j * np.pi * pts @ K.T) @ c).real.T  # [d, npts]
+
+    pts = dg.grid_points(M)
+    u = real_field(cu, pts).reshape((d,) + M)
+    v = real_field(cv, pts).reshape((d,) + M)
+    lhs = orc.bilinear(N, orc.GA, orc.ga_assemble(N, A), np.zeros(d), u, np.zeros(d), v)
+    # exact: Re-fields u = (e(x) + conj e(x))/2 with e(x) = sum_k c_k exp(2 pi i k x)
+    # int A u v = sum over pairs of exponentials of A^(-(k + l)) contractions
+    Kfull = np.concatenate([K, -K])
+    cu_f = np.concatenate([cu, cu.conj()]) / 2
+    cv_f = np.concatenate([cv, cv.conj()]) / 2
+    pairs = (Kfull[:, None, :] + Kfull[None, :, :]).reshape(-1, d)
+    Ah = dg.pixel_fourier_coeffs(N, A, -pairs).reshape(len(Kfull), len(Kfull), d, d)
+    exact = np.einsum("ka,klab,lb->", cu_f, Ah, cv_f)
+    assert abs(exact.imag) < 1e-10
+    assert abs(lhs - exact.real) < 1e-11 * max(1.0, abs(exact.real))
+
+
+def test_prolongation_interpolates_trig_polynomials():
+    """R_{N,2N-1} = I_{2N-1} o I_N^{-1}: exact for fields in T_N (eq:ev_bounds_GaNi)."""
+    rng = _rng(8)
+    N = (5, 7)
+    M = orc.double_grid(N)
+    _, gN = _trig_potential(N, N, _rng(9))
+    _, gM = _trig_potential(N, M, _rng(9))
+    assert np.allclose(orc.prolong(N, gN), gM, atol=1e-11 * np.abs(gM).max())
+    del rng
+
+
+def test_spectral_bounds_closed_form():
+    rng = _rng(10)
+    R = I.haar_rotations(50, 3, rng)
+    lam = rng.uniform(0.5, 7.0, size=(50, 3))
+    A = np.einsum("nki,nk,nkj->nij", R, lam, R)
+    lo, hi = orc.spectral_bounds(A)
+    assert abs(lo - lam.min()) < 1e-12 and abs(hi - lam.max()) < 1e-12
+    A2 = np.array([[[2.0, 1.0], [1.0, 2.0]]])  # eigenvalues 1 and 3
+    assert np.allclose(orc.spectral_bounds(A2), (1.0, 3.0), atol=1e-14)
+
+
+# ------------------------------------------------------------------------------------------
+# Printed numbers of Sec. 4 (square inclusion, contrast 100, E = [1; 0])
+# ------------------------------------------------------------------------------------------
+def test_printed_guaranteed_bounds_square_85():
+    """Sec. 4.3: GaNi bound 2.793, Ga 2.241 for the 85 x 85 square inclusion."""
+    g = _golden("paper_values.json")["guaranteed_bounds_square_85"]
+    N = (85, 85)
+    A = _square_problem(N, 100.0)
+    E = np.array([1.0, 0.0])
+    r = orc.solve(N, orc.GANI, A, E, "cg", 1.0, 100.0, 1e-10)
+    assert r.status == orc.OK
+    AM = orc.ga_assemble(N, A)
+    bound = orc.energy(N, orc.GA, AM, E, orc.prolong(N, r.e))
+    r2 = orc.solve(N, orc.GA, AM, E, "cg", 1.0, 100.0, 1e-10)
+    assert r2.status == orc.OK
+    ga = orc.energy(N, orc.GA, AM, E, r2.e)
+    assert abs(bound - g["gani_bound"]) <= g["tol"]
+    assert abs(ga - g["ga"]) <= g["tol"]
+    # eq:bounds ordering: A_H,N (Ga) <= GaNi bound
+    assert ga <= bound
+
+
+def test_printed_rank_and_null_spaces_15():
+    """Sec. 4.1: at 15 x 15, C has rank 224 for both rules; null spaces 226 (GaNi, of 450) and
+    1458 (Ga, of 1682); non-zero eigenvalues inside [1, 100]."""
+    g = _golden("paper_values.json")["rank_square_15"]
+    N = (15, 15)
+    A = _square_problem(N, 100.0)
+    for rule, A_op, nfull in ((orc.GANI, A, 450), (orc.GA, orc.ga_assemble(N, A), 1682)):
+        grid = orc.op_grid(N, rule)
+        n = 2 * int(np.prod(grid))
+        assert n == nfull
+        C = np.empty((n, n))
+        for j in range(n):
+            e = np.zeros(n)
+            e[j] = 1.0
+            C[:, j] = orc.apply(N, rule, A_op, e.reshape((2,) + grid)).reshape(-1)
+        ev = np.linalg.eigvals(C)
+        nz = ev[np.abs(ev) > 1e-8]
+        assert len(nz) == g["rank"]
+        assert n - len(nz) == (g["null_gani"] if rule == orc.GANI else g["null_ga"])
+        assert np.abs(nz.imag).max() < 1e-8
+        assert nz.real.min() >= 1.0 - 1e-9 and nz.real.max() <= 100.0 + 1e-9
+
+
+# ------------------------------------------------------------------------------------------
+# Closed forms: homogeneous medium, laminates
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("solver", ["richardson", "cg", "chebyshev", "eyre_milton"])
+def test_homogeneous_medium(solver):
+    """A constant: b = 0, A_H = A; CG/Chebyshev stop before the first body, Richardson and
+    Eyre-Milton after one (repeat-until loops)."""
+    rng = _rng(11)
+    N = (5, 7, 3)
+    R = I.haar_rotations(1, 3, rng)[0]
+    A0 = R.T @ np.diag([1.0, 2.0, 5.0]) @ R
+    A = np.broadcast_to(A0, N + (3, 3)).copy()
+    fields = []
+    for j in range(3):
+        E = np.eye(3)[j]
+        r = orc.solve(N, orc.GANI, A, E, solver, 1.0, 5.0, 1e-8)
+        assert r.status == orc.OK
+        assert r.iters == (0 if solver in ("cg", "chebyshev") else 1)
+        assert np.abs(r.e).max() < 1e-13
+        fields.append(r.e)
+    AH = orc.effective_tensor(N, orc.GANI, A, fields)
+    assert np.allclose(AH, A0, atol=1e-13)
+
+
+def test_laminate_gani_harmonic_and_arithmetic_means():
+    """Pixel-aligned laminate: across the layers A_H is the harmonic mean, along them the
+    arithmetic mean; CG converges in a single iteration for two phases."""
+    N = (7, 5)
+    layers = [1, 1, 0, 0, 1, 0, 0]
+    ph = I.laminate(N, 0, layers)
+    vals = [1.0, 5.0]
+    A = I.phase_to_full(ph, I.iso_tables(2, vals))
+    f1 = np.mean(layers)
+    harm = 1.0 / ((1 - f1) / vals[0] + f1 / vals[1])
+    arith = (1 - f1) * vals[0] + f1 * vals[1]
+    r0 = orc.solve(N, orc.GANI, A, np.array([1.0, 0.0]), "cg", 1.0, 5.0, 1e-10)
+    r1 = orc.solve(N, orc.GANI, A, np.array([0.0, 1.0]), "cg", 1.0, 5.0, 1e-10)
+    assert r0.iters == 1 and r1.iters == 0
+    AH = orc.effective_tensor(N, orc.GANI, A, [r0.e, r1.e])
+    assert abs(AH[0, 0] - harm) < 1e-13 and abs(AH[1, 1] - arith) < 1e-13
+    assert abs(AH[0, 1]) < 1e-13
+
+
+def test_laminate_ga_between_harmonic_and_gani_bound():
+    N = (9, 5)
+    layers = [1, 1, 1, 0, 0, 0, 0, 1, 0]
+    ph = I.laminate(N, 0, layers)
+    vals = [1.0, 5.0]
+    A = I.phase_to_full(ph, I.iso_tables(2, vals))
+    f1 = np.mean(layers)
+    harm = 1.0 / ((1 - f1) / vals[0] + f1 / vals[1])
+    arith = (1 - f1) * vals[0] + f1 * vals[1]
+    AM = orc.ga_assemble(N, A)
+    E0, E1 = np.eye(2)
+    ra = orc.solve(N, orc.GA, AM, E0, "cg", 1.0, 5.0, 1e-12)
+    rb = orc.solve(N, orc.GA, AM, E1, "cg", 1.0, 5.0, 1e-12)
+    assert rb.iters == 0  # load along the layers: b = 0
+    across = orc.energy(N, orc.GA, AM, E0, ra.e)
+    along = orc.energy(N, orc.GA, AM, E1, rb.e)
+    assert abs(along - arith) < 1e-12
+    rn = orc.solve(N, orc.GANI, A, E0, "cg", 1.0, 5.0, 1e-12)
+    bound = orc.energy(N, orc.GA, AM, E0, orc.prolong(N, rn.e))
+    assert harm - 1e-12 <= across <= bound + 1e-12
+    assert across > harm + 1e-3  # Ga is strictly above the true (harmonic) value here
+
+
+# ------------------------------------------------------------------------------------------
+# Brute force: dense Galerkin without FFTs (grids <= 9^d)
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("N", [(5, 7), (9, 9), (5, 5, 3)])
+def test_gani_matches_dense_galerkin(N):
+    rng = _rng(12)
+    d = len(N)
+    A = _random_spd_field(N, rng, 1.0, 20.0)
+    E = rng.standard_normal(d)
+    e_ref, en_ref = dg.gani_solve(N, A, E)
+    cA, CA = orc.spectral_bounds(A)
+    for solver in ("cg", "chebyshev", "richardson", "eyre_milton"):
+        r = orc.solve(N, orc.GANI, A, E, solver, cA, CA, 1e-12, max_iter=20000)
+        assert r.status == orc.OK, solver
+        scale = np.linalg.norm(E) * np.sqrt(np.prod(N))
+        assert np.linalg.norm(r.e - e_ref) / scale < 1e-9, solver
+        en = orc.energy(N, orc.GANI, A, E, r.e)
+        assert abs(en - en_ref) / abs(en_ref) < 1e-12, solver
+
+
+@pytest.mark.parametrize("N", [(5, 7), (7, 7), (3, 5, 3)])
+def test_ga_matches_dense_galerkin(N):
+    rng = _rng(13)
+    d = len(N)
+    A = _random_spd_field(N, rng, 1.0, 20.0)
+    E = rng.standard_normal(d)
+    e_ref, en_ref = dg.ga_solve(N, A, E)
+    AM = orc.ga_assemble(N, A)
+    cA, CA = orc.spectral_bounds(A)
+    for solver in ("cg", "chebyshev", "richardson"):
+        r = orc.solve(N, orc.GA, AM, E, solver, cA, CA, 1e-12, max_iter=20000)
+        assert r.status == orc.OK, solver
+        M = orc.double_grid(N)
+        scale = np.linalg.norm(E) * np.sqrt(np.prod(M))
+        assert np.linalg.norm(r.e - e_ref) / scale < 1e-9, solver
+        en = orc.energy(N, orc.GA, AM, E, r.e)
+        assert abs(en - en_ref) / abs(en_ref) < 1e-12, solver
+
+
+# ------------------------------------------------------------------------------------------
+# Bounds and invariants of A_H
+# ------------------------------------------------------------------------------------------
+def _hs_scalar(s1, s2, f2, d):
+    f1 = 1 - f2
+    lower = s1 + f2 / (1.0 / (s2 - s1) + f1 / (d * s1))
+    upper = s2 + f1 / (1.0 / (s1 - s2) + f2 / (d * s2))
+    return lower, upper
+
+
+@pytest.mark.parametrize("d,n", [(2, 15), (3, 7)])
+def test_voigt_reuss_hashin_shtrikman(d, n):
+    N = (n,) * d
+    rho = 20.0
+    ph = I.centred_box(N, n // 4)
+    A = I.phase_to_full(ph, I.iso_tables(d, [1.0, rho]))
+    f2 = ph.mean()
+    voigt = (1 - f2) + f2 * rho
+    reuss = 1.0 / ((1 - f2) + f2 / rho)
+    hs_lo, hs_hi = _hs_scalar(1.0, rho, f2, d)
+    AM = orc.ga_assemble(N, A)
+    res = {}
+    for rule, Aop in ((orc.GANI, A), (orc.GA, AM)):
+        fields = [orc.solve(N, rule, Aop, np.eye(d)[j], "cg", 1.0, rho, 1e-11).e for j in range(d)]
+        AH = orc.effective_tensor(N, rule, Aop, fields)
+        ev = np.linalg.eigvalsh(0.5 * (AH + AH.T))
+        assert np.allclose(AH, AH.T, atol=1e-12)
+        assert ev.min() >= reuss - 1e-10 and ev.max() <= voigt + 1e-10
+        # cubic symmetry: isotropic A_H
+        assert np.allclose(AH, AH[0, 0] * np.eye(d), atol=1e-9)
+        res[rule] = AH[0, 0]
+    # Ga is an upper bound on the true A_H, which lies above the HS lower bound
+    assert res[orc.GA] >= hs_lo - 1e-12
+    assert hs_lo <= res[orc.GANI] <= hs_hi
+
+
+def test_ga_below_gani_bound_per_load():
+    """eq:bounds: A_H,N (Ga) <= A~_H,N^bound in the quadratic form, for random loads."""
+    rng = _rng(14)
+    N = (7, 9)
+    A = _random_spd_field(N, rng, 1.0, 30.0)
+    AM = orc.ga_assemble(N, A)
+    cA, CA = orc.spectral_bounds(A)
+    for _ in range(3):
+        E = rng.standard_normal(2)
+        rg = orc.solve(N, orc.GA, AM, E, "cg", cA, CA, 1e-12)
+        rn = orc.solve(N, orc.GANI, A, E, "cg", cA, CA, 1e-12)
+        ga = orc.energy(N, orc.GA, AM, E, rg.e)
+        bound = orc.energy(N, orc.GA, AM, E, orc.prolong(N, rn.e))
+        assert ga <= bound + 1e-12
+
+
+def test_metamorphic_shift_permutation_scaling():
+    rng = _rng(15)
+    N = (7, 9)
+    A = _random_spd_field(N, rng, 1.0, 10.0)
+    cA, CA = orc.spectral_bounds(A)
+    AM = orc.ga_assemble(N, A)
+
+    def AH(Af, rule):
+        Aop = Af if rule == orc.GANI else orc.ga_assemble(N if Af.shape[:2] == N else Af.shape[:2], Af)
+        NN = Af.shape[:2]
+        fields = [orc.solve(NN, rule, Aop, np.eye(2)[j], "cg", cA, CA, 1e-12).e for j in range(2)]
+        return orc.effective_tensor(NN, rule, Aop, fields)
+
+    for rule in (orc.GANI, orc.GA):
+        base = AH(A, rule)
+        shifted = AH(np.roll(A, (2, -3), axis=(0, 1)), rule)
+        assert np.allclose(shifted, base, atol=1e-11)
+        # transpose the grid axes and the tensor indices: A_H permutes
+        At = np.transpose(A, (1, 0, 2, 3))[..., ::-1, ::-1].copy()
+        perm = AH(At, rule)
+        assert np.allclose(perm, base[::-1, ::-1], atol=1e-11)
+    # scaling: A -> s A gives A_H -> s A_H, the same fields and the same count
+    E = np.array([1.0, 0.3])
+    r1 = orc.solve(N, orc.GANI, A, E, "cg", cA, CA, 1e-10)
+    r2 = orc.solve(N, orc.GANI, 3.0 * A, E, "cg", 3 * cA, 3 * CA, 1e-10)
+    assert r1.iters == r2.iters
+    assert np.allclose(r1.e, r2.e, atol=1e-12)
+    del AM
+
+
+def test_multi_rhs_bilinear_symmetric():
+    rng = _rng(16)
+    N = (5, 5, 5)
+    A = _random_spd_field(N, rng, 1.0, 100.0)
+    cA, CA = orc.spectral_bounds(A)
+    fields = [orc.solve(N, orc.GANI, A, np.eye(3)[j], "cg", cA, CA, 1e-9).e for j in range(3)]
+    AH = orc.effective_tensor(N, orc.GANI, A, fields)
+    assert np.allclose(AH, AH.T, rtol=0, atol=1e-10 * np.abs(AH).max())
+    assert np.linalg.eigvalsh(AH).min() > 0
+    flux = np.stack([orc.flux(N, orc.GANI, A, np.eye(3)[j], fields[j]) for j in range(3)], axis=1)
+    assert np.allclose(flux, AH, rtol=1e-6)
+
+
+# ------------------------------------------------------------------------------------------
+# Solver facts (Sec. 3, Table 1)
+# ------------------------------------------------------------------------------------------
+def test_eyre_milton_fixed_point_mean_is_E():
+    """The fixed point of Alg. 4 is E + e with e curl-free of zero mean (the q-term sign that
+    makes the k = 0 mode of the fixed-point equation consistent)."""
+    N = (15, 15)
+    A = _square_problem(N, 100.0)
+    E = np.array([1.0, 0.0])
+    r = orc.solve(N, orc.GANI, A, E, "eyre_milton", 1.0, 100.0, 1e-10)
+    assert r.status == orc.OK
+    assert np.abs(r.e.mean(axis=(1, 2))).max() < 1e-9
+    rc = orc.solve(N, orc.GANI, A, E, "cg", 1.0, 100.0, 1e-12)
+    assert abs(orc.energy(N, orc.GANI, A, E, r.e) - orc.energy(N, orc.GANI, A, E, rc.e)) < 1e-8
+
+
+def test_eyre_milton_diverges_for_ga():
+    """Sec. 3.4: Eyre-Milton does not converge for the Ga system."""
+    N = (15, 15)
+    A = _square_problem(N, 100.0)
+    AM = orc.ga_assemble(N, A)
+    r = orc.solve(N, orc.GA, AM, np.array([1.0, 0.0]), "eyre_milton", 1.0, 100.0, 1e-6, max_iter=400)
+    assert r.status in (orc.E_DIVERGED, orc.E_NO_CONVERGENCE)
+    assert r.res_hist[-1] > r.res_hist[1]
+
+
+def test_conforming_iterates():
+    """Table 1: Richardson, CG and Chebyshev iterates stay in E (curl-free, zero mean);
+    Eyre-Milton's do not."""
+    N = (15, 15)
+    A = _square_problem(N, 100.0)
+    E = np.array([1.0, 0.0])
+    for solver in ("richardson", "cg", "chebyshev"):
+        r = orc.solve(N, orc.GANI, A, E, solver, 1.0, 100.0, 1e-6, fixed_iters=7)
+        nc = np.linalg.norm(orc.project(N, orc.GANI, r.e) - r.e) / np.linalg.norm(r.e)
+        assert nc < 1e-13, solver
+    r = orc.solve(N, orc.GANI, A, E, "eyre_milton", 1.0, 100.0, 1e-6, fixed_iters=3)
+    nc = np.linalg.norm(orc.project(N, orc.GANI, r.e) - r.e) / np.linalg.norm(r.e)
+    assert nc > 1e-3
+
+
+def test_richardson_is_moulinec_suquet():
+    """Footnote of Sec. 3.1: x_m = x_{m-1} - Gamma0 A (E + x_{m-1}), Gamma0 = G / c0,
+    c0 = (c_A + C_A)/2, generates the Richardson iterates."""
+    N = (9, 7)
+    A = _square_problem(N, 10.0)
+    E = np.array([0.6, -0.8])
+    c0 = (1.0 + 10.0) / 2
+    x = np.zeros((2,) + N)
+    for _ in range(5):
+        AE = np.einsum("...ab,b...->a...", A, (E[:, None, None] + x))
+        x = x - orc.project(N, orc.GANI, AE) / c0
+    r = orc.solve(N, orc.GANI, A, E, "richardson", 1.0, 10.0, 1e-6, fixed_iters=5)
+    assert np.allclose(r.e, x, atol=1e-13)
+
+
+def test_iteration_counts_within_a_priori_estimates():
+    """eq:Richard_estimate, eq:CG_estimate, eq:E-M_estimate give upper bounds on iteration
+    counts; measured counts must not exceed generous versions of them."""
+    N = (31, 31)
+    rho = 100.0
+    A = _square_problem(N, rho)
+    E = np.array([1.0, 0.0])
+    kappa = rho
+    tol = 1e-6
+    q_rich = (kappa - 1) / (kappa + 1)
+    q_sqrt = (np.sqrt(kappa) - 1) / (np.sqrt(kappa) + 1)
+    # residual-based counts relate to the error bounds through kappa
+    bound_rich = int(np.ceil(np.log(tol / kappa) / np.log(q_rich))) + 1
+    bound_sqrt = int(np.ceil(np.log(tol / (2 * kappa)) / np.log(q_sqrt))) + 1
+    counts = {}
+    for s in ("richardson", "cg", "chebyshev", "eyre_milton"):
+        r = orc.solve(N, orc.GANI, A, E, s, 1.0, rho, tol)
+        assert r.status == orc.OK
+        counts[s] = r.iters
+    assert counts["richardson"] <= bound_rich
+    for s in ("cg", "chebyshev", "eyre_milton"):
+        assert counts[s] <= bound_sqrt, (s, counts[s], bound_sqrt)
+    assert counts["cg"] < counts["richardson"]
+
+
+def test_ga_upper_bound_monotone_cg_richardson():
+    """Table 1: for Ga the bound U_E(x_m) decreases monotonically along CG and Richardson."""
+    N = (15, 15)
+    A = _square_problem(N, 100.0)
+    AM = orc.ga_assemble(N, A)
+    E = np.array([1.0, 0.0])
+    for s in ("cg", "richardson"):
+        r = orc.solve(N, orc.GA, AM, E, s, 1.0, 100.0, 1e-8, energy=True)
+        U = r.energy_hist
+        voigt = (1 - 0.36) + 0.36 * 100
+        assert abs(U[0] - voigt) < 1e-12  # x_0 = 0 gives the Voigt estimate
+        assert np.all(np.diff(U) <= 1e-12 * U[0]), s
+
+
+def test_zero_rhs_returns_immediately():
+    """b = 0 (load along laminate layers): CG/Chebyshev return m = 0 with e = 0."""
+    N = (7, 5)
+    A = I.phase_to_full(I.laminate(N, 0, [0, 1, 0, 1, 1, 0, 0]), I.iso_tables(2, [1.0, 3.0]))
+    for s in ("cg", "chebyshev"):
+        r = orc.solve(N, orc.GANI, A, np.array([0.0, 1.0]), s, 1.0, 3.0, 1e-8)
+        assert r.iters == 0 and np.abs(r.e).max() == 0.0
