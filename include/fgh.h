@@ -1,0 +1,177 @@
+/*
+ * fgh.h -- C-ABI of libfgh: Fourier-Galerkin FFT homogenization on AMD MI355X (gfx950).
+ *
+ * Method: Mishra, Vondrejc, Zeman, "A comparative study on low-memory iterative solvers for
+ * FFT-based homogenization of periodic media" (arXiv 1508.02045).
+ *
+ * Problem (Sec. 2, eq:homog_form): given a periodic field of symmetric positive-definite
+ * d x d coefficients A(x) on the unit cell, with c_A |v|^2 <= v.A(x)v <= C_A |v|^2 (eq:A), and a
+ * macroscopic gradient E, find the curl-free zero-mean fluctuation e minimising the energy
+ * (A(E+e), E+e); the minimum is (A_H E, E).  Discretised by trigonometric polynomials of odd
+ * order N (Sec. 2.1), with the trapezoidal rule on the N grid (GaNi, eq:GaNi) or with exact
+ * integration on the double grid 2N-1 (Ga, eq:Ga, eq:Ga_eval), it becomes the linear system
+ * C x = b with C = G A, b = -G A E (eq:linsys), solved by Richardson, conjugate gradients,
+ * Chebyshev or Eyre-Milton iterations (Sec. 3, Algorithms 1-4).
+ *
+ * Conventions shared by every entry point
+ *  - d is 2 or 3.  N[a] >= 3 and odd for every axis a (Sec. 2.1: N_alpha odd).
+ *  - The integration grid is N (GaNi) or M = 2N-1 (Ga).  Its points are C-ordered, the last
+ *    axis contiguous; array index i on an axis of n points stands for the grid point x = m/n
+ *    with m = i if 2i < n else i - n (Sec. 2.1: grid points x_N^m = m/N), so the origin is
+ *    index 0.
+ *  - A vector field is double[d][grid] (structure of arrays).
+ *  - Inner products and norms are (a,b)_2 = (1/|grid|) sum_points a.b (Notation paragraph);
+ *    the norm of a constant field E is the Euclidean |E|.
+ *  - Device pointers are HIP device memory on the current device.  The library allocates
+ *    nothing: the caller provides one device workspace per plan (size from
+ *    fgh_plan_workspace) and keeps it, A and the field buffers alive until
+ *    fgh_plan_destroy.  All work is enqueued on the plan's stream.
+ *  - Errors are returned as fgh_status codes; nothing aborts and no exception crosses the ABI.
+ *  - A plan is not thread-safe; distinct plans may be used from distinct threads.
+ */
+#ifndef FGH_H
+#define FGH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fgh_plan_s* fgh_plan;
+
+typedef enum {
+    FGH_OK = 0,
+    FGH_E_INVALID = 1,        /* bad argument: d, even or < 3 N, tolerance outside (0,1), NULL */
+    FGH_E_NOT_SPD = 2,        /* some A(x) has lambda_min <= 0, or c_A > C_A given */
+    FGH_E_UNSUPPORTED = 3,    /* Eyre-Milton with exact integration (Sec. 3.4, Table 1) */
+    FGH_E_WORKSPACE = 4,      /* workspace NULL or smaller than fgh_plan_workspace reports */
+    FGH_E_NO_CONVERGENCE = 5, /* iteration cap reached; outputs hold the last iterate */
+    FGH_E_DIVERGED = 6,       /* non-finite values or a step norm above 1e12 |E| */
+    FGH_E_DEVICE = 7          /* a HIP runtime call failed */
+} fgh_status;
+
+typedef enum {
+    FGH_GANI = 0, /* Galerkin with numerical (trapezoidal) integration on the N grid, eq:GaNi */
+    FGH_GA = 1    /* Galerkin with exact integration on the 2N-1 double grid, eq:Ga_eval     */
+} fgh_rule;
+
+typedef enum {
+    FGH_RICHARDSON = 0,  /* Algorithm 1, omega = 2/(c_A + C_A)            */
+    FGH_CG = 1,          /* Algorithm 2                                    */
+    FGH_CHEBYSHEV = 2,   /* Algorithm 3 on the interval [c_A, C_A]         */
+    FGH_EYRE_MILTON = 3  /* Algorithm 4, omega = sqrt(c_A C_A); GaNi only  */
+} fgh_solver;
+
+typedef enum {
+    FGH_FP64 = 0,        /* every step in double precision                                   */
+    FGH_FP32_REFINED = 1 /* FFTs, projection and A(x) multiply in single precision inside a
+                            double-precision defect-correction loop; residuals, reductions
+                            and A_H in double precision                                      */
+} fgh_precision;
+
+typedef enum {
+    FGH_A_SYM = 0,   /* per point packed symmetric d x d: double[ncoef][N grid], ncoef = 3 (2D:
+                        a00 a01 a11) or 6 (3D: a00 a01 a02 a11 a12 a22)                        */
+    FGH_A_ISO = 1,   /* per point isotropic scalar a: A(x) = a(x) I, double[N grid]          */
+    FGH_A_PHASE = 2  /* uint8 phase index per point on the N grid plus a host table of
+                        n_phases packed symmetric matrices (double[n_phases][ncoef])         */
+} fgh_akind;
+
+typedef struct {
+    int32_t iters;             /* loop bodies executed, each with exactly one operator apply
+                                  (FP32_REFINED: inner FP32 bodies summed over outer steps)   */
+    int32_t outer_iters;       /* FP32_REFINED: defect-correction steps; FP64: 0              */
+    int32_t fp64_applies;      /* double-precision operator applications performed            */
+    int32_t status;            /* fgh_status of this load                                    */
+    double rel_res_recursive;  /* the stopping-test quantity at exit (see fgh_solve)         */
+    double rel_res_true;       /* ||b - C x||_2 / ||b||_2 recomputed at exit (0 if b = 0)      */
+    double c_A, C_A;           /* spectral bounds used                                       */
+    double seconds;            /* wall time of this load's solve                             */
+} fgh_stats;
+
+/* Size in bytes of the device workspace a plan with these parameters needs (and its required
+ * alignment is 256 bytes).  N, rule, precision and the coefficient kind determine it; solver
+ * state for every solver is included.  Returns FGH_E_INVALID for bad d or N. */
+fgh_status fgh_plan_workspace(int d, const int32_t* N, fgh_rule rule, fgh_precision precision,
+                              fgh_akind a_kind, size_t* bytes);
+
+/* Create a plan (Sec. 2.2-2.3): validates the input, derives c_A and C_A (eq:A) from A unless
+ * both are given (> 0), builds the operator's coefficients on the device -- A itself for GaNi
+ * (eq:GaNi), the double-grid coefficients A_{2N-1} of the pixel-wise constant field for Ga
+ * (eq:Ga_exact_integration, assembled from the exact pixel Fourier coefficients) -- and lays
+ * out every buffer inside `workspace`.
+ *   A        device pointer, layout per a_kind on the N grid (NULL for FGH_A_PHASE).
+ *   phase    device uint8 [N grid] for FGH_A_PHASE, else NULL; values < n_phases.
+ *   phase_table  host double[n_phases][ncoef] for FGH_A_PHASE, else NULL; 1 <= n_phases <= 16.
+ *   c_A, C_A spectral bounds to use; if either is <= 0 both are derived from A.
+ *   stream   hipStream_t to enqueue on (NULL = default stream).
+ * Blocks until set-up is complete.  Errors: FGH_E_INVALID, FGH_E_NOT_SPD, FGH_E_WORKSPACE,
+ * FGH_E_DEVICE.  On error *out is NULL. */
+fgh_status fgh_plan_create(fgh_plan* out, int d, const int32_t* N, fgh_rule rule,
+                           fgh_precision precision, fgh_akind a_kind, const void* A,
+                           const uint8_t* phase, const double* phase_table, int n_phases,
+                           double c_A, double C_A, void* workspace, size_t workspace_bytes,
+                           void* stream);
+
+/* Release the plan's host state (the workspace stays the caller's). NULL is ignored. */
+void fgh_plan_destroy(fgh_plan plan);
+
+/* Number of points of the plan's integration grid (|N| for GaNi, |2N-1| for Ga). */
+int64_t fgh_plan_grid_points(fgh_plan plan);
+
+/* Spectral bounds the plan uses (eq:A). */
+fgh_status fgh_plan_bounds(fgh_plan plan, double* c_A, double* C_A);
+
+/* y = C x = G A x in double precision (eq:linsys; G as in eq:discrete_proj, band-limited to
+ * Z_N on the double grid for Ga).  x and y: device double[d][grid] of the integration grid;
+ * they must not overlap.  Asynchronous on the plan's stream. */
+fgh_status fgh_apply(fgh_plan plan, const double* x, double* y);
+
+/* Same operator in single precision: x, y device float[d][grid] (the FP32 path of
+ * FGH_FP32_REFINED plans; FGH_E_UNSUPPORTED for FGH_FP64 plans). */
+fgh_status fgh_apply_f32(fgh_plan plan, const float* x, float* y);
+
+/* Write the double-grid coefficients A_{2N-1} of a Ga plan (eq:Ga_exact_integration) to device
+ * double[ncoef_op][M grid], where ncoef_op is 1 for FGH_A_ISO / FGH_A_PHASE (A_{2N-1} is a
+ * scalar field times I) and 3 or 6 packed symmetric entries for FGH_A_SYM.  FGH_E_INVALID for
+ * GaNi plans.  Blocks. */
+fgh_status fgh_ga_coefficients(fgh_plan plan, double* out);
+
+/* Solve C e = b for nrhs loads E (host double[nrhs][d]), each independently (Algorithms 1-4):
+ *   Richardson: x0 = 0, stop when ||x_m - x_{m-1}||_2 <= tol |E|.
+ *   CG, Chebyshev: x0 = 0, stop when ||r_m||_2 <= tol ||b||_2 (recursive residual); if
+ *     ||b||_2 <= 1e-12 ||A E||_2 the load is taken as b = 0 and returns e = 0, iters = 0.
+ *   Eyre-Milton: x0 = E, x_m = (A + wI)^{-1}[F^{-1}(I - 2G^)F (A - wI) x_{m-1} + 2wE], stop
+ *     when ||x_m - x_{m-1}||_2 <= tol |E|; the returned fluctuation is x_m - E.
+ * e: device double[nrhs][d][grid] output.  tol in (0,1).  max_iter >= 1 caps loop bodies
+ * (inner bodies per outer step for FGH_FP32_REFINED).  stats: host fgh_stats[nrhs] or NULL.
+ * FGH_FP32_REFINED: outer FP64 residual r = b - C x, inner FP32 solve of C delta = r to the
+ * relative tolerance max(tol_abs/||r||, 1e-4) by the same solver, then x += G delta in FP64;
+ * stops on the true FP64 residual ||b - C x|| <= tol ||b|| (Richardson, CG, Chebyshev) or on
+ * the outer step norm (Eyre-Milton).  Blocks until done.  Returns the worst load status. */
+fgh_status fgh_solve(fgh_plan plan, fgh_solver solver, const double* E, int nrhs, double tol,
+                     int max_iter, double* e, fgh_stats* stats);
+
+/* Same as fgh_solve with the iteration count fixed: exactly `iters` loop bodies per load, the
+ * stopping test skipped (iterate-matched comparisons).  FGH_FP64 plans only. */
+fgh_status fgh_solve_fixed(fgh_plan plan, fgh_solver solver, const double* E, int nrhs,
+                           int iters, double* e, fgh_stats* stats);
+
+/* Effective quantities from solved fluctuations (eq:ev_bounds), accumulated in double:
+ *   bilinear  host double[nrhs][nrhs] (may be NULL): B[i][j] = (A(E_j + e_j), E_i + e_i)_2;
+ *             with the d unit loads this is A_H (eq:ev_bounds_Ga / eq:GaNi).
+ *   flux      host double[nrhs][d] (may be NULL): <A(E_j + e_j)>, the flux column of load j.
+ * E: host double[nrhs][d]; e: device double[nrhs][d][grid] as written by fgh_solve.
+ * Sums run over the integration grid (the double grid for Ga).  Blocks. */
+fgh_status fgh_effective(fgh_plan plan, const double* E, int nrhs, const double* e,
+                         double* bilinear, double* flux);
+
+const char* fgh_status_string(fgh_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FGH_H */

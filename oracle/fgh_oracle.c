@@ -446,7 +446,7 @@ int orc_flux(int d, const int* N, int rule, const double* A, const double* E, co
     grid_t g;
     if (op_grid(d, N, rule, &g)) return ORC_E_INVALID;
     const long S = g.size;
-    double* u = (double*)malloc(sizeof(double) * d * S);
+    double* u = (double*)calloc((size_t)d * S, sizeof(double));
     double* z = (double*)malloc(sizeof(double) * d * S);
     for (int a = 0; a < d; a++)
         for (long p = 0; p < S; p++) u[a * S + p] = E[a] + (e ? e[a * S + p] : 0.0);

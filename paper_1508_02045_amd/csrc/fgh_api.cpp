@@ -1,0 +1,1123 @@
+// fgh_api.cpp -- host side of libfgh: plans, workspace layout, coefficient set-up and the
+// solver drivers of Algorithms 1-4 (Sec. 3) on top of the gfx950 passes.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/fgh.h"
+#include "fgh_internal.hpp"
+#include "fgh_launch.hpp"
+
+using namespace fgh;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr size_t kLdsBudget = 80 * 1024;
+constexpr double kZeroRhs = 1e-12;      // b is taken as zero when ||b|| <= kZeroRhs ||A E||
+constexpr double kInnerTolMin = 1e-4;   // FP32 inner solves stop at this relative residual
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int ncoef_for(int d) { return d == 2 ? 3 : 6; }
+
+// Radix sequence of an odd length: 7s, 5s, 3s, then any other prime factor.
+bool factorize(int L, Axis* ax)
+{
+    int n = L, k = 0;
+    const int small[3] = {7, 5, 3};
+    for (int p : small)
+        while (n % p == 0) {
+            if (k >= kMaxRadices) return false;
+            ax->rad[k++] = p;
+            n /= p;
+        }
+    for (int p = 11; n > 1; p += 2)
+        while (n % p == 0) {
+            if (k >= kMaxRadices) return false;
+            ax->rad[k++] = p;
+            n /= p;
+        }
+    ax->L = L;
+    ax->nst = k;
+    return true;
+}
+
+struct Config {
+    int rpb, npen, P_axis, P_mid;
+    size_t lds_first, lds_axis, lds_mid;
+};
+
+Config choose_config(const Geo& g, size_t cs /* bytes per complex */, size_t rs /* bytes per real */)
+{
+    Config c{};
+    const int d = g.d;
+    const int Ll = g.L[d - 1];
+    // first/last: as many rows per block as fit, at most 32
+    c.rpb = 1;
+    for (int rpb = 32; rpb >= 1; rpb--) {
+        const int npen = (rpb * d + 1) / 2;
+        const size_t lds = (size_t)(Ll + 2 * npen * Ll) * cs + kMaxPhases * 6 * rs;
+        if (lds <= kLdsBudget) {
+            c.rpb = rpb;
+            break;
+        }
+    }
+    c.npen = (c.rpb * d + 1) / 2;
+    c.lds_first = (size_t)(Ll + 2 * c.npen * Ll) * cs + kMaxPhases * 6 * rs;
+    const int Ps[5] = {16, 8, 4, 2, 1};
+    c.P_axis = 1;
+    if (d == 3)
+        for (int P : Ps)
+            if ((size_t)(g.L[1] + 2 * P * g.L[1]) * cs <= kLdsBudget) {
+                c.P_axis = P;
+                break;
+            }
+    c.lds_axis = (size_t)(g.L[1] + 2 * c.P_axis * g.L[1]) * cs;
+    c.P_mid = 1;
+    for (int P : Ps)
+        if ((size_t)(g.L[0] + (d + 1) * P * g.L[0]) * cs <= kLdsBudget) {
+            c.P_mid = P;
+            break;
+        }
+    c.lds_mid = (size_t)(g.L[0] + (d + 1) * c.P_mid * g.L[0]) * cs;
+    return c;
+}
+
+bool make_geo(int d, const int32_t* N, int rule, Geo* g)
+{
+    if (d != 2 && d != 3) return false;
+    if (!N) return false;
+    g->d = d;
+    g->npts = 1;
+    for (int a = 0; a < 3; a++) g->L[a] = g->B[a] = 1;
+    for (int a = 0; a < d; a++) {
+        if (N[a] < 3 || N[a] % 2 == 0 || N[a] > 8191) return false;
+        g->B[a] = N[a];
+        g->L[a] = rule == FGH_GA ? 2 * N[a] - 1 : N[a];
+        g->npts *= g->L[a];
+    }
+    g->Hb = (g->B[d - 1] + 1) / 2;
+    g->rows = g->npts / g->L[d - 1];
+    g->s1 = g->rows * g->Hb;
+    g->s2 = d == 3 ? (long long)g->L[0] * g->B[1] * g->Hb : g->s1;
+    g->cols_mid = d == 3 ? g->B[1] * g->Hb : g->Hb;
+    return true;
+}
+
+struct Layout {
+    size_t tw64[3], tw32[3], SA, SB, vec64, vec32, partials, scalars, mask, coef64, coef32, sinc[3], twN[3], twM[3];
+    size_t total;
+    long long npart;
+};
+
+Layout make_layout(const Geo& g, const int32_t* N, int rule, int prec, int akind)
+{
+    Layout l{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    const int d = g.d;
+    for (int a = 0; a < d; a++) l.tw64[a] = take((size_t)g.L[a] * 16);
+    for (int a = 0; a < d; a++) l.tw32[a] = take((size_t)g.L[a] * 8);
+    const long long sp = g.s1 > g.s2 ? g.s1 : g.s2;
+    l.SA = take((size_t)d * sp * 16);
+    l.SB = take((size_t)d * sp * 16);
+    const long long nv = (long long)d * g.npts;
+    // three double vectors (CG r, p, q; Chebyshev r, p; refinement r, delta, G delta), which
+    // also host the Ga-assembly scratch at set-up time
+    size_t v64 = (size_t)3 * nv * 8;
+    long long nM = 1, nN = 1;
+    for (int a = 0; a < d; a++) {
+        nN *= N[a];
+        nM *= 2 * N[a] - 1;
+    }
+    if (rule == FGH_GA && v64 < (size_t)2 * nM * 16) v64 = (size_t)2 * nM * 16;
+    l.vec64 = take(v64);
+    l.vec32 = take(prec == FGH_FP32_REFINED ? (size_t)4 * nv * 4 : 0);
+    const Config c64 = choose_config(g, 16, 8);
+    const Config c32 = choose_config(g, 8, 4);
+    long long nb = (g.rows + c64.rpb - 1) / c64.rpb;
+    const long long nb32 = (g.rows + c32.rpb - 1) / c32.rpb;
+    if (nb32 > nb) nb = nb32;
+    long long np = nb;
+    if (np < 1024 * 2 + 2) np = 1024 * 2 + 2;
+    if (np < 512 * 18) np = 512 * 18;
+    l.npart = np + 64;
+    l.partials = take((size_t)l.npart * 8);
+    l.scalars = take(sizeof(Scalars));
+    l.mask = take(16);
+    const int ncoef_op = (akind == FGH_A_SYM) ? ncoef_for(d) : 1;
+    l.coef64 = take(rule == FGH_GA ? (size_t)ncoef_op * g.npts * 8 : 0);
+    const bool need32 = prec == FGH_FP32_REFINED && (rule == FGH_GA || akind != FGH_A_PHASE);
+    l.coef32 = take(need32 ? (size_t)ncoef_op * g.npts * 4 : 0);
+    for (int a = 0; a < d; a++) {
+        l.sinc[a] = take(rule == FGH_GA ? (size_t)(2 * N[a] - 1) * 8 : 0);
+        l.twN[a] = take(rule == FGH_GA ? (size_t)N[a] * 16 : 0);
+        l.twM[a] = take(rule == FGH_GA ? (size_t)(2 * N[a] - 1) * 16 : 0);
+    }
+    l.total = off;
+    return l;
+}
+
+// Eigenvalues of a packed symmetric 2x2 / 3x3 block on the host (cyclic Jacobi).
+void host_sym_eigs(int d, const double* p, double* lo, double* hi)
+{
+    double a[3][3];
+    if (d == 2) {
+        a[0][0] = p[0]; a[0][1] = a[1][0] = p[1]; a[1][1] = p[2];
+    } else {
+        a[0][0] = p[0]; a[0][1] = a[1][0] = p[1]; a[0][2] = a[2][0] = p[2];
+        a[1][1] = p[3]; a[1][2] = a[2][1] = p[4]; a[2][2] = p[5];
+    }
+    for (int sweep = 0; sweep < 60; sweep++) {
+        double off = 0.0;
+        for (int i = 0; i < d; i++)
+            for (int j = i + 1; j < d; j++) off += a[i][j] * a[i][j];
+        if (off < 1e-300) break;
+        for (int pp = 0; pp < d; pp++)
+            for (int q = pp + 1; q < d; q++) {
+                if (a[pp][q] == 0.0) continue;
+                const double th = (a[q][q] - a[pp][pp]) / (2.0 * a[pp][q]);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < d; k++) {
+                    const double akp = a[k][pp], akq = a[k][q];
+                    a[k][pp] = c * akp - s * akq;
+                    a[k][q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < d; k++) {
+                    const double apk = a[pp][k], aqk = a[q][k];
+                    a[pp][k] = c * apk - s * aqk;
+                    a[q][k] = s * apk + c * aqk;
+                }
+            }
+    }
+    *lo = 1e300;
+    *hi = -1e300;
+    for (int i = 0; i < d; i++) {
+        *lo = std::fmin(*lo, a[i][i]);
+        *hi = std::fmax(*hi, a[i][i]);
+    }
+}
+
+// Packed inverse of (A + w I) for a packed symmetric block.
+void host_shift_inverse(int d, const double* p, double w, double* inv)
+{
+    if (d == 2) {
+        const double m00 = p[0] + w, m01 = p[1], m11 = p[2] + w;
+        const double det = m00 * m11 - m01 * m01;
+        inv[0] = m11 / det;
+        inv[1] = -m01 / det;
+        inv[2] = m00 / det;
+    } else {
+        const double m00 = p[0] + w, m01 = p[1], m02 = p[2], m11 = p[3] + w, m12 = p[4], m22 = p[5] + w;
+        const double c00 = m11 * m22 - m12 * m12, c01 = m02 * m12 - m01 * m22, c02 = m01 * m12 - m02 * m11;
+        const double c11 = m00 * m22 - m02 * m02, c12 = m01 * m02 - m00 * m12, c22 = m00 * m11 - m01 * m01;
+        const double det = m00 * c00 + m01 * c01 + m02 * c02;
+        inv[0] = c00 / det; inv[1] = c01 / det; inv[2] = c02 / det;
+        inv[3] = c11 / det; inv[4] = c12 / det; inv[5] = c22 / det;
+    }
+}
+
+}  // namespace
+
+struct fgh_plan_s {
+    int d;
+    int32_t N[3];
+    int rule, prec, akind;
+    Geo g;
+    Layout lay;
+    char* ws;
+    hipStream_t stream;
+    double cA, CA;
+    int nphase;
+    double tab[kMaxPhases][6];
+    int ncoef_op;             // 1 (scalar A_{2N-1} / iso) or ncoef
+    OpPlan op64, op32;
+    double* r64;
+    double* p64;
+    double* q64;
+    float* x32;
+    float* r32;
+    float* p32;
+    float* q32;
+    double* host_buf;         // pinned host scalars
+};
+
+namespace {
+
+#define HIPOK(x)                                 \
+    do {                                         \
+        if ((x) != hipSuccess) return FGH_E_DEVICE; \
+    } while (0)
+
+fgh_status upload_twiddles(fgh_plan p)
+{
+    std::vector<double> t64;
+    std::vector<float> t32;
+    for (int a = 0; a < p->d; a++) {
+        const int L = p->g.L[a];
+        t64.resize(2 * (size_t)L);
+        t32.resize(2 * (size_t)L);
+        for (int m = 0; m < L; m++) {
+            const long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)L;
+            const double c = (double)cosl(ang), s = -(double)sinl(ang);
+            t64[2 * m] = c;
+            t64[2 * m + 1] = s;
+            t32[2 * m] = (float)cosl(ang);
+            t32[2 * m + 1] = (float)(-sinl(ang));
+        }
+        HIPOK(hipMemcpyAsync(p->ws + p->lay.tw64[a], t64.data(), (size_t)L * 16, hipMemcpyHostToDevice, p->stream));
+        HIPOK(hipMemcpyAsync(p->ws + p->lay.tw32[a], t32.data(), (size_t)L * 8, hipMemcpyHostToDevice, p->stream));
+        HIPOK(hipStreamSynchronize(p->stream));
+    }
+    return FGH_OK;
+}
+
+void fill_opplan(fgh_plan p, OpPlan* op, bool f32)
+{
+    const Config c = choose_config(p->g, f32 ? 8 : 16, f32 ? 4 : 8);
+    op->g = p->g;
+    for (int a = 0; a < 3; a++) {
+        if (a < p->d) factorize(p->g.L[a], &op->ax[a]);
+        op->ax[a].tw = 0;
+        op->tw[a] = a < p->d ? p->ws + (f32 ? p->lay.tw32[a] : p->lay.tw64[a]) : nullptr;
+    }
+    op->SA = p->ws + p->lay.SA;
+    op->SB = p->ws + p->lay.SB;
+    op->rpb = c.rpb;
+    op->npen = c.npen;
+    op->P_axis = c.P_axis;
+    op->P_mid = c.P_mid;
+    op->lds_first = c.lds_first;
+    op->lds_axis = c.lds_axis;
+    op->lds_mid = c.lds_mid;
+    op->partials = reinterpret_cast<double*>(p->ws + p->lay.partials);
+    op->sc = reinterpret_cast<Scalars*>(p->ws + p->lay.scalars);
+    op->stream = p->stream;
+}
+
+// Read one device double (synchronises the stream).
+fgh_status read_scalar(fgh_plan p, const double* dev, double* out)
+{
+    HIPOK(hipMemcpyAsync(p->host_buf, dev, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIPOK(hipStreamSynchronize(p->stream));
+    *out = p->host_buf[0];
+    return FGH_OK;
+}
+
+fgh_status reduce_read(fgh_plan p, const OpPlan& op, int n, int redop, double* out)
+{
+    HIPOK(run_reduce_async(op, n, redop));
+    return read_scalar(p, &op.sc->total, out);
+}
+
+template <typename T>
+const OpPlan& opp(fgh_plan p);
+template <>
+const OpPlan& opp<double>(fgh_plan p) { return p->op64; }
+template <>
+const OpPlan& opp<float>(fgh_plan p) { return p->op32; }
+
+// ||b||^2 (raw sum) of b = -G A E into r; also ||A E||^2.
+template <typename T>
+fgh_status rhs(fgh_plan p, const double* E, T* r, double* bb, double* ae2)
+{
+    const OpPlan& op = opp<T>(p);
+    ApplyArgs a;
+    a.op = OP_E;
+    a.epi = EPI_STORE;
+    a.sgn = -1.0;
+    for (int c = 0; c < p->d; c++) a.E[c] = E[c];
+    a.y = r;
+    int nb = 0;
+    HIPOK(run_apply<T>(op, a, &nb));
+    fgh_status st = reduce_read(p, op, nb, RED_SET_RR, bb);
+    if (st) return st;
+    if (ae2) {
+        HIPOK(run_norm_AE(p->op64, E, &nb));
+        double v;
+        st = reduce_read(p, p->op64, nb, RED_TOTAL, &v);
+        if (st) return st;
+        *ae2 = v;
+    }
+    return FGH_OK;
+}
+
+struct SolveOut {
+    int iters = 0;
+    int status = FGH_OK;
+    double res = 0.0;   // stopping-test quantity at exit
+};
+
+// Conjugate gradients (Algorithm 2) for C x = b with b already in r, x = 0 on entry.
+// The right-hand side norm^2 is bb (raw sum).  Stops when ||r|| <= tol_rel sqrt(bb).
+template <typename T>
+fgh_status cg_core(fgh_plan p, T* x, T* r, T* pv, T* q, double bb, double tol_rel, int max_iter, int fixed,
+                   SolveOut* out)
+{
+    const OpPlan& op = opp<T>(p);
+    const long long n = (long long)p->d * p->g.npts;
+    HIPOK(run_copy<T>(p->stream, n, pv, r));
+    const double S = (double)p->g.npts;
+    // (r, r) of the vector actually iterated on, also the device scalar the first alpha uses
+    {
+        int nb = 0;
+        HIPOK(run_dot<T>(op, n, r, r, &nb));
+        fgh_status st0 = reduce_read(p, op, nb, RED_SET_RR, &bb);
+        if (st0) return st0;
+    }
+    const double normb = std::sqrt(bb / S);
+    out->iters = 0;
+    out->res = 1.0;
+    double rr = bb;
+    if (!(fixed > 0) && std::sqrt(rr / S) <= tol_rel * normb) {
+        out->res = std::sqrt(rr / S) / normb;
+        return FGH_OK;
+    }
+    const int limit = fixed > 0 ? fixed : max_iter;
+    int m = 0;
+    while (m < limit) {
+        ApplyArgs a;
+        a.op = m == 0 ? OP_AX : OP_AP_CG;
+        a.x = pv;
+        a.p_cg = pv;
+        a.r_cg = r;
+        a.epi = EPI_CG;
+        a.eq = q;
+        a.ep = pv;
+        int nb = 0;
+        HIPOK(run_apply<T>(op, a, &nb));
+        HIPOK(run_reduce_async(op, nb, RED_CG_ALPHA));
+        HIPOK(run_cg_update<T>(op, n, x, r, pv, q));
+        double rr_new;
+        fgh_status st = reduce_read(p, op, vec_blocks(), RED_CG_BETA, &rr_new);
+        if (st) return st;
+        m++;
+        out->res = std::sqrt(rr_new / S) / normb;
+        if (!std::isfinite(rr_new)) {
+            out->iters = m;
+            out->status = FGH_E_DIVERGED;
+            return FGH_OK;
+        }
+        if (!(fixed > 0) && std::sqrt(rr_new / S) <= tol_rel * normb) break;
+        rr = rr_new;
+    }
+    out->iters = m;
+    if (!(fixed > 0) && !(out->res <= tol_rel)) out->status = FGH_E_NO_CONVERGENCE;
+    return FGH_OK;
+}
+
+// Chebyshev semi-iteration (Algorithm 3), b in r, x = 0.
+template <typename T>
+fgh_status cheb_core(fgh_plan p, T* x, T* r, T* pv, double bb, double tol_rel, int max_iter, int fixed,
+                     SolveOut* out)
+{
+    const OpPlan& op = opp<T>(p);
+    const long long n = (long long)p->d * p->g.npts;
+    HIPOK(run_copy<T>(p->stream, n, pv, r));
+    const double S = (double)p->g.npts;
+    {
+        int nb = 0;
+        HIPOK(run_dot<T>(op, n, r, r, &nb));
+        fgh_status st0 = reduce_read(p, op, nb, RED_SET_RR, &bb);
+        if (st0) return st0;
+    }
+    const double normb = std::sqrt(bb / S);
+    out->iters = 0;
+    out->res = 1.0;
+    if (!(fixed > 0) && std::sqrt(bb / S) <= tol_rel * normb) return FGH_OK;
+    const double c = 0.5 * (p->CA - p->cA), delta = 0.5 * (p->cA + p->CA);
+    double alpha = 1.0 / delta;
+    double beta = -0.5 * (c / delta) * (c / delta);
+    const int limit = fixed > 0 ? fixed : max_iter;
+    int m = 0;
+    while (m < limit) {
+        if (m + 1 > 1) {
+            alpha = 1.0 / (delta + beta / alpha);
+            beta = -(c * alpha / 2.0) * (c * alpha / 2.0);
+        }
+        ApplyArgs a;
+        a.op = OP_AX;
+        a.x = pv;
+        a.epi = EPI_CHEB;
+        a.ex = x;
+        a.er = r;
+        a.ep = pv;
+        a.alpha = alpha;
+        a.beta = beta;
+        int nb = 0;
+        HIPOK(run_apply<T>(op, a, &nb));
+        double rr;
+        fgh_status st = reduce_read(p, op, nb, RED_TOTAL, &rr);
+        if (st) return st;
+        m++;
+        out->res = std::sqrt(rr / S) / normb;
+        if (!std::isfinite(rr)) {
+            out->iters = m;
+            out->status = FGH_E_DIVERGED;
+            return FGH_OK;
+        }
+        if (!(fixed > 0) && std::sqrt(rr / S) <= tol_rel * normb) break;
+    }
+    out->iters = m;
+    if (!(fixed > 0) && !(out->res <= tol_rel)) out->status = FGH_E_NO_CONVERGENCE;
+    return FGH_OK;
+}
+
+// Richardson (Algorithm 1) on C x = b with b = -G A E0 implicit: step = -w G A (E0 + x).
+// With E0 = 0 and an explicit right-hand side this is used as an inner solver only through
+// the Moulinec-Suquet form, so the driver passes the load E0; stops when
+// ||x_m - x_{m-1}|| <= thr.
+template <typename T>
+fgh_status rich_core(fgh_plan p, T* x, const double* E0, double thr, int max_iter, int fixed, double scale,
+                     SolveOut* out)
+{
+    const OpPlan& op = opp<T>(p);
+    const double S = (double)p->g.npts;
+    const double omega = 2.0 / (p->cA + p->CA);
+    out->iters = 0;
+    out->res = 1.0;
+    const int limit = fixed > 0 ? fixed : max_iter;
+    int m = 0;
+    while (m < limit) {
+        ApplyArgs a;
+        a.op = OP_AX;
+        a.x = x;
+        for (int c = 0; c < p->d; c++) a.E[c] = E0[c];
+        a.epi = EPI_RICH;
+        a.ex = x;
+        a.omega = omega;
+        int nb = 0;
+        HIPOK(run_apply<T>(op, a, &nb));
+        double ss;
+        fgh_status st = reduce_read(p, op, nb, RED_TOTAL, &ss);
+        if (st) return st;
+        m++;
+        const double step = std::sqrt(ss / S);
+        out->res = scale > 0 ? step / scale : step;
+        if (!std::isfinite(step)) {
+            out->iters = m;
+            out->status = FGH_E_DIVERGED;
+            return FGH_OK;
+        }
+        if (!(fixed > 0) && step <= thr) break;
+    }
+    out->iters = m;
+    if (!(fixed > 0) && !(out->res * (scale > 0 ? scale : 1.0) <= thr)) out->status = FGH_E_NO_CONVERGENCE;
+    return FGH_OK;
+}
+
+// Eyre-Milton (Algorithm 4).  Plain form (src == NULL): x holds E + e; correction form
+// (src != NULL): x holds delta, the source field is the double-precision defect.
+template <typename T>
+fgh_status em_core(fgh_plan p, T* x, const double* E, const T* src, double thr, int max_iter, int fixed,
+                   double scale, SolveOut* out)
+{
+    const OpPlan& op = opp<T>(p);
+    const double S = (double)p->g.npts;
+    const double omega = std::sqrt(p->cA * p->CA);
+    out->iters = 0;
+    out->res = 1.0;
+    const int limit = fixed > 0 ? fixed : max_iter;
+    int m = 0;
+    while (m < limit) {
+        ApplyArgs a;
+        a.op = OP_EM;
+        a.x = x;
+        a.omega = omega;
+        a.mult = MULT_EM;
+        a.epi = EPI_EM;
+        a.ex = x;
+        a.src = src;
+        for (int c = 0; c < p->d; c++) a.E[c] = E[c];
+        int nb = 0;
+        HIPOK(run_apply<T>(op, a, &nb));
+        double ss;
+        fgh_status st = reduce_read(p, op, nb, RED_TOTAL, &ss);
+        if (st) return st;
+        m++;
+        const double step = std::sqrt(ss / S);
+        out->res = scale > 0 ? step / scale : step;
+        if (!std::isfinite(step) || step > 1e12 * (scale > 0 ? scale : 1.0)) {
+            out->iters = m;
+            out->status = FGH_E_DIVERGED;
+            return FGH_OK;
+        }
+        if (!(fixed > 0) && step <= thr) break;
+    }
+    out->iters = m;
+    if (!(fixed > 0) && !(out->res * (scale > 0 ? scale : 1.0) <= thr)) out->status = FGH_E_NO_CONVERGENCE;
+    return FGH_OK;
+}
+
+// ||b - C e|| / ||b|| for the fluctuation e (double): apply C to (E + e) and compare with 0.
+fgh_status true_residual(fgh_plan p, const double* E, const double* e, double bb, double* out)
+{
+    ApplyArgs a;
+    a.op = OP_AX;
+    a.x = e;
+    for (int c = 0; c < p->d; c++) a.E[c] = E[c];
+    a.epi = EPI_STORE;
+    a.sgn = 1.0;
+    a.y = p->q64;
+    int nb = 0;
+    HIPOK(run_apply<double>(p->op64, a, &nb));
+    double v;
+    fgh_status st = reduce_read(p, p->op64, nb, RED_TOTAL, &v);
+    if (st) return st;
+    *out = bb > 0 ? std::sqrt(v / bb) : std::sqrt(v / (double)p->g.npts);
+    return FGH_OK;
+}
+
+fgh_status solve_one_fp64(fgh_plan p, int solver, const double* E, double tol, int max_iter, int fixed, double* e,
+                          fgh_stats* st)
+{
+    const long long n = (long long)p->d * p->g.npts;
+    const double S = (double)p->g.npts;
+    double normE = 0.0;
+    for (int c = 0; c < p->d; c++) normE += E[c] * E[c];
+    normE = std::sqrt(normE);
+    SolveOut so;
+    double bb = 0.0, ae2 = 0.0;
+    fgh_status s;
+    if (solver == FGH_CG || solver == FGH_CHEBYSHEV) {
+        if ((s = rhs<double>(p, E, p->r64, &bb, &ae2))) return s;
+        HIPOK(run_fill<double>(p->stream, n, e, 0.0));
+        const bool zero = !(std::sqrt(bb / S) > kZeroRhs * std::sqrt(ae2 / S));
+        if (zero) {
+            so.iters = 0;
+            so.res = 0.0;
+        } else if (solver == FGH_CG) {
+            if ((s = cg_core<double>(p, e, p->r64, p->p64, p->q64, bb, tol, max_iter, fixed, &so))) return s;
+        } else {
+            if ((s = cheb_core<double>(p, e, p->r64, p->p64, bb, tol, max_iter, fixed, &so))) return s;
+        }
+    } else if (solver == FGH_RICHARDSON) {
+        HIPOK(run_fill<double>(p->stream, n, e, 0.0));
+        if ((s = rich_core<double>(p, e, E, tol * normE, max_iter, fixed, normE, &so))) return s;
+    } else {
+        HIPOK(run_fill_field<double>(p->stream, p->d, p->g.npts, e, E));
+        if ((s = em_core<double>(p, e, E, nullptr, tol * normE, max_iter, fixed, normE, &so))) return s;
+        double negE[3] = {-E[0], -E[1], p->d == 3 ? -E[2] : 0.0};
+        // e <- x - E
+        HIPOK(run_fill_field<double>(p->stream, p->d, p->g.npts, p->q64, negE));
+        HIPOK(run_add_f64(p->stream, n, e, p->q64));
+    }
+    if (st) {
+        st->iters = so.iters;
+        st->outer_iters = 0;
+        st->fp64_applies = so.iters;
+        st->status = so.status;
+        st->rel_res_recursive = so.res;
+    }
+    return FGH_OK;
+}
+
+// Defect correction: FP64 outer loop, FP32 inner solves (the same algorithm as `solver`).
+//  CG / Chebyshev: r = b - C x in FP64, inner FP32 solve of C delta = r to the relative
+//    tolerance max(tol ||b|| / ||r||, kInnerTolMin), then x += G delta in FP64 (the projection
+//    removes the FP32 round-off that is not curl-free, so the iterate stays conforming);
+//    stop when ||b - C x|| <= tol ||b||.
+//  Eyre-Milton: the FP64 defect dbar = EM(x) - x; the correction delta obeys
+//    delta = (A + wI)^{-1} (I - 2G^)(A - wI) delta + dbar (same contraction as Algorithm 4),
+//    iterated in FP32 from delta = 0; x += delta; stop when ||dbar|| <= tol |E| (then x takes
+//    that last FP64 step, as Algorithm 4 would).
+fgh_status solve_one_refined(fgh_plan p, int solver, const double* E, double tol, int max_iter, double* e,
+                             fgh_stats* st)
+{
+    const long long n = (long long)p->d * p->g.npts;
+    const double S = (double)p->g.npts;
+    double normE = 0.0;
+    for (int c = 0; c < p->d; c++) normE += E[c] * E[c];
+    normE = std::sqrt(normE);
+    int inner_total = 0, outer = 0, applies64 = 0, status = FGH_OK;
+    double res = 0.0;
+    fgh_status s;
+    if (solver == FGH_EYRE_MILTON) {
+        const double omega = std::sqrt(p->cA * p->CA);
+        HIPOK(run_fill_field<double>(p->stream, p->d, p->g.npts, e, E));  // x = E
+        bool done = false;
+        for (outer = 0; outer < 200 && !done; outer++) {
+            // r64 = EM(x) in FP64; the epilogue sums |EM(x) - x|^2
+            HIPOK(run_copy<double>(p->stream, n, p->r64, e));
+            ApplyArgs a;
+            a.op = OP_EM;
+            a.x = p->r64;
+            a.omega = omega;
+            a.mult = MULT_EM;
+            a.epi = EPI_EM;
+            a.ex = p->r64;
+            for (int c = 0; c < p->d; c++) a.E[c] = E[c];
+            int nb = 0;
+            HIPOK(run_apply<double>(p->op64, a, &nb));
+            applies64++;
+            double dd;
+            if ((s = reduce_read(p, p->op64, nb, RED_TOTAL, &dd))) return s;
+            const double dnorm = std::sqrt(dd / S);
+            res = normE > 0 ? dnorm / normE : dnorm;
+            if (!std::isfinite(dnorm) || dnorm > 1e12 * (normE > 0 ? normE : 1.0)) {
+                status = FGH_E_DIVERGED;
+                break;
+            }
+            if (dnorm <= tol * normE) {
+                HIPOK(run_copy<double>(p->stream, n, e, p->r64));
+                done = true;
+                break;
+            }
+            // dbar = EM(x) - x  (q64), its FP32 copy is the inner source
+            HIPOK(run_axpby(p->stream, n, p->q64, 1.0, p->r64, 0.0));
+            HIPOK(run_axpby(p->stream, n, p->q64, -1.0, e, 1.0));
+            HIPOK(run_f64_to_f32(p->stream, n, p->r32, p->q64));
+            HIPOK(run_fill<float>(p->stream, n, p->x32, 0.0f));
+            double eta = tol * normE / dnorm;
+            if (eta < kInnerTolMin) eta = kInnerTolMin;
+            SolveOut so;
+            if ((s = em_core<float>(p, p->x32, E, p->r32, eta * dnorm, max_iter, 0, dnorm, &so))) return s;
+            inner_total += so.iters;
+            if (so.status == FGH_E_DIVERGED) {
+                status = FGH_E_DIVERGED;
+                break;
+            }
+            HIPOK(run_add_f32_to_f64(p->stream, n, e, p->x32));
+        }
+        if (status == FGH_OK && !done) status = FGH_E_NO_CONVERGENCE;
+        // fluctuation e = x - E
+        double negE[3] = {-E[0], -E[1], p->d == 3 ? -E[2] : 0.0};
+        HIPOK(run_fill_field<double>(p->stream, p->d, p->g.npts, p->q64, negE));
+        HIPOK(run_add_f64(p->stream, n, e, p->q64));
+    } else if (solver == FGH_CG || solver == FGH_CHEBYSHEV) {
+        HIPOK(run_fill<double>(p->stream, n, e, 0.0));
+        double bb = 0.0, ae2 = 0.0;
+        if ((s = rhs<double>(p, E, p->r64, &bb, &ae2))) return s;
+        applies64++;
+        const bool zero = !(std::sqrt(bb / S) > kZeroRhs * std::sqrt(ae2 / S));
+        const double normb = std::sqrt(bb / S);
+        double rr = bb;
+        if (!zero) {
+            for (outer = 0; outer < 64; outer++) {
+                if (outer > 0) {
+                    // r = b - C x = -G A (E + x)
+                    ApplyArgs a;
+                    a.op = OP_AX;
+                    a.x = e;
+                    for (int c = 0; c < p->d; c++) a.E[c] = E[c];
+                    a.epi = EPI_STORE;
+                    a.sgn = -1.0;
+                    a.y = p->r64;
+                    int nb = 0;
+                    HIPOK(run_apply<double>(p->op64, a, &nb));
+                    applies64++;
+                    if ((s = reduce_read(p, p->op64, nb, RED_TOTAL, &rr))) return s;
+                }
+                res = std::sqrt(rr / S) / normb;
+                if (!std::isfinite(rr)) {
+                    status = FGH_E_DIVERGED;
+                    break;
+                }
+                if (res <= tol) break;
+                double eta = tol / res;
+                if (eta < kInnerTolMin) eta = kInnerTolMin;
+                HIPOK(run_f64_to_f32(p->stream, n, p->r32, p->r64));
+                HIPOK(run_fill<float>(p->stream, n, p->x32, 0.0f));
+                SolveOut so;
+                if (solver == FGH_CG) {
+                    if ((s = cg_core<float>(p, p->x32, p->r32, p->p32, p->q32, rr, eta, max_iter, 0, &so))) return s;
+                } else {
+                    if ((s = cheb_core<float>(p, p->x32, p->r32, p->p32, rr, eta, max_iter, 0, &so))) return s;
+                }
+                inner_total += so.iters;
+                if (so.status == FGH_E_DIVERGED) {
+                    status = FGH_E_DIVERGED;
+                    break;
+                }
+                // x += G delta in FP64
+                HIPOK(run_fill<double>(p->stream, n, p->p64, 0.0));
+                HIPOK(run_add_f32_to_f64(p->stream, n, p->p64, p->x32));
+                ApplyArgs a;
+                a.op = OP_ID;
+                a.x = p->p64;
+                a.epi = EPI_STORE;
+                a.sgn = 1.0;
+                a.y = p->q64;
+                int nb = 0;
+                HIPOK(run_apply<double>(p->op64, a, &nb));
+                applies64++;
+                HIPOK(run_add_f64(p->stream, n, e, p->q64));
+            }
+            if (status == FGH_OK && !(res <= tol)) status = FGH_E_NO_CONVERGENCE;
+        }
+    } else {
+        return FGH_E_UNSUPPORTED;
+    }
+    if (st) {
+        st->iters = inner_total;
+        st->outer_iters = outer;
+        st->fp64_applies = applies64;
+        st->status = status;
+        st->rel_res_recursive = res;
+    }
+    return FGH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fgh_status_string(fgh_status s)
+{
+    switch (s) {
+        case FGH_OK: return "ok";
+        case FGH_E_INVALID: return "invalid argument";
+        case FGH_E_NOT_SPD: return "coefficients not symmetric positive definite";
+        case FGH_E_UNSUPPORTED: return "unsupported combination";
+        case FGH_E_WORKSPACE: return "workspace missing or too small";
+        case FGH_E_NO_CONVERGENCE: return "no convergence within the iteration cap";
+        case FGH_E_DIVERGED: return "diverged";
+        case FGH_E_DEVICE: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+fgh_status fgh_plan_workspace(int d, const int32_t* N, fgh_rule rule, fgh_precision precision, fgh_akind a_kind,
+                              size_t* bytes)
+{
+    if (!bytes) return FGH_E_INVALID;
+    if (rule != FGH_GANI && rule != FGH_GA) return FGH_E_INVALID;
+    if (precision != FGH_FP64 && precision != FGH_FP32_REFINED) return FGH_E_INVALID;
+    if (a_kind < FGH_A_SYM || a_kind > FGH_A_PHASE) return FGH_E_INVALID;
+    Geo g;
+    if (!make_geo(d, N, rule, &g)) return FGH_E_INVALID;
+    *bytes = make_layout(g, N, rule, precision, a_kind).total;
+    return FGH_OK;
+}
+
+fgh_status fgh_plan_create(fgh_plan* out, int d, const int32_t* N, fgh_rule rule, fgh_precision precision,
+                           fgh_akind a_kind, const void* A, const uint8_t* phase, const double* phase_table,
+                           int n_phases, double c_A, double C_A, void* workspace, size_t workspace_bytes,
+                           void* stream)
+{
+    if (!out) return FGH_E_INVALID;
+    *out = nullptr;
+    size_t need = 0;
+    fgh_status s = fgh_plan_workspace(d, N, rule, precision, a_kind, &need);
+    if (s) return s;
+    if (a_kind == FGH_A_PHASE) {
+        if (!phase || !phase_table || n_phases < 1 || n_phases > kMaxPhases) return FGH_E_INVALID;
+    } else if (!A) {
+        return FGH_E_INVALID;
+    }
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) % kAlign)) return FGH_E_WORKSPACE;
+    fgh_plan p = new (std::nothrow) fgh_plan_s();
+    if (!p) return FGH_E_DEVICE;
+    p->d = d;
+    for (int a = 0; a < 3; a++) p->N[a] = a < d ? N[a] : 1;
+    p->rule = rule;
+    p->prec = precision;
+    p->akind = a_kind;
+    make_geo(d, N, rule, &p->g);
+    p->lay = make_layout(p->g, N, rule, precision, a_kind);
+    p->ws = static_cast<char*>(workspace);
+    p->stream = static_cast<hipStream_t>(stream);
+    p->ncoef_op = (a_kind == FGH_A_SYM) ? ncoef_for(d) : 1;
+    if (hipHostMalloc(reinterpret_cast<void**>(&p->host_buf), 64 * sizeof(double)) != hipSuccess) {
+        delete p;
+        return FGH_E_DEVICE;
+    }
+    auto fail = [&](fgh_status e) {
+        fgh_plan_destroy(p);
+        return e;
+    };
+    const int nc = ncoef_for(d);
+    p->nphase = a_kind == FGH_A_PHASE ? n_phases : 0;
+    for (int i = 0; i < kMaxPhases; i++)
+        for (int q = 0; q < 6; q++) p->tab[i][q] = (i < p->nphase && q < nc) ? phase_table[i * nc + q] : 0.0;
+    if (a_kind == FGH_A_PHASE)
+        for (int i = 0; i < p->nphase; i++)
+            for (int q = 0; q < nc; q++)
+                if (!std::isfinite(p->tab[i][q])) return fail(FGH_E_NOT_SPD);
+    fill_opplan(p, &p->op64, false);
+    fill_opplan(p, &p->op32, true);
+    const long long nv = (long long)d * p->g.npts;
+    double* v64 = reinterpret_cast<double*>(p->ws + p->lay.vec64);
+    p->r64 = v64;
+    p->p64 = v64 + nv;
+    p->q64 = v64 + 2 * nv;
+    float* v32 = reinterpret_cast<float*>(p->ws + p->lay.vec32);
+    p->x32 = v32;
+    p->r32 = v32 + nv;
+    p->p32 = v32 + 2 * nv;
+    p->q32 = v32 + 3 * nv;
+    if ((s = upload_twiddles(p))) return fail(s);
+
+    long long nN = 1;
+    for (int a = 0; a < d; a++) nN *= N[a];
+    double* partials = reinterpret_cast<double*>(p->ws + p->lay.partials);
+
+    // spectral bounds of the input (eq:A)
+    double lo = 1e300, hi = -1e300;
+    if (a_kind == FGH_A_PHASE) {
+        unsigned* mask = reinterpret_cast<unsigned*>(p->ws + p->lay.mask);
+        if (run_fill<unsigned>(p->stream, 1, mask, 0u) != hipSuccess) return fail(FGH_E_DEVICE);
+        if (run_phase_mask(p->stream, phase, nN, mask) != hipSuccess) return fail(FGH_E_DEVICE);
+        unsigned hm = 0;
+        if (hipMemcpyAsync(&hm, mask, sizeof(unsigned), hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
+            hipStreamSynchronize(p->stream) != hipSuccess)
+            return fail(FGH_E_DEVICE);
+        if (hm >> p->nphase) return fail(FGH_E_INVALID);  // a phase index outside the table
+        for (int i = 0; i < p->nphase; i++)
+            if (hm & (1u << i)) {
+                double l, h;
+                host_sym_eigs(d, p->tab[i], &l, &h);
+                lo = std::fmin(lo, l);
+                hi = std::fmax(hi, h);
+            }
+    } else {
+        int nb = 0;
+        if (run_eig_bounds(p->stream, d, a_kind == FGH_A_ISO ? AK_ISO : AK_SYM, static_cast<const double*>(A), nN,
+                           partials, &nb) != hipSuccess)
+            return fail(FGH_E_DEVICE);
+        double lh[2];
+        if (run_minmax_reduce(p->stream, partials, nb, lh) != hipSuccess) return fail(FGH_E_DEVICE);
+        lo = lh[0];
+        hi = lh[1];
+    }
+    if (!(lo > 0.0) || !std::isfinite(hi)) return fail(FGH_E_NOT_SPD);
+    if (c_A > 0.0 && C_A > 0.0) {
+        if (c_A > C_A) return fail(FGH_E_NOT_SPD);
+        p->cA = c_A;
+        p->CA = C_A;
+    } else {
+        p->cA = lo;
+        p->CA = hi;
+    }
+
+    // operator coefficients (CoefArgs)
+    CoefArgs ca{};
+    for (int i = 0; i < kMaxPhases; i++)
+        for (int q = 0; q < 6; q++) ca.tab[i][q] = p->tab[i][q];
+    const double omega = std::sqrt(p->cA * p->CA);
+    for (int i = 0; i < p->nphase; i++) host_shift_inverse(d, p->tab[i], omega, ca.tab_inv[i]);
+    const long long npts = p->g.npts;
+    if (rule == FGH_GA) {
+        GaAsm ga{};
+        ga.d = d;
+        ga.nN = nN;
+        ga.nM = npts;
+        std::vector<double> buf;
+        for (int a = 0; a < d; a++) {
+            ga.N[a] = N[a];
+            ga.M[a] = 2 * N[a] - 1;
+            // sinc(n / N) for the signed frequencies n of the M positions, and DFT tables
+            buf.assign((size_t)ga.M[a], 0.0);
+            for (int i = 0; i < ga.M[a]; i++) {
+                const int nf = (2 * i < ga.M[a]) ? i : i - ga.M[a];
+                if (nf == 0) {
+                    buf[i] = 1.0;
+                } else {
+                    const long double t = 3.141592653589793238462643383279502884L * (long double)nf / (long double)N[a];
+                    buf[i] = (double)(sinl(t) / t);
+                }
+            }
+            if (hipMemcpyAsync(p->ws + p->lay.sinc[a], buf.data(), (size_t)ga.M[a] * 8, hipMemcpyHostToDevice, p->stream) != hipSuccess)
+                return fail(FGH_E_DEVICE);
+            std::vector<double> t;
+            for (int which = 0; which < 2; which++) {
+                const int L = which ? ga.M[a] : ga.N[a];
+                t.assign(2 * (size_t)L, 0.0);
+                for (int m = 0; m < L; m++) {
+                    const long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)L;
+                    t[2 * m] = (double)cosl(ang);
+                    t[2 * m + 1] = -(double)sinl(ang);
+                }
+                const size_t off = which ? p->lay.twM[a] : p->lay.twN[a];
+                if (hipMemcpyAsync(p->ws + off, t.data(), (size_t)L * 16, hipMemcpyHostToDevice, p->stream) != hipSuccess ||
+                    hipStreamSynchronize(p->stream) != hipSuccess)
+                    return fail(FGH_E_DEVICE);
+            }
+            ga.sinc[a] = reinterpret_cast<const double*>(p->ws + p->lay.sinc[a]);
+            ga.twN[a] = reinterpret_cast<const double2*>(p->ws + p->lay.twN[a]);
+            ga.twM[a] = reinterpret_cast<const double2*>(p->ws + p->lay.twM[a]);
+        }
+        ga.c0 = reinterpret_cast<double2*>(p->ws + p->lay.vec64);
+        ga.c1 = ga.c0 + npts;
+        double* coef = reinterpret_cast<double*>(p->ws + p->lay.coef64);
+        const int kind = a_kind == FGH_A_PHASE ? AK_PHASE : a_kind == FGH_A_ISO ? AK_ISO : AK_SYM;
+        for (int q = 0; q < p->ncoef_op; q++) {
+            double pv[kMaxPhases] = {0};
+            for (int i = 0; i < p->nphase; i++) pv[i] = p->tab[i][0];  // isotropic phases: a00
+            if (run_ga_component(p->stream, ga, kind, static_cast<const double*>(A), q, phase, pv, p->nphase,
+                                 coef + q * npts) != hipSuccess)
+                return fail(FGH_E_DEVICE);
+        }
+        if (hipStreamSynchronize(p->stream) != hipSuccess) return fail(FGH_E_DEVICE);
+        ca.kind = p->ncoef_op == 1 ? AK_ISO : AK_SYM;
+        ca.ncoef = p->ncoef_op;
+        ca.coef = coef;
+        ca.phase = nullptr;
+        if (a_kind == FGH_A_PHASE) {
+            // the phase table must be isotropic for the scalar double-grid representation
+            for (int i = 0; i < p->nphase; i++) {
+                const double* t = p->tab[i];
+                const bool iso = d == 2 ? (t[1] == 0.0 && t[0] == t[2])
+                                        : (t[1] == 0.0 && t[2] == 0.0 && t[4] == 0.0 && t[0] == t[3] && t[0] == t[5]);
+                if (!iso) return fail(FGH_E_UNSUPPORTED);
+            }
+        }
+    } else {
+        ca.kind = a_kind == FGH_A_PHASE ? AK_PHASE : a_kind == FGH_A_ISO ? AK_ISO : AK_SYM;
+        ca.ncoef = a_kind == FGH_A_SYM ? nc : 1;
+        ca.coef = A;
+        ca.phase = phase;
+    }
+    p->op64.A = ca;
+    p->op32.A = ca;
+    if (precision == FGH_FP32_REFINED && ca.kind != AK_PHASE) {
+        float* c32 = reinterpret_cast<float*>(p->ws + p->lay.coef32);
+        if (run_to_f32(p->stream, (long long)ca.ncoef * npts, c32, static_cast<const double*>(ca.coef)) != hipSuccess)
+            return fail(FGH_E_DEVICE);
+        p->op32.A.coef = c32;
+    }
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return fail(FGH_E_DEVICE);
+    *out = p;
+    return FGH_OK;
+}
+
+void fgh_plan_destroy(fgh_plan p)
+{
+    if (!p) return;
+    if (p->host_buf) (void)hipHostFree(p->host_buf);
+    delete p;
+}
+
+int64_t fgh_plan_grid_points(fgh_plan p) { return p ? p->g.npts : 0; }
+
+fgh_status fgh_plan_bounds(fgh_plan p, double* c_A, double* C_A)
+{
+    if (!p || !c_A || !C_A) return FGH_E_INVALID;
+    *c_A = p->cA;
+    *C_A = p->CA;
+    return FGH_OK;
+}
+
+fgh_status fgh_apply(fgh_plan p, const double* x, double* y)
+{
+    if (!p || !x || !y) return FGH_E_INVALID;
+    ApplyArgs a;
+    a.op = OP_AX;
+    a.x = x;
+    a.epi = EPI_STORE;
+    a.sgn = 1.0;
+    a.y = y;
+    int nb = 0;
+    HIPOK(run_apply<double>(p->op64, a, &nb));
+    return FGH_OK;
+}
+
+fgh_status fgh_apply_f32(fgh_plan p, const float* x, float* y)
+{
+    if (!p || !x || !y) return FGH_E_INVALID;
+    if (p->prec != FGH_FP32_REFINED) return FGH_E_UNSUPPORTED;
+    ApplyArgs a;
+    a.op = OP_AX;
+    a.x = x;
+    a.epi = EPI_STORE;
+    a.sgn = 1.0;
+    a.y = y;
+    int nb = 0;
+    HIPOK(run_apply<float>(p->op32, a, &nb));
+    return FGH_OK;
+}
+
+fgh_status fgh_ga_coefficients(fgh_plan p, double* out)
+{
+    if (!p || !out) return FGH_E_INVALID;
+    if (p->rule != FGH_GA) return FGH_E_INVALID;
+    const size_t bytes = (size_t)p->ncoef_op * p->g.npts * 8;
+    HIPOK(hipMemcpyAsync(out, p->ws + p->lay.coef64, bytes, hipMemcpyDeviceToDevice, p->stream));
+    HIPOK(hipStreamSynchronize(p->stream));
+    return FGH_OK;
+}
+
+static fgh_status solve_common(fgh_plan p, fgh_solver solver, const double* E, int nrhs, double tol, int max_iter,
+                               int fixed, double* e, fgh_stats* stats)
+{
+    if (!p || !E || !e || nrhs < 1) return FGH_E_INVALID;
+    if (solver < FGH_RICHARDSON || solver > FGH_EYRE_MILTON) return FGH_E_INVALID;
+    if (fixed <= 0 && (!(tol > 0.0) || !(tol < 1.0) || max_iter < 1)) return FGH_E_INVALID;
+    if (solver == FGH_EYRE_MILTON && p->rule == FGH_GA) return FGH_E_UNSUPPORTED;
+    for (int j = 0; j < nrhs * p->d; j++)
+        if (!std::isfinite(E[j])) return FGH_E_INVALID;
+    const long long n = (long long)p->d * p->g.npts;
+    int worst = FGH_OK;
+    for (int j = 0; j < nrhs; j++) {
+        const double* Ej = E + j * p->d;
+        double* ej = e + j * n;
+        fgh_stats st{};
+        const auto t0 = std::chrono::steady_clock::now();
+        fgh_status s;
+        if (p->prec == FGH_FP32_REFINED && fixed <= 0)
+            s = solve_one_refined(p, solver, Ej, tol, max_iter, ej, &st);
+        else
+            s = solve_one_fp64(p, solver, Ej, tol, max_iter, fixed, ej, &st);
+        if (s) return s;
+        if (hipStreamSynchronize(p->stream) != hipSuccess) return FGH_E_DEVICE;
+        const auto t1 = std::chrono::steady_clock::now();
+        st.seconds = std::chrono::duration<double>(t1 - t0).count();
+        st.c_A = p->cA;
+        st.C_A = p->CA;
+        // true residual at exit (not timed)
+        double bb = 0.0;
+        if ((s = rhs<double>(p, Ej, p->r64, &bb, nullptr))) return s;
+        double rt = 0.0;
+        if ((s = true_residual(p, Ej, ej, bb, &rt))) return s;
+        st.rel_res_true = rt;
+        if (stats) stats[j] = st;
+        if (st.status != FGH_OK && worst == FGH_OK) worst = st.status;
+    }
+    return (fgh_status)worst;
+}
+
+fgh_status fgh_solve(fgh_plan p, fgh_solver solver, const double* E, int nrhs, double tol, int max_iter, double* e,
+                     fgh_stats* stats)
+{
+    return solve_common(p, solver, E, nrhs, tol, max_iter, 0, e, stats);
+}
+
+fgh_status fgh_solve_fixed(fgh_plan p, fgh_solver solver, const double* E, int nrhs, int iters, double* e,
+                           fgh_stats* stats)
+{
+    if (iters < 1) return FGH_E_INVALID;
+    if (p && p->prec != FGH_FP64) return FGH_E_UNSUPPORTED;
+    return solve_common(p, solver, E, nrhs, 0.5, iters, iters, e, stats);
+}
+
+fgh_status fgh_effective(fgh_plan p, const double* E, int nrhs, const double* e, double* bilinear, double* flux)
+{
+    if (!p || !E || !e || nrhs < 1 || nrhs > 3) return FGH_E_INVALID;
+    const int d = p->d;
+    // loads into the scalar block (device) for the kernel
+    double* Ed = reinterpret_cast<Scalars*>(p->ws + p->lay.scalars)->aux;
+    HIPOK(hipMemcpyAsync(Ed, E, sizeof(double) * nrhs * d, hipMemcpyHostToDevice, p->stream));
+    int nb = 0;
+    HIPOK(run_effective(p->op64, nrhs, Ed, e, &nb));
+    const int nv = nrhs * nrhs + nrhs * d;
+    double host[18];
+    HIPOK(run_reduce_multi(p->op64, nb, nv, host));
+    const double S = (double)p->g.npts;
+    if (bilinear)
+        for (int q = 0; q < nrhs * nrhs; q++) bilinear[q] = host[q] / S;
+    if (flux)
+        for (int q = 0; q < nrhs * d; q++) flux[q] = host[nrhs * nrhs + q] / S;
+    return FGH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1347 @@
+// fgh_kernels.hip -- gfx950 kernels of libfgh: the passes of y = G A x (eq:linsys) with the
+// solver epilogues of Algorithms 1-4 fused into the last pass, deterministic FP64 reductions,
+// and the set-up kernels (double-grid coefficients, spectral bounds).
+#include <hip/hip_runtime.h>
+
+#include "fgh_fft.hpp"
+#include "fgh_launch.hpp"
+
+namespace fgh {
+
+// ------------------------------------------------------------------------------------------
+// Coefficient helpers: z = A(pt) u with A as the passes see it (eq:A, eq:GaNi, eq:Ga_eval).
+// ------------------------------------------------------------------------------------------
+template <typename T, int D>
+__device__ __forceinline__ void sym_mul(const T* a, const T* u, T* z)
+{
+    if (D == 2) {  // a00 a01 a11
+        z[0] = a[0] * u[0] + a[1] * u[1];
+        z[1] = a[1] * u[0] + a[2] * u[1];
+    } else {       // a00 a01 a02 a11 a12 a22
+        z[0] = a[0] * u[0] + a[1] * u[1] + a[2] * u[2];
+        z[1] = a[1] * u[0] + a[3] * u[1] + a[4] * u[2];
+        z[2] = a[2] * u[0] + a[4] * u[1] + a[5] * u[2];
+    }
+}
+
+template <int D>
+constexpr int ncoef_of() { return D == 2 ? 3 : 6; }
+
+// Load the packed coefficients of point pt into a[] (AK_ISO gives a scalar in a[0]).
+template <typename T, int D, int AK>
+__device__ __forceinline__ void load_coef(const CoefArgs& A, const T* tab, long long pt, long long npts, T* a)
+{
+    if (AK == AK_ISO) {
+        a[0] = static_cast<const T*>(A.coef)[pt];
+    } else if (AK == AK_PHASE) {
+        const int ph = A.phase[pt];
+#pragma unroll
+        for (int q = 0; q < ncoef_of<D>(); q++) a[q] = tab[ph * 6 + q];
+    } else {
+        const T* c = static_cast<const T*>(A.coef);
+#pragma unroll
+        for (int q = 0; q < ncoef_of<D>(); q++) a[q] = c[q * npts + pt];
+    }
+}
+
+template <typename T, int D, int AK>
+__device__ __forceinline__ void mul_A(const T* a, const T* u, T* z)
+{
+    if (AK == AK_ISO) {
+#pragma unroll
+        for (int c = 0; c < D; c++) z[c] = a[0] * u[c];
+    } else {
+        sym_mul<T, D>(a, u, z);
+    }
+}
+
+// Solve (A + w I) v = rhs at one point for packed symmetric A (closed-form inverse).
+template <typename T, int D>
+__device__ __forceinline__ void sym_shift_solve(const T* a, T w, const T* rhs, T* v)
+{
+    if (D == 2) {
+        const T m00 = a[0] + w, m01 = a[1], m11 = a[2] + w;
+        const T det = m00 * m11 - m01 * m01;
+        v[0] = (m11 * rhs[0] - m01 * rhs[1]) / det;
+        v[1] = (-m01 * rhs[0] + m00 * rhs[1]) / det;
+    } else {
+        const T m00 = a[0] + w, m01 = a[1], m02 = a[2], m11 = a[3] + w, m12 = a[4], m22 = a[5] + w;
+        const T c00 = m11 * m22 - m12 * m12;
+        const T c01 = m02 * m12 - m01 * m22;
+        const T c02 = m01 * m12 - m02 * m11;
+        const T c11 = m00 * m22 - m02 * m02;
+        const T c12 = m01 * m02 - m00 * m12;
+        const T c22 = m00 * m11 - m01 * m01;
+        const T det = m00 * c00 + m01 * c01 + m02 * c02;
+        v[0] = (c00 * rhs[0] + c01 * rhs[1] + c02 * rhs[2]) / det;
+        v[1] = (c01 * rhs[0] + c11 * rhs[1] + c12 * rhs[2]) / det;
+        v[2] = (c02 * rhs[0] + c12 * rhs[1] + c22 * rhs[2]) / det;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Pass 1: real rows along the last axis -> half spectra S1.
+// ------------------------------------------------------------------------------------------
+template <typename T>
+struct FirstArgs {
+    Geo g;
+    Axis ax;
+    int rpb, npen;
+    const T* x;
+    T* p;
+    const T* r;
+    const Scalars* sc;
+    double E[3];
+    double omega;
+    CoefArgs A;
+    cpx<T>* out;
+    const cpx<T>* twg;
+};
+
+template <typename T, int D, int AK, int OP>
+__global__ __launch_bounds__(kThreads) void k_first(FirstArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int L = a.ax.L;
+    const int npen = a.npen;
+    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
+    cpx<T>* b0 = tw + L;
+    cpx<T>* b1 = b0 + npen * L;
+    T* tab = reinterpret_cast<T*>(b1 + npen * L);
+    for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
+    if (AK == AK_PHASE)
+        for (int m = threadIdx.x; m < kMaxPhases * 6; m += blockDim.x) tab[m] = T(a.A.tab[m / 6][m % 6]);
+    const long long row0 = (long long)blockIdx.x * a.rpb;
+    const long long npts = a.g.npts;
+    if ((a.rpb * D) & 1)
+        for (int i = threadIdx.x; i < L; i += blockDim.x) b0[(npen - 1) * L + i].y = T(0);
+    __syncthreads();
+    const T beta = (OP == OP_AP_CG) ? T(a.sc->beta) : T(0);
+    for (int idx = threadIdx.x; idx < a.rpb * L; idx += blockDim.x) {
+        const int r = idx / L;
+        const int i = idx - r * L;
+        const long long row = row0 + r;
+        T z[D];
+        if (row < a.g.rows) {
+            const long long pt = row * L + i;
+            T u[D];
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                if (OP == OP_AX)
+                    u[c] = a.x[c * npts + pt] + T(a.E[c]);
+                else if (OP == OP_E)
+                    u[c] = T(a.E[c]);
+                else if (OP == OP_AP_CG) {
+                    const T pn = a.r[c * npts + pt] + beta * a.p[c * npts + pt];
+                    a.p[c * npts + pt] = pn;
+                    u[c] = pn;
+                } else
+                    u[c] = a.x[c * npts + pt];
+            }
+            if (OP == OP_ID) {
+#pragma unroll
+                for (int c = 0; c < D; c++) z[c] = u[c];
+            } else {
+                T co[6];
+                load_coef<T, D, AK>(a.A, tab, pt, npts, co);
+                mul_A<T, D, AK>(co, u, z);
+                if (OP == OP_EM) {
+#pragma unroll
+                    for (int c = 0; c < D; c++) z[c] -= T(a.omega) * u[c];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < D; c++) z[c] = T(0);
+        }
+#pragma unroll
+        for (int c = 0; c < D; c++) {
+            const int pp = r * D + c;
+            if (pp & 1)
+                b0[(pp >> 1) * L + i].y = z[c];
+            else
+                b0[(pp >> 1) * L + i].x = z[c];
+        }
+    }
+    __syncthreads();
+    cpx<T>* res = fft_lds<T, false>(b0, b1, a.ax, npen, tw);
+    const int Hb = a.g.Hb;
+    const int nreal = a.rpb * D;
+    for (int idx = threadIdx.x; idx < npen * Hb; idx += blockDim.x) {
+        const int pen = idx / Hb;
+        const int k = idx - pen * Hb;
+        const cpx<T> Z = res[pen * L + k];
+        const cpx<T> Zm = res[pen * L + (k ? L - k : 0)];
+        const cpx<T> Av = {T(0.5) * (Z.x + Zm.x), T(0.5) * (Z.y - Zm.y)};
+        const cpx<T> Bv = {T(0.5) * (Z.y + Zm.y), T(-0.5) * (Z.x - Zm.x)};
+#pragma unroll
+        for (int half = 0; half < 2; half++) {
+            const int pp = 2 * pen + half;
+            if (pp < nreal) {
+                const int r = pp / D;
+                const int c = pp - r * D;
+                const long long row = row0 + r;
+                if (row < a.g.rows) a.out[c * a.g.s1 + row * Hb + k] = half ? Bv : Av;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Strided pass along a middle axis (3D axis 1), one component per workgroup.
+// ------------------------------------------------------------------------------------------
+template <typename T>
+struct AxisArgs {
+    Axis ax;
+    int nin, nout;          // stored counts along the axis
+    int bin, bout;          // 1: stored index is a band index (frequency signed(s, n)), 0: position
+    int inner, P, ntiles;
+    long long in_os, out_os, in_cs, out_cs;
+    const cpx<T>* in;
+    cpx<T>* out;
+    const cpx<T>* twg;
+};
+
+template <typename T, bool INV>
+__global__ __launch_bounds__(kThreads) void k_axis(AxisArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int L = a.ax.L;
+    const int P = a.P;
+    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
+    cpx<T>* b0 = tw + L;
+    cpx<T>* b1 = b0 + P * L;
+    const int tile = blockIdx.x, o = blockIdx.y, c = blockIdx.z;
+    for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
+    if (a.nin < L)
+        for (int m = threadIdx.x; m < P * L; m += blockDim.x) b0[m] = {T(0), T(0)};
+    __syncthreads();
+    const cpx<T>* in = a.in + c * a.in_cs + o * a.in_os;
+    for (int idx = threadIdx.x; idx < a.nin * P; idx += blockDim.x) {
+        const int s = idx / P;
+        const int col = idx - s * P;
+        const int j = tile * P + col;
+        const int pos = a.bin ? band_pos(s, a.nin, L) : s;
+        cpx<T> v = {T(0), T(0)};
+        if (j < a.inner) v = in[(long long)s * a.inner + j];
+        b0[col * L + pos] = v;
+    }
+    __syncthreads();
+    cpx<T>* res = fft_lds<T, INV>(b0, b1, a.ax, P, tw);
+    cpx<T>* out = a.out + c * a.out_cs + o * a.out_os;
+    for (int idx = threadIdx.x; idx < a.nout * P; idx += blockDim.x) {
+        const int s = idx / P;
+        const int col = idx - s * P;
+        const int j = tile * P + col;
+        if (j < a.inner) {
+            const int pos = a.bout ? band_pos(s, a.nout, L) : s;
+            out[(long long)s * a.inner + j] = res[col * L + pos];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Middle pass along axis 0: forward FFT of every component, Fourier multiplier with all d
+// components of a frequency at hand (eq:proj / eq:discrete_proj; Algorithm 4's I - 2G^),
+// inverse FFT.  Works in place on the spectrum.
+// ------------------------------------------------------------------------------------------
+template <typename T>
+struct MidArgs {
+    Axis ax;
+    int B0, cols, Hb, B1, P, ntiles;
+    long long cs;
+    double scale;  // 1 / |grid| (the forward DFT factor of eq:DFT)
+    cpx<T>* buf;
+    const cpx<T>* twg;
+};
+
+template <typename T, int D, int MULT>
+__global__ __launch_bounds__(kThreads) void k_middle(MidArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int L = a.ax.L;
+    const int P = a.P;
+    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
+    cpx<T>* reg = tw + L;
+    const int PL = P * L;
+    const int tile = blockIdx.x;
+    for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
+    for (int idx = threadIdx.x; idx < D * PL; idx += blockDim.x) {
+        const int c = idx / PL;
+        const int rem = idx - c * PL;
+        const int i0 = rem / P;
+        const int col = rem - i0 * P;
+        const int j = tile * P + col;
+        cpx<T> v = {T(0), T(0)};
+        if (j < a.cols) v = a.buf[c * a.cs + (long long)i0 * a.cols + j];
+        reg[c * PL + col * L + i0] = v;
+    }
+    __syncthreads();
+    int where[D];
+    int freebuf = D;
+#pragma unroll
+    for (int c = 0; c < D; c++) where[c] = c;
+#pragma unroll
+    for (int c = 0; c < D; c++) {
+        cpx<T>* res = fft_lds<T, false>(reg + where[c] * PL, reg + freebuf * PL, a.ax, P, tw);
+        if (res != reg + where[c] * PL) {
+            const int t = where[c];
+            where[c] = freebuf;
+            freebuf = t;
+        }
+    }
+    const T scale = T(a.scale);
+    for (int idx = threadIdx.x; idx < PL; idx += blockDim.x) {
+        const int f = idx / P;
+        const int col = idx - f * P;
+        const int j = tile * P + col;
+        const int k0 = signed_index(f, L);
+        const bool inband = (2 * (k0 < 0 ? -k0 : k0) < a.B0) && (j < a.cols);
+        int kv[3];
+        kv[0] = k0;
+        if (D == 2) {
+            kv[1] = j;
+        } else {
+            const int kb1 = j / a.Hb;
+            kv[1] = signed_index(kb1, a.B1);
+            kv[2] = j - kb1 * a.Hb;
+        }
+        cpx<T> z[D];
+#pragma unroll
+        for (int c = 0; c < D; c++) z[c] = reg[where[c] * PL + col * L + f];
+        cpx<T> w[D];
+        double kk = 0.0;
+#pragma unroll
+        for (int c = 0; c < D; c++) kk += double(kv[c]) * double(kv[c]);
+        if (!inband) {
+#pragma unroll
+            for (int c = 0; c < D; c++) w[c] = {T(0), T(0)};
+        } else if (kk == 0.0) {
+#pragma unroll
+            for (int c = 0; c < D; c++) w[c] = (MULT == MULT_EM) ? scale * z[c] : cpx<T>{T(0), T(0)};
+        } else {
+            cpx<T> kz = {T(0), T(0)};
+#pragma unroll
+            for (int c = 0; c < D; c++) kz = kz + T(kv[c]) * z[c];
+            const T inv = T(1.0 / kk);
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                const cpx<T> gz = (T(kv[c]) * inv) * kz;
+                w[c] = (MULT == MULT_G) ? scale * gz : scale * (z[c] - T(2) * gz);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < D; c++) reg[where[c] * PL + col * L + f] = w[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < D; c++) {
+        cpx<T>* res = fft_lds<T, true>(reg + where[c] * PL, reg + freebuf * PL, a.ax, P, tw);
+        if (res != reg + where[c] * PL) {
+            const int t = where[c];
+            where[c] = freebuf;
+            freebuf = t;
+        }
+    }
+    for (int idx = threadIdx.x; idx < D * PL; idx += blockDim.x) {
+        const int c = idx / PL;
+        const int rem = idx - c * PL;
+        const int i0 = rem / P;
+        const int col = rem - i0 * P;
+        const int j = tile * P + col;
+        if (j < a.cols) a.buf[c * a.cs + (long long)i0 * a.cols + j] = reg[where[c] * PL + col * L + i0];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Last pass: half spectra -> real rows, with the solver epilogue (Algorithms 1-4).
+// ------------------------------------------------------------------------------------------
+template <typename T>
+struct LastArgs {
+    Geo g;
+    Axis ax;
+    int rpb, npen;
+    const cpx<T>* in;
+    T* y;
+    T* x;
+    T* r;
+    T* p;
+    T* q;
+    const T* src;
+    double E[3];
+    double omega, alpha, beta, sgn;
+    CoefArgs A;
+    double* partials;
+    const cpx<T>* twg;
+};
+
+template <typename T, int D, int AK, int EPI>
+__global__ __launch_bounds__(kThreads) void k_last(LastArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int L = a.ax.L;
+    const int npen = a.npen;
+    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
+    cpx<T>* b0 = tw + L;
+    cpx<T>* b1 = b0 + npen * L;
+    T* tab = reinterpret_cast<T*>(b1 + npen * L);
+    __shared__ double red[kThreads / 64];
+    for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
+    if (EPI == EPI_EM && AK == AK_PHASE)
+        for (int m = threadIdx.x; m < kMaxPhases * 6; m += blockDim.x) tab[m] = T(a.A.tab_inv[m / 6][m % 6]);
+    const long long row0 = (long long)blockIdx.x * a.rpb;
+    const int Hb = a.g.Hb;
+    const int nreal = a.rpb * D;
+    for (int idx = threadIdx.x; idx < npen * L; idx += blockDim.x) {
+        const int pen = idx / L;
+        const int f = idx - pen * L;
+        int kk = -1;
+        bool mirror = false;
+        if (f < Hb) {
+            kk = f;
+        } else if (L - f < Hb) {
+            kk = L - f;
+            mirror = true;
+        }
+        cpx<T> Z = {T(0), T(0)};
+        if (kk >= 0) {
+            cpx<T> v[2];
+#pragma unroll
+            for (int half = 0; half < 2; half++) {
+                v[half] = {T(0), T(0)};
+                const int pp = 2 * pen + half;
+                if (pp < nreal) {
+                    const int r = pp / D;
+                    const int c = pp - r * D;
+                    const long long row = row0 + r;
+                    if (row < a.g.rows) v[half] = a.in[c * a.g.s1 + row * Hb + kk];
+                }
+            }
+            if (!mirror)
+                Z = {v[0].x - v[1].y, v[0].y + v[1].x};
+            else
+                Z = {v[0].x + v[1].y, -v[0].y + v[1].x};
+        }
+        b0[pen * L + f] = Z;
+    }
+    __syncthreads();
+    cpx<T>* res = fft_lds<T, true>(b0, b1, a.ax, npen, tw);
+    const long long npts = a.g.npts;
+    double acc = 0.0;
+    for (int idx = threadIdx.x; idx < a.rpb * L; idx += blockDim.x) {
+        const int r = idx / L;
+        const int i = idx - r * L;
+        const long long row = row0 + r;
+        if (row >= a.g.rows) continue;
+        const long long pt = row * L + i;
+        T y[D];
+#pragma unroll
+        for (int c = 0; c < D; c++) {
+            const int pp = r * D + c;
+            const cpx<T> v = res[(pp >> 1) * L + i];
+            y[c] = (pp & 1) ? v.y : v.x;
+        }
+        if (EPI == EPI_STORE) {
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                const T v = T(a.sgn) * y[c];
+                a.y[c * npts + pt] = v;
+                acc += double(v) * double(v);
+            }
+        } else if (EPI == EPI_RICH) {
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                const T s = T(-a.omega) * y[c];
+                a.x[c * npts + pt] += s;
+                acc += double(s) * double(s);
+            }
+        } else if (EPI == EPI_CG) {
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                a.q[c * npts + pt] = y[c];
+                acc += double(y[c]) * double(a.p[c * npts + pt]);
+            }
+        } else if (EPI == EPI_CHEB) {
+            const T al = T(a.alpha), be = T(a.beta);
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                const long long o = c * npts + pt;
+                const T pv = a.p[o];
+                const T rv = a.r[o] - al * y[c];
+                a.r[o] = rv;
+                a.x[o] += al * pv;
+                a.p[o] = rv - be * pv;
+                acc += double(rv) * double(rv);
+            }
+        } else if (EPI == EPI_EM) {
+            const T w = T(a.omega);
+            T v[D], xn[D];
+            // plain form: x_new = (A + wI)^{-1} (y + 2 w E); correction form (src != NULL):
+            // delta_new = (A + wI)^{-1} y + src, src the double-precision defect
+#pragma unroll
+            for (int c = 0; c < D; c++) v[c] = a.src ? y[c] : y[c] + T(2.0 * a.omega * a.E[c]);
+            if (AK == AK_ISO) {
+                const T av = static_cast<const T*>(a.A.coef)[pt];
+#pragma unroll
+                for (int c = 0; c < D; c++) xn[c] = v[c] / (av + w);
+            } else if (AK == AK_PHASE) {
+                const int ph = a.A.phase[pt];
+                sym_mul<T, D>(tab + ph * 6, v, xn);
+            } else {
+                T co[6];
+                const T* cc = static_cast<const T*>(a.A.coef);
+#pragma unroll
+                for (int q = 0; q < ncoef_of<D>(); q++) co[q] = cc[q * npts + pt];
+                sym_shift_solve<T, D>(co, w, v, xn);
+            }
+            if (a.src) {
+#pragma unroll
+                for (int c = 0; c < D; c++) xn[c] += a.src[c * npts + pt];
+            }
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                const long long o = c * npts + pt;
+                const T s = xn[c] - a.x[o];
+                a.x[o] = xn[c];
+                acc += double(s) * double(s);
+            }
+        }
+    }
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
+}
+
+// ------------------------------------------------------------------------------------------
+// Reductions and vector kernels.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ partials, int n, Scalars* s, int op)
+{
+    __shared__ double red[kThreads / 64];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += partials[i];
+    const double tot = block_sum(v, red);
+    if (threadIdx.x == 0) {
+        s->total = tot;
+        if (op == RED_CG_ALPHA) {
+            s->qp = tot;
+            s->alpha = s->rr / tot;
+        } else if (op == RED_CG_BETA) {
+            s->rr_new = tot;
+            s->beta = tot / s->rr;
+            s->rr = tot;
+        } else if (op == RED_SET_RR) {
+            s->rr = tot;
+        }
+    }
+}
+
+// Reduce nvals interleaved partial sums [nblocks][nvals] (fixed order).
+__global__ __launch_bounds__(kThreads) void k_reduce_multi(const double* __restrict__ partials, int nblocks,
+                                                           int nvals, double* out)
+{
+    __shared__ double red[kThreads / 64];
+    for (int q = 0; q < nvals; q++) {
+        double v = 0.0;
+        for (int i = threadIdx.x; i < nblocks; i += blockDim.x) v += partials[(long long)i * nvals + q];
+        const double tot = block_sum(v, red);
+        if (threadIdx.x == 0) out[q] = tot;
+        __syncthreads();
+    }
+}
+
+constexpr int kVecBlocks = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_update(long long n, T* __restrict__ x, T* __restrict__ r,
+                                                        const T* __restrict__ p, const T* __restrict__ q,
+                                                        const Scalars* s, double* partials)
+{
+    __shared__ double red[kThreads / 64];
+    const T alpha = T(s->alpha);
+    double acc = 0.0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        x[i] += alpha * p[i];
+        const T rv = r[i] - alpha * q[i];
+        r[i] = rv;
+        acc += double(rv) * double(rv);
+    }
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_p(long long n, T* __restrict__ p, const T* __restrict__ r,
+                                                   const Scalars* s)
+{
+    const T beta = T(s->beta);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = r[i] + beta * p[i];
+}
+
+template <typename T>
+__global__ void k_fill(long long n, T* x, T v)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+template <typename T>
+__global__ void k_fill_field(int d, long long npts, T* x, double v0, double v1, double v2)
+{
+    const double vv[3] = {v0, v1, v2};
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < d * npts; i += (long long)gridDim.x * blockDim.x)
+        x[i] = T(vv[i / npts]);
+}
+
+template <typename T>
+__global__ void k_copy(long long n, T* __restrict__ dst, const T* __restrict__ src)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void k_f64_to_f32(long long n, float* __restrict__ dst, const double* __restrict__ src)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = float(src[i]);
+}
+
+__global__ void k_add_f32_to_f64(long long n, double* __restrict__ x, const float* __restrict__ d)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        x[i] += double(d[i]);
+}
+
+// y = a x + b y
+__global__ void k_axpby(long long n, double* __restrict__ y, double a, const double* __restrict__ x, double b)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        y[i] = a * x[i] + b * y[i];
+}
+
+__global__ void k_add_f64(long long n, double* __restrict__ x, const double* __restrict__ d)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        x[i] += d[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_dot(long long n, const T* __restrict__ a, const T* __restrict__ b,
+                                                  double* partials)
+{
+    __shared__ double red[kThreads / 64];
+    double acc = 0.0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        acc += double(a[i]) * double(b[i]);
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// ||A E||^2 summed over the grid (the scale of the zero right-hand-side test).
+template <int D, int AK>
+__global__ __launch_bounds__(kThreads) void k_norm_AE(long long npts, CoefArgs A, double E0, double E1, double E2,
+                                                      double* partials)
+{
+    __shared__ double red[kThreads / 64];
+    __shared__ double tab[kMaxPhases * 6];
+    if (AK == AK_PHASE)
+        for (int m = threadIdx.x; m < kMaxPhases * 6; m += blockDim.x) tab[m] = A.tab[m / 6][m % 6];
+    __syncthreads();
+    const double E[3] = {E0, E1, E2};
+    double acc = 0.0;
+    for (long long pt = (long long)blockIdx.x * blockDim.x + threadIdx.x; pt < npts; pt += (long long)gridDim.x * blockDim.x) {
+        double co[6], z[D];
+        load_coef<double, D, AK>(A, tab, pt, npts, co);
+        mul_A<double, D, AK>(co, E, z);
+#pragma unroll
+        for (int c = 0; c < D; c++) acc += z[c] * z[c];
+    }
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// A_H and flux (eq:ev_bounds): for each load j, u_j = E_j + e_j, z_j = A u_j;
+// partials [block][nrhs*nrhs + nrhs*d]: bilinear (z_j . u_i) then flux z_j.
+template <int D, int AK>
+__global__ __launch_bounds__(kThreads) void k_effective(long long npts, CoefArgs A, int nrhs, const double* Eall,
+                                                        const double* __restrict__ e, double* partials)
+{
+    __shared__ double red[kThreads / 64];
+    __shared__ double tab[kMaxPhases * 6];
+    if (AK == AK_PHASE)
+        for (int m = threadIdx.x; m < kMaxPhases * 6; m += blockDim.x) tab[m] = A.tab[m / 6][m % 6];
+    __syncthreads();
+    const int nv = nrhs * nrhs + nrhs * D;
+    // at most 3 loads: 9 + 9 accumulators
+    double acc[18];
+    for (int q = 0; q < 18; q++) acc[q] = 0.0;
+    for (long long pt = (long long)blockIdx.x * blockDim.x + threadIdx.x; pt < npts; pt += (long long)gridDim.x * blockDim.x) {
+        double co[6];
+        load_coef<double, D, AK>(A, tab, pt, npts, co);
+        double u[3][D], z[3][D];
+        for (int j = 0; j < nrhs; j++) {
+#pragma unroll
+            for (int c = 0; c < D; c++) u[j][c] = Eall[j * D + c] + e[((long long)j * D + c) * npts + pt];
+            mul_A<double, D, AK>(co, u[j], z[j]);
+        }
+        for (int j = 0; j < nrhs; j++) {
+            for (int i = 0; i < nrhs; i++) {
+                double s = 0.0;
+#pragma unroll
+                for (int c = 0; c < D; c++) s += z[j][c] * u[i][c];
+                acc[i * nrhs + j] += s;
+            }
+#pragma unroll
+            for (int c = 0; c < D; c++) acc[nrhs * nrhs + j * D + c] += z[j][c];
+        }
+    }
+    for (int q = 0; q < nv; q++) {
+        const double tot = block_sum(acc[q], red);
+        if (threadIdx.x == 0) partials[(long long)blockIdx.x * nv + q] = tot;
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Set-up kernels.
+// ------------------------------------------------------------------------------------------
+__global__ void k_to_f32(long long n, float* dst, const double* src)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = float(src[i]);
+}
+
+// Closed-form eigenvalues of symmetric 2x2 / 3x3 blocks (3x3: trigonometric method for the
+// roots of the characteristic cubic); per-block min and max -> partials [block][2].
+template <int D>
+__device__ void sym_eigs(const double* a, double* lo, double* hi)
+{
+    if (D == 2) {
+        const double m = 0.5 * (a[0] + a[2]);
+        const double h = 0.5 * (a[0] - a[2]);
+        const double rad = sqrt(h * h + a[1] * a[1]);
+        *lo = m - rad;
+        *hi = m + rad;
+    } else {
+        const double p1 = a[1] * a[1] + a[2] * a[2] + a[4] * a[4];
+        const double q = (a[0] + a[3] + a[5]) / 3.0;
+        if (p1 == 0.0) {
+            *lo = fmin(a[0], fmin(a[3], a[5]));
+            *hi = fmax(a[0], fmax(a[3], a[5]));
+            return;
+        }
+        const double p2 = (a[0] - q) * (a[0] - q) + (a[3] - q) * (a[3] - q) + (a[5] - q) * (a[5] - q) + 2.0 * p1;
+        const double p = sqrt(p2 / 6.0);
+        const double b00 = (a[0] - q) / p, b11 = (a[3] - q) / p, b22 = (a[5] - q) / p;
+        const double b01 = a[1] / p, b02 = a[2] / p, b12 = a[4] / p;
+        const double detb = b00 * (b11 * b22 - b12 * b12) - b01 * (b01 * b22 - b12 * b02) + b02 * (b01 * b12 - b11 * b02);
+        double rr = 0.5 * detb;
+        rr = fmin(1.0, fmax(-1.0, rr));
+        const double phi = acos(rr) / 3.0;
+        const double e1 = q + 2.0 * p * cos(phi);
+        const double e3 = q + 2.0 * p * cos(phi + 2.0943951023931954923);
+        *hi = e1;
+        *lo = e3;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_eig_bounds(int kind, const double* coef, long long npts, double* partials)
+{
+    __shared__ double rlo[kThreads], rhi[kThreads];
+    double lo = 1e300, hi = -1e300;
+    for (long long pt = (long long)blockIdx.x * blockDim.x + threadIdx.x; pt < npts; pt += (long long)gridDim.x * blockDim.x) {
+        double l, h;
+        if (kind == AK_ISO) {
+            l = h = coef[pt];
+        } else {
+            double a[6];
+            for (int q = 0; q < ncoef_of<D>(); q++) a[q] = coef[q * npts + pt];
+            sym_eigs<D>(a, &l, &h);
+        }
+        if (!(l == l) || !(h == h)) { l = -1e300; h = 1e300; }  // NaN poisons both bounds
+        lo = fmin(lo, l);
+        hi = fmax(hi, h);
+    }
+    rlo[threadIdx.x] = lo;
+    rhi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            rlo[threadIdx.x] = fmin(rlo[threadIdx.x], rlo[threadIdx.x + s]);
+            rhi[threadIdx.x] = fmax(rhi[threadIdx.x], rhi[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = rlo[0];
+        partials[2 * blockIdx.x + 1] = rhi[0];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_minmax(const double* partials, int n, double* out)
+{
+    __shared__ double rlo[kThreads], rhi[kThreads];
+    double lo = 1e300, hi = -1e300;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        lo = fmin(lo, partials[2 * i]);
+        hi = fmax(hi, partials[2 * i + 1]);
+    }
+    rlo[threadIdx.x] = lo;
+    rhi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            rlo[threadIdx.x] = fmin(rlo[threadIdx.x], rlo[threadIdx.x + s]);
+            rhi[threadIdx.x] = fmax(rhi[threadIdx.x], rhi[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = rlo[0];
+        out[1] = rhi[0];
+    }
+}
+
+// Which phases occur: block-local OR in LDS, then one atomic OR per block.
+__global__ __launch_bounds__(kThreads) void k_phase_mask(const uint8_t* phase, long long npts, unsigned* mask)
+{
+    __shared__ unsigned m;
+    if (threadIdx.x == 0) m = 0u;
+    __syncthreads();
+    unsigned loc = 0u;
+    for (long long pt = (long long)blockIdx.x * blockDim.x + threadIdx.x; pt < npts; pt += (long long)gridDim.x * blockDim.x)
+        loc |= (phase[pt] < 32) ? (1u << phase[pt]) : 0x80000000u;
+    atomicOr(&m, loc);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicOr(mask, m);
+}
+
+// Ga assembly, step 1: one real coefficient component on the N grid -> complex buffer.
+__global__ void k_coef_component(long long n, int kind, const double* coef, int comp, const uint8_t* phase,
+                                 double pv0, double pv1, double pv2, double pv3, double pv4, double pv5,
+                                 double pv6, double pv7, double pv8, double pv9, double pv10, double pv11,
+                                 double pv12, double pv13, double pv14, double pv15, double2* out)
+{
+    const double pv[16] = {pv0, pv1, pv2, pv3, pv4, pv5, pv6, pv7, pv8, pv9, pv10, pv11, pv12, pv13, pv14, pv15};
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        double v;
+        if (kind == AK_PHASE)
+            v = pv[phase[i] & 15];
+        else if (kind == AK_ISO)
+            v = coef[i];
+        else
+            v = coef[comp * n + i];
+        out[i] = make_double2(v, 0.0);
+    }
+}
+
+// Direct DFT along one axis of a complex grid (set-up only): out[.., k, ..] =
+// scale * sum_j in[.., j, ..] w^(j k), w = exp(sign 2 pi i / n) from the table.
+__global__ void k_dft_axis(const double2* __restrict__ in, double2* __restrict__ out, long long total, int n,
+                           long long stride, const double2* __restrict__ tw, int sign, double scale)
+{
+    for (long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x; o < total; o += (long long)gridDim.x * blockDim.x) {
+        const long long inner = o % stride;
+        const long long k = (o / stride) % n;
+        const long long outer = o / (stride * n);
+        const double2* src = in + outer * n * stride + inner;
+        double sr = 0.0, si = 0.0;
+        long long m = 0;
+        for (int j = 0; j < n; j++) {
+            const double2 w = tw[m];
+            const double wi = sign < 0 ? w.y : -w.y;
+            const double2 v = src[j * stride];
+            sr += v.x * w.x - v.y * wi;
+            si += v.x * wi + v.y * w.x;
+            m += k;
+            if (m >= n) m -= n;
+        }
+        out[o] = make_double2(scale * sr, scale * si);
+    }
+}
+
+// Ga assembly, step 2: spectrum on the N grid -> exact pixel Fourier coefficients at the
+// frequencies of the double grid (periodic extension times the sinc weights).
+__global__ void k_ga_extend(const double2* __restrict__ cn, double2* __restrict__ cm, int d, int N0, int N1, int N2,
+                            int M0, int M1, int M2, const double* s0, const double* s1, const double* s2)
+{
+    const long long nM = (long long)M0 * M1 * (d == 3 ? M2 : 1);
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < nM; q += (long long)gridDim.x * blockDim.x) {
+        int i[3];
+        long long t = q;
+        if (d == 3) {
+            i[2] = t % M2;
+            t /= M2;
+        }
+        i[1] = t % M1;
+        i[0] = t / M1;
+        const int Ns[3] = {N0, N1, N2}, Ms[3] = {M0, M1, M2};
+        const double* sw[3] = {s0, s1, s2};
+        double w = 1.0;
+        long long src = 0;
+        for (int a = 0; a < d; a++) {
+            const int nf = signed_index(i[a], Ms[a]);
+            const int r = ((nf % Ns[a]) + Ns[a]) % Ns[a];
+            src = src * Ns[a] + r;
+            w *= sw[a][i[a]];
+        }
+        const double2 v = cn[src];
+        cm[q] = make_double2(w * v.x, w * v.y);
+    }
+}
+
+__global__ void k_real_part(long long n, const double2* __restrict__ c, double* __restrict__ out)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = c[i].x;
+}
+
+// ==========================================================================================
+// Host launch wrappers.
+// ==========================================================================================
+__global__ void k_set_scalar(double* dst, double v) { *dst = v; }
+
+// Allow dynamic LDS above 64 KB for a kernel (gfx950 has 160 KB per compute unit).
+static hipError_t allow_lds(const void* fn, size_t bytes)
+{
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+#define LAUNCH_LDS(KERNEL, GRID, LDS, STREAM, ...)                                              \
+    do {                                                                                        \
+        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&KERNEL), (LDS));               \
+        if (e_ != hipSuccess) return e_;                                                        \
+        hipLaunchKernelGGL(KERNEL, GRID, dim3(kThreads), (LDS), (STREAM), __VA_ARGS__);          \
+    } while (0)
+static inline unsigned grid_for(long long n, int per = kThreads, int cap = 4096)
+{
+    long long b = (n + per - 1) / per;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+int vec_blocks() { return kVecBlocks; }
+
+template <typename T, int D, int AK>
+static hipError_t launch_first_ak(const OpPlan& op, const FirstArgs<T>& fa, int opc, unsigned nblk)
+{
+    const size_t lds = op.lds_first;
+    switch (opc) {
+        case OP_AX: LAUNCH_LDS((k_first<T, D, AK, OP_AX>), dim3(nblk), lds, op.stream, fa); break;
+        case OP_E: LAUNCH_LDS((k_first<T, D, AK, OP_E>), dim3(nblk), lds, op.stream, fa); break;
+        case OP_EM: LAUNCH_LDS((k_first<T, D, AK, OP_EM>), dim3(nblk), lds, op.stream, fa); break;
+        case OP_ID: LAUNCH_LDS((k_first<T, D, AK, OP_ID>), dim3(nblk), lds, op.stream, fa); break;
+        case OP_AP_CG: LAUNCH_LDS((k_first<T, D, AK, OP_AP_CG>), dim3(nblk), lds, op.stream, fa); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int D, int AK>
+static hipError_t launch_last_ak(const OpPlan& op, const LastArgs<T>& la, int epi, unsigned nblk)
+{
+    const size_t lds = op.lds_first;
+    switch (epi) {
+        case EPI_STORE: LAUNCH_LDS((k_last<T, D, AK, EPI_STORE>), dim3(nblk), lds, op.stream, la); break;
+        case EPI_RICH: LAUNCH_LDS((k_last<T, D, AK, EPI_RICH>), dim3(nblk), lds, op.stream, la); break;
+        case EPI_CG: LAUNCH_LDS((k_last<T, D, AK, EPI_CG>), dim3(nblk), lds, op.stream, la); break;
+        case EPI_CHEB: LAUNCH_LDS((k_last<T, D, AK, EPI_CHEB>), dim3(nblk), lds, op.stream, la); break;
+        case EPI_EM: LAUNCH_LDS((k_last<T, D, AK, EPI_EM>), dim3(nblk), lds, op.stream, la); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int D>
+static hipError_t launch_first(const OpPlan& op, const FirstArgs<T>& fa, int opc, unsigned nblk)
+{
+    switch (op.A.kind) {
+        case AK_SYM: return launch_first_ak<T, D, AK_SYM>(op, fa, opc, nblk);
+        case AK_ISO: return launch_first_ak<T, D, AK_ISO>(op, fa, opc, nblk);
+        case AK_PHASE: return launch_first_ak<T, D, AK_PHASE>(op, fa, opc, nblk);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int D>
+static hipError_t launch_last(const OpPlan& op, const LastArgs<T>& la, int epi, unsigned nblk)
+{
+    switch (op.A.kind) {
+        case AK_SYM: return launch_last_ak<T, D, AK_SYM>(op, la, epi, nblk);
+        case AK_ISO: return launch_last_ak<T, D, AK_ISO>(op, la, epi, nblk);
+        case AK_PHASE: return launch_last_ak<T, D, AK_PHASE>(op, la, epi, nblk);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int D>
+static hipError_t launch_middle(const OpPlan& op, const MidArgs<T>& ma, int mult)
+{
+    const size_t lds = op.lds_mid;
+    if (mult == MULT_G)
+        LAUNCH_LDS((k_middle<T, D, MULT_G>), dim3(ma.ntiles), lds, op.stream, ma);
+    else
+        LAUNCH_LDS((k_middle<T, D, MULT_EM>), dim3(ma.ntiles), lds, op.stream, ma);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_axis(const OpPlan& op, const AxisArgs<T>& xa, bool inv, int outer)
+{
+    dim3 grid(xa.ntiles, outer, op.g.d);
+    if (inv)
+        LAUNCH_LDS((k_axis<T, true>), grid, op.lds_axis, op.stream, xa);
+    else
+        LAUNCH_LDS((k_axis<T, false>), grid, op.lds_axis, op.stream, xa);
+    return hipGetLastError();
+}
+
+template <typename T, int D>
+static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_last)
+{
+    const Geo& g = op.g;
+    const int last = D - 1;
+    hipError_t e;
+    const unsigned nblk = (unsigned)((g.rows + op.rpb - 1) / op.rpb);
+    cpx<T>* SA = static_cast<cpx<T>*>(op.SA);
+    cpx<T>* SB = static_cast<cpx<T>*>(op.SB);
+
+    FirstArgs<T> fa;
+    fa.g = g;
+    fa.ax = op.ax[last];
+    fa.rpb = op.rpb;
+    fa.npen = op.npen;
+    fa.x = static_cast<const T*>(a.x);
+    fa.p = static_cast<T*>(a.p_cg);
+    fa.r = static_cast<const T*>(a.r_cg);
+    fa.sc = op.sc;
+    for (int c = 0; c < 3; c++) fa.E[c] = a.E[c];
+    fa.omega = a.omega;
+    fa.A = op.A;
+    fa.out = SA;
+    fa.twg = static_cast<const cpx<T>*>(op.tw[last]);
+    if ((e = launch_first<T, D>(op, fa, a.op, nblk)) != hipSuccess) return e;
+
+    cpx<T>* mid = SA;
+    if (D == 3) {
+        AxisArgs<T> xa;
+        xa.ax = op.ax[1];
+        xa.nin = g.L[1];
+        xa.nout = g.B[1];
+        xa.bin = 0;
+        xa.bout = 1;
+        xa.inner = g.Hb;
+        xa.P = op.P_axis;
+        xa.ntiles = (g.Hb + op.P_axis - 1) / op.P_axis;
+        xa.in_os = (long long)g.L[1] * g.Hb;
+        xa.out_os = (long long)g.B[1] * g.Hb;
+        xa.in_cs = g.s1;
+        xa.out_cs = g.s2;
+        xa.in = SA;
+        xa.out = SB;
+        xa.twg = static_cast<const cpx<T>*>(op.tw[1]);
+        if ((e = launch_axis<T>(op, xa, false, g.L[0])) != hipSuccess) return e;
+        mid = SB;
+    }
+
+    MidArgs<T> ma;
+    ma.ax = op.ax[0];
+    ma.B0 = g.B[0];
+    ma.cols = g.cols_mid;
+    ma.Hb = g.Hb;
+    ma.B1 = g.B[1];
+    ma.P = op.P_mid;
+    ma.ntiles = (g.cols_mid + op.P_mid - 1) / op.P_mid;
+    ma.cs = (long long)g.L[0] * g.cols_mid;
+    ma.scale = 1.0 / (double)g.npts;
+    ma.buf = mid;
+    ma.twg = static_cast<const cpx<T>*>(op.tw[0]);
+    if ((e = launch_middle<T, D>(op, ma, a.mult)) != hipSuccess) return e;
+
+    if (D == 3) {
+        AxisArgs<T> xa;
+        xa.ax = op.ax[1];
+        xa.nin = g.B[1];
+        xa.nout = g.L[1];
+        xa.bin = 1;
+        xa.bout = 0;
+        xa.inner = g.Hb;
+        xa.P = op.P_axis;
+        xa.ntiles = (g.Hb + op.P_axis - 1) / op.P_axis;
+        xa.in_os = (long long)g.B[1] * g.Hb;
+        xa.out_os = (long long)g.L[1] * g.Hb;
+        xa.in_cs = g.s2;
+        xa.out_cs = g.s1;
+        xa.in = SB;
+        xa.out = SA;
+        xa.twg = static_cast<const cpx<T>*>(op.tw[1]);
+        if ((e = launch_axis<T>(op, xa, true, g.L[0])) != hipSuccess) return e;
+    }
+
+    LastArgs<T> la;
+    la.g = g;
+    la.ax = op.ax[last];
+    la.rpb = op.rpb;
+    la.npen = op.npen;
+    la.in = SA;
+    la.y = static_cast<T*>(a.y);
+    la.x = static_cast<T*>(a.ex);
+    la.r = static_cast<T*>(a.er);
+    la.p = static_cast<T*>(a.ep);
+    la.q = static_cast<T*>(a.eq);
+    la.src = static_cast<const T*>(a.src);
+    for (int c = 0; c < 3; c++) la.E[c] = a.E[c];
+    la.omega = a.omega;
+    la.alpha = a.alpha;
+    la.beta = a.beta;
+    la.sgn = a.sgn;
+    la.A = op.A;
+    la.partials = op.partials;
+    la.twg = static_cast<const cpx<T>*>(op.tw[last]);
+    if ((e = launch_last<T, D>(op, la, a.epi, nblk)) != hipSuccess) return e;
+    if (nblocks_last) *nblocks_last = (int)nblk;
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t run_apply(const OpPlan& op, const ApplyArgs& a, int* nblocks_last)
+{
+    if (op.g.d == 2) return apply_d<T, 2>(op, a, nblocks_last);
+    return apply_d<T, 3>(op, a, nblocks_last);
+}
+template hipError_t run_apply<float>(const OpPlan&, const ApplyArgs&, int*);
+template hipError_t run_apply<double>(const OpPlan&, const ApplyArgs&, int*);
+
+hipError_t run_set_scalar(const OpPlan& op, double* dst, double v)
+{
+    hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, op.stream, dst, v);
+    return hipGetLastError();
+}
+
+hipError_t run_reduce_async(const OpPlan& op, int n, int redop)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, op.stream, op.partials, n, op.sc, redop);
+    return hipGetLastError();
+}
+
+hipError_t run_reduce(const OpPlan& op, int n, int redop, double* host_out)
+{
+    hipError_t e = run_reduce_async(op, n, redop);
+    if (e != hipSuccess) return e;
+    if (!host_out) return hipSuccess;
+    e = hipMemcpyAsync(host_out, &op.sc->total, sizeof(double), hipMemcpyDeviceToHost, op.stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(op.stream);
+}
+
+template <typename T>
+hipError_t run_cg_update(const OpPlan& op, long long n, T* x, T* r, const T* p, const T* q)
+{
+    hipLaunchKernelGGL(k_cg_update<T>, dim3(kVecBlocks), dim3(kThreads), 0, op.stream, n, x, r, p, q, op.sc, op.partials);
+    return hipGetLastError();
+}
+template hipError_t run_cg_update<float>(const OpPlan&, long long, float*, float*, const float*, const float*);
+template hipError_t run_cg_update<double>(const OpPlan&, long long, double*, double*, const double*, const double*);
+
+template <typename T>
+hipError_t run_cg_p(const OpPlan& op, long long n, T* p, const T* r)
+{
+    hipLaunchKernelGGL(k_cg_p<T>, dim3(kVecBlocks), dim3(kThreads), 0, op.stream, n, p, r, op.sc);
+    return hipGetLastError();
+}
+template hipError_t run_cg_p<float>(const OpPlan&, long long, float*, const float*);
+template hipError_t run_cg_p<double>(const OpPlan&, long long, double*, const double*);
+
+template <typename T>
+hipError_t run_fill(hipStream_t s, long long n, T* x, T v)
+{
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, x, v);
+    return hipGetLastError();
+}
+template hipError_t run_fill<float>(hipStream_t, long long, float*, float);
+template hipError_t run_fill<double>(hipStream_t, long long, double*, double);
+template hipError_t run_fill<unsigned>(hipStream_t, long long, unsigned*, unsigned);
+
+template <typename T>
+hipError_t run_fill_field(hipStream_t s, int d, long long npts, T* x, const double* v)
+{
+    hipLaunchKernelGGL(k_fill_field<T>, dim3(grid_for(d * npts)), dim3(kThreads), 0, s, d, npts, x, v[0], v[1],
+                       d == 3 ? v[2] : 0.0);
+    return hipGetLastError();
+}
+template hipError_t run_fill_field<float>(hipStream_t, int, long long, float*, const double*);
+template hipError_t run_fill_field<double>(hipStream_t, int, long long, double*, const double*);
+
+template <typename T>
+hipError_t run_copy(hipStream_t s, long long n, T* dst, const T* src)
+{
+    hipLaunchKernelGGL(k_copy<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, dst, src);
+    return hipGetLastError();
+}
+template hipError_t run_copy<float>(hipStream_t, long long, float*, const float*);
+template hipError_t run_copy<double>(hipStream_t, long long, double*, const double*);
+
+hipError_t run_f64_to_f32(hipStream_t s, long long n, float* dst, const double* src)
+{
+    hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(n)), dim3(kThreads), 0, s, n, dst, src);
+    return hipGetLastError();
+}
+
+hipError_t run_add_f32_to_f64(hipStream_t s, long long n, double* x, const float* d)
+{
+    hipLaunchKernelGGL(k_add_f32_to_f64, dim3(grid_for(n)), dim3(kThreads), 0, s, n, x, d);
+    return hipGetLastError();
+}
+
+hipError_t run_axpby(hipStream_t s, long long n, double* y, double a, const double* x, double b)
+{
+    hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(kThreads), 0, s, n, y, a, x, b);
+    return hipGetLastError();
+}
+
+hipError_t run_add_f64(hipStream_t s, long long n, double* x, const double* d)
+{
+    hipLaunchKernelGGL(k_add_f64, dim3(grid_for(n)), dim3(kThreads), 0, s, n, x, d);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t run_dot(const OpPlan& op, long long n, const T* a, const T* b, int* nblocks)
+{
+    hipLaunchKernelGGL(k_dot<T>, dim3(kVecBlocks), dim3(kThreads), 0, op.stream, n, a, b, op.partials);
+    *nblocks = kVecBlocks;
+    return hipGetLastError();
+}
+template hipError_t run_dot<float>(const OpPlan&, long long, const float*, const float*, int*);
+template hipError_t run_dot<double>(const OpPlan&, long long, const double*, const double*, int*);
+
+hipError_t run_norm_AE(const OpPlan& op, const double* E, int* nblocks)
+{
+    const long long n = op.g.npts;
+    const int d = op.g.d;
+    const int k = op.A.kind;
+#define NAE(DD, KK) hipLaunchKernelGGL((k_norm_AE<DD, KK>), dim3(kVecBlocks), dim3(kThreads), 0, op.stream, n, op.A, E[0], E[1], d == 3 ? E[2] : 0.0, op.partials)
+    if (d == 2) {
+        if (k == AK_SYM) NAE(2, AK_SYM); else if (k == AK_ISO) NAE(2, AK_ISO); else NAE(2, AK_PHASE);
+    } else {
+        if (k == AK_SYM) NAE(3, AK_SYM); else if (k == AK_ISO) NAE(3, AK_ISO); else NAE(3, AK_PHASE);
+    }
+#undef NAE
+    *nblocks = kVecBlocks;
+    return hipGetLastError();
+}
+
+hipError_t run_effective(const OpPlan& op, int nrhs, const double* E, const double* e, int* nblocks)
+{
+    const long long n = op.g.npts;
+    const int d = op.g.d;
+    const int k = op.A.kind;
+    const int nb = 512;
+#define EFF(DD, KK) hipLaunchKernelGGL((k_effective<DD, KK>), dim3(nb), dim3(kThreads), 0, op.stream, n, op.A, nrhs, E, e, op.partials)
+    if (d == 2) {
+        if (k == AK_SYM) EFF(2, AK_SYM); else if (k == AK_ISO) EFF(2, AK_ISO); else EFF(2, AK_PHASE);
+    } else {
+        if (k == AK_SYM) EFF(3, AK_SYM); else if (k == AK_ISO) EFF(3, AK_ISO); else EFF(3, AK_PHASE);
+    }
+#undef EFF
+    *nblocks = nb;
+    return hipGetLastError();
+}
+
+hipError_t run_reduce_multi(const OpPlan& op, int nblocks, int nvals, double* host_out)
+{
+    double* dev_out = op.sc->aux + 16;
+    hipLaunchKernelGGL(k_reduce_multi, dim3(1), dim3(kThreads), 0, op.stream, op.partials, nblocks, nvals, dev_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(host_out, dev_out, sizeof(double) * nvals, hipMemcpyDeviceToHost, op.stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(op.stream);
+}
+
+hipError_t run_to_f32(hipStream_t s, long long n, float* dst, const double* src)
+{
+    hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(kThreads), 0, s, n, dst, src);
+    return hipGetLastError();
+}
+
+hipError_t run_eig_bounds(hipStream_t s, int d, int kind, const double* coef, long long npts, double* partials,
+                          int* nblocks)
+{
+    const unsigned nb = grid_for(npts, kThreads, 1024);
+    if (d == 2)
+        hipLaunchKernelGGL(k_eig_bounds<2>, dim3(nb), dim3(kThreads), 0, s, kind, coef, npts, partials);
+    else
+        hipLaunchKernelGGL(k_eig_bounds<3>, dim3(nb), dim3(kThreads), 0, s, kind, coef, npts, partials);
+    *nblocks = (int)nb;
+    return hipGetLastError();
+}
+
+hipError_t run_minmax_reduce(hipStream_t s, const double* partials, int nblocks, double* host_lo_hi)
+{
+    double* dev = const_cast<double*>(partials) + 2 * nblocks;
+    hipLaunchKernelGGL(k_minmax, dim3(1), dim3(kThreads), 0, s, partials, nblocks, dev);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(host_lo_hi, dev, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+hipError_t run_phase_mask(hipStream_t s, const uint8_t* phase, long long npts, unsigned* mask)
+{
+    hipLaunchKernelGGL(k_phase_mask, dim3(grid_for(npts, kThreads, 1024)), dim3(kThreads), 0, s, phase, npts, mask);
+    return hipGetLastError();
+}
+
+hipError_t run_ga_component(hipStream_t s, const GaAsm& ga, int kind, const double* coef, int comp,
+                            const uint8_t* phase, const double* pv, int nphase, double* out)
+{
+    double v[16] = {0};
+    for (int i = 0; i < nphase && i < 16; i++) v[i] = pv[i];
+    hipLaunchKernelGGL(k_coef_component, dim3(grid_for(ga.nN)), dim3(kThreads), 0, s, ga.nN, kind, coef, comp, phase,
+                       v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], v[9], v[10], v[11], v[12], v[13], v[14],
+                       v[15], ga.c0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // forward DFT on the N grid (with 1/|N|), axis by axis, ping-pong c0 <-> c1
+    double2* src = ga.c0;
+    double2* dst = ga.c1;
+    for (int a = 0; a < ga.d; a++) {
+        long long stride = 1;
+        for (int b = a + 1; b < ga.d; b++) stride *= ga.N[b];
+        const double scale = (a == 0) ? 1.0 / (double)ga.nN : 1.0;
+        hipLaunchKernelGGL(k_dft_axis, dim3(grid_for(ga.nN)), dim3(kThreads), 0, s, src, dst, ga.nN, ga.N[a], stride,
+                           ga.twN[a], -1, scale);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        double2* t = src;
+        src = dst;
+        dst = t;
+    }
+    // periodic extension with sinc weights onto the double-grid frequencies
+    hipLaunchKernelGGL(k_ga_extend, dim3(grid_for(ga.nM)), dim3(kThreads), 0, s, src, dst, ga.d, ga.N[0], ga.N[1],
+                       ga.d == 3 ? ga.N[2] : 1, ga.M[0], ga.M[1], ga.d == 3 ? ga.M[2] : 1, ga.sinc[0], ga.sinc[1],
+                       ga.d == 3 ? ga.sinc[2] : ga.sinc[1]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    {
+        double2* t = src;
+        src = dst;
+        dst = t;
+    }
+    for (int a = 0; a < ga.d; a++) {
+        long long stride = 1;
+        for (int b = a + 1; b < ga.d; b++) stride *= ga.M[b];
+        hipLaunchKernelGGL(k_dft_axis, dim3(grid_for(ga.nM)), dim3(kThreads), 0, s, src, dst, ga.nM, ga.M[a], stride,
+                           ga.twM[a], +1, 1.0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        double2* t = src;
+        src = dst;
+        dst = t;
+    }
+    hipLaunchKernelGGL(k_real_part, dim3(grid_for(ga.nM)), dim3(kThreads), 0, s, ga.nM, src, out);
+    return hipGetLastError();
+}
+
+}  // namespace fgh

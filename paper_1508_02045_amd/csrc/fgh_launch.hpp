@@ -1,0 +1,96 @@
+// fgh_launch.hpp -- host-side launch wrappers of the libfgh kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fgh_internal.hpp"
+
+namespace fgh {
+
+// Everything one operator application needs (one precision).
+struct OpPlan {
+    Geo g;
+    Axis ax[3];              // FFT descriptor per axis (length L[a])
+    const void* tw[3];       // device twiddle table per axis (element type of the pass)
+    void* SA;                // spectrum buffers (complex, element type of the pass)
+    void* SB;
+    CoefArgs A;              // coefficients as seen by the passes
+    int rpb, npen;           // first/last passes: rows per block, complex pencils per block
+    int P_axis, P_mid;       // axis / middle passes: tile width
+    size_t lds_first, lds_axis, lds_mid;
+    double* partials;        // one double per block of the last pass (and of vector kernels)
+    Scalars* sc;
+    hipStream_t stream;
+};
+
+// Parameters of one application: what the first pass reads, the multiplier, the epilogue.
+struct ApplyArgs {
+    int op = OP_AX;          // FirstOp
+    int mult = MULT_G;       // Mult
+    int epi = EPI_STORE;     // Epi
+    const void* x = nullptr; // first-pass input vector ([d][npts])
+    void* p_cg = nullptr;    // OP_AP_CG: p (updated in place)
+    const void* r_cg = nullptr;
+    double E[3] = {0, 0, 0};
+    double omega = 0.0;      // Eyre-Milton omega, Richardson omega
+    double alpha = 0.0, beta = 0.0, sgn = 1.0;
+    void* y = nullptr;       // EPI_STORE output
+    void* ex = nullptr;      // epilogue vectors
+    void* er = nullptr;
+    void* ep = nullptr;
+    void* eq = nullptr;
+    const void* src = nullptr; // EPI_EM: additive source field (refinement); nullptr: 2 w E
+};
+
+template <typename T>
+hipError_t run_apply(const OpPlan& op, const ApplyArgs& a, int* nblocks_last);
+
+hipError_t run_reduce(const OpPlan& op, int n, int redop, double* host_out);
+hipError_t run_reduce_async(const OpPlan& op, int n, int redop);
+hipError_t run_set_scalar(const OpPlan& op, double* dst, double v);
+
+int vec_blocks();
+template <typename T>
+hipError_t run_cg_update(const OpPlan& op, long long n, T* x, T* r, const T* p, const T* q);
+template <typename T>
+hipError_t run_cg_p(const OpPlan& op, long long n, T* p, const T* r);
+template <typename T>
+hipError_t run_fill(hipStream_t s, long long n, T* x, T v);
+template <typename T>
+hipError_t run_fill_field(hipStream_t s, int d, long long npts, T* x, const double* v);
+template <typename T>
+hipError_t run_copy(hipStream_t s, long long n, T* dst, const T* src);
+hipError_t run_f64_to_f32(hipStream_t s, long long n, float* dst, const double* src);
+hipError_t run_add_f32_to_f64(hipStream_t s, long long n, double* x, const float* d);
+hipError_t run_add_f64(hipStream_t s, long long n, double* x, const double* d);
+hipError_t run_axpby(hipStream_t s, long long n, double* y, double a, const double* x, double b);
+hipError_t run_norm_AE(const OpPlan& op, const double* E, int* nblocks);
+template <typename T>
+hipError_t run_dot(const OpPlan& op, long long n, const T* a, const T* b, int* nblocks);
+
+// Effective quantities: partials [nblocks][nrhs*nrhs + nrhs*d].
+hipError_t run_effective(const OpPlan& op, int nrhs, const double* E, const double* e, int* nblocks);
+hipError_t run_reduce_multi(const OpPlan& op, int nblocks, int nvals, double* host_out);
+
+// Coefficient preparation.
+hipError_t run_to_f32(hipStream_t s, long long n, float* dst, const double* src);
+hipError_t run_eig_bounds(hipStream_t s, int d, int kind, const double* coef, long long npts,
+                          double* partials, int* nblocks);
+hipError_t run_minmax_reduce(hipStream_t s, const double* partials, int nblocks, double* host_lo_hi);
+hipError_t run_phase_mask(hipStream_t s, const uint8_t* phase, long long npts, unsigned* mask);
+
+// Ga coefficients on the double grid from a pixel-wise constant field on the N grid.
+struct GaAsm {
+    int d;
+    int N[3], M[3];
+    long long nN, nM;
+    const double2* twN[3];   // exp(-2 pi i m / N_a)
+    const double2* twM[3];   // exp(-2 pi i m / M_a)
+    const double* sinc[3];   // sinc(n / N_a) for the M_a positions of axis a
+    double2* c0;             // scratch complex buffers, |M| elements each
+    double2* c1;
+};
+hipError_t run_ga_component(hipStream_t s, const GaAsm& ga, int kind, const double* coef, int comp,
+                            const uint8_t* phase, const double* phase_vals, int nphase,
+                            double* out /* [nM] */);
+
+}  // namespace fgh

@@ -1,0 +1,280 @@
+"""Thin ctypes binding of libfgh (include/fgh.h).
+
+Every step of the computation runs in the HIP library; this module only marshals arguments.
+PyTorch provides device memory and the stream.  The functions keep the C names; ``Plan`` is a
+small convenience owner of the workspace and of the tensors a plan points to.
+
+The library must have been built (``python -m paper_1508_02045_amd.build``); importing this
+module on a machine without it raises immediately: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfgh.so")
+
+FGH_OK = 0
+FGH_E_INVALID = 1
+FGH_E_NOT_SPD = 2
+FGH_E_UNSUPPORTED = 3
+FGH_E_WORKSPACE = 4
+FGH_E_NO_CONVERGENCE = 5
+FGH_E_DIVERGED = 6
+FGH_E_DEVICE = 7
+
+FGH_GANI, FGH_GA = 0, 1
+FGH_RICHARDSON, FGH_CG, FGH_CHEBYSHEV, FGH_EYRE_MILTON = 0, 1, 2, 3
+FGH_FP64, FGH_FP32_REFINED = 0, 1
+FGH_A_SYM, FGH_A_ISO, FGH_A_PHASE = 0, 1, 2
+
+SOLVERS = {"richardson": FGH_RICHARDSON, "cg": FGH_CG, "chebyshev": FGH_CHEBYSHEV,
+           "eyre_milton": FGH_EYRE_MILTON}
+
+EXPORTS = ["fgh_plan_workspace", "fgh_plan_create", "fgh_plan_destroy", "fgh_plan_grid_points",
+           "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32", "fgh_ga_coefficients", "fgh_solve",
+           "fgh_solve_fixed", "fgh_effective", "fgh_status_string"]
+
+
+class FghError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
+                ("fp64_applies", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("rel_res_recursive", ctypes.c_double), ("rel_res_true", ctypes.c_double),
+                ("c_A", ctypes.c_double), ("C_A", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib():
+    """Load libfgh.so (raises if it is missing: the HIP path is the only path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libfgh.so not built at {LIB_PATH}; run python -m paper_1508_02045_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        L.fgh_plan_workspace.argtypes = [ctypes.c_int, _i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_size_t)]
+        L.fgh_plan_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _i32p, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, _vp, _vp, _dp, ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_double, _vp, ctypes.c_size_t, _vp]
+        L.fgh_plan_destroy.argtypes = [_vp]
+        L.fgh_plan_destroy.restype = None
+        L.fgh_plan_grid_points.argtypes = [_vp]
+        L.fgh_plan_grid_points.restype = ctypes.c_int64
+        L.fgh_plan_bounds.argtypes = [_vp, _dp, _dp]
+        L.fgh_apply.argtypes = [_vp, _vp, _vp]
+        L.fgh_apply_f32.argtypes = [_vp, _vp, _vp]
+        L.fgh_ga_coefficients.argtypes = [_vp, _vp]
+        L.fgh_solve.argtypes = [_vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _vp,
+                                ctypes.POINTER(Stats)]
+        L.fgh_solve_fixed.argtypes = [_vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _vp,
+                                      ctypes.POINTER(Stats)]
+        L.fgh_effective.argtypes = [_vp, _dp, ctypes.c_int, _vp, _dp, _dp]
+        L.fgh_status_string.argtypes = [ctypes.c_int]
+        L.fgh_status_string.restype = ctypes.c_char_p
+        for name in ("fgh_plan_workspace", "fgh_plan_create", "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32",
+                     "fgh_ga_coefficients", "fgh_solve", "fgh_solve_fixed", "fgh_effective"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().fgh_status_string(int(status)).decode()
+
+
+def _n32(N):
+    return (ctypes.c_int32 * len(N))(*[int(n) for n in N])
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _hostd(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+# ----------------------------------------------------------------------------- C-name wrappers
+def fgh_plan_workspace(d: int, N: Sequence[int], rule: int, precision: int, a_kind: int) -> int:
+    out = ctypes.c_size_t()
+    st = lib().fgh_plan_workspace(d, _n32(N), rule, precision, a_kind, ctypes.byref(out))
+    if st:
+        raise FghError(st, "fgh_plan_workspace")
+    return out.value
+
+
+def fgh_plan_create(d, N, rule, precision, a_kind, A, phase, phase_table, n_phases, c_A, C_A, workspace,
+                    workspace_bytes, stream) -> int:
+    h = ctypes.c_void_p()
+    tab_keep = None
+    tab_ptr = None
+    if phase_table is not None:
+        tab_keep, tab_ptr = _hostd(phase_table)
+    st = lib().fgh_plan_create(ctypes.byref(h), d, _n32(N), rule, precision, a_kind, _ptr(A), _ptr(phase),
+                               tab_ptr, int(n_phases), float(c_A), float(C_A), _ptr(workspace),
+                               int(workspace_bytes), ctypes.c_void_p(stream))
+    del tab_keep
+    if st:
+        raise FghError(st, "fgh_plan_create")
+    return h.value
+
+
+def fgh_plan_destroy(plan) -> None:
+    lib().fgh_plan_destroy(ctypes.c_void_p(plan))
+
+
+def fgh_apply(plan, x, y) -> None:
+    st = lib().fgh_apply(ctypes.c_void_p(plan), _ptr(x), _ptr(y))
+    if st:
+        raise FghError(st, "fgh_apply")
+
+
+def fgh_apply_f32(plan, x, y) -> None:
+    st = lib().fgh_apply_f32(ctypes.c_void_p(plan), _ptr(x), _ptr(y))
+    if st:
+        raise FghError(st, "fgh_apply_f32")
+
+
+def fgh_solve(plan, solver, E, nrhs, tol, max_iter, e, raise_on=(FGH_E_INVALID, FGH_E_UNSUPPORTED, FGH_E_DEVICE,
+                                                               FGH_E_WORKSPACE, FGH_E_NOT_SPD)):
+    Ek, Ep = _hostd(E)
+    stats = (Stats * nrhs)()
+    st = lib().fgh_solve(ctypes.c_void_p(plan), int(solver), Ep, int(nrhs), float(tol), int(max_iter), _ptr(e), stats)
+    if st in raise_on:
+        raise FghError(st, "fgh_solve")
+    return st, [s.as_dict() for s in stats]
+
+
+def fgh_solve_fixed(plan, solver, E, nrhs, iters, e):
+    Ek, Ep = _hostd(E)
+    stats = (Stats * nrhs)()
+    st = lib().fgh_solve_fixed(ctypes.c_void_p(plan), int(solver), Ep, int(nrhs), int(iters), _ptr(e), stats)
+    if st in (FGH_E_INVALID, FGH_E_UNSUPPORTED, FGH_E_DEVICE):
+        raise FghError(st, "fgh_solve_fixed")
+    return st, [s.as_dict() for s in stats]
+
+
+def fgh_effective(plan, E, nrhs, e, d):
+    Ek, Ep = _hostd(E)
+    bil = np.zeros((nrhs, nrhs))
+    flux = np.zeros((nrhs, d))
+    st = lib().fgh_effective(ctypes.c_void_p(plan), Ep, int(nrhs), _ptr(e), bil.ctypes.data_as(_dp),
+                             flux.ctypes.data_as(_dp))
+    if st:
+        raise FghError(st, "fgh_effective")
+    return bil, flux
+
+
+# ----------------------------------------------------------------------------- convenience owner
+class Plan:
+    """Owns the workspace (a torch uint8 tensor on the device) and keeps A alive.
+
+    A: torch float64 device tensor [ncoef, *N] (FGH_A_SYM) or [*N] (FGH_A_ISO), or None with
+    phase (torch uint8 device tensor [*N]) and phase_table (numpy [n_phases, ncoef])."""
+
+    def __init__(self, N, rule=FGH_GANI, precision=FGH_FP64, A=None, phase=None, phase_table=None, a_kind=None,
+                 c_A=0.0, C_A=0.0, device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.N = tuple(int(n) for n in N)
+        self.d = len(self.N)
+        self.rule = rule
+        self.precision = precision
+        if a_kind is None:
+            a_kind = FGH_A_PHASE if phase is not None else (FGH_A_ISO if A.dim() == self.d else FGH_A_SYM)
+        self.a_kind = a_kind
+        self.A = A.contiguous() if A is not None else None
+        self.phase = phase.contiguous() if phase is not None else None
+        self.phase_table = None if phase_table is None else np.ascontiguousarray(phase_table, dtype=np.float64)
+        nbytes = fgh_plan_workspace(self.d, self.N, rule, precision, a_kind)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self._ws_view = self.workspace[off:off + nbytes]
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.handle = fgh_plan_create(self.d, self.N, rule, precision, a_kind, self.A, self.phase, self.phase_table,
+                                      0 if self.phase_table is None else self.phase_table.shape[0], c_A, C_A,
+                                      self._ws_view, nbytes, self.stream.cuda_stream)
+        self.grid = tuple(self.N) if rule == FGH_GANI else tuple(2 * n - 1 for n in self.N)
+        self.npts = int(np.prod(self.grid))
+
+    def bounds(self):
+        lo = ctypes.c_double()
+        hi = ctypes.c_double()
+        lib().fgh_plan_bounds(ctypes.c_void_p(self.handle), ctypes.byref(lo), ctypes.byref(hi))
+        return lo.value, hi.value
+
+    def field(self, nrhs=1, dtype=None):
+        t = self.torch
+        shape = (self.d,) + self.grid if nrhs == 1 else (nrhs, self.d) + self.grid
+        return t.zeros(shape, dtype=dtype or t.float64, device=self.workspace.device)
+
+    def apply(self, x, y=None):
+        if y is None:
+            y = self.torch.empty_like(x)
+        if x.dtype == self.torch.float32:
+            fgh_apply_f32(self.handle, x, y)
+        else:
+            fgh_apply(self.handle, x, y)
+        return y
+
+    def solve(self, solver, E, tol, max_iter=10000, e=None):
+        E = np.atleast_2d(np.asarray(E, dtype=np.float64))
+        nrhs = E.shape[0]
+        if e is None:
+            e = self.field(nrhs)
+        solver = SOLVERS.get(solver, solver)
+        st, stats = fgh_solve(self.handle, solver, E, nrhs, tol, max_iter, e)
+        return e, st, stats
+
+    def solve_fixed(self, solver, E, iters, e=None):
+        E = np.atleast_2d(np.asarray(E, dtype=np.float64))
+        nrhs = E.shape[0]
+        if e is None:
+            e = self.field(nrhs)
+        solver = SOLVERS.get(solver, solver)
+        st, stats = fgh_solve_fixed(self.handle, solver, E, nrhs, iters, e)
+        return e, st, stats
+
+    def effective(self, E, e):
+        E = np.atleast_2d(np.asarray(E, dtype=np.float64))
+        return fgh_effective(self.handle, E, E.shape[0], e, self.d)
+
+    def ga_coefficients(self):
+        ncoef = (3 if self.d == 2 else 6) if self.a_kind == FGH_A_SYM else 1
+        out = self.torch.empty((ncoef,) + self.grid, dtype=self.torch.float64, device=self.workspace.device)
+        st = lib().fgh_ga_coefficients(ctypes.c_void_p(self.handle), _ptr(out))
+        if st:
+            raise FghError(st, "fgh_ga_coefficients")
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fgh_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,77 @@
+"""The C-ABI library loads and exports every entry point include/fgh.h declares; host-side
+argument validation (no GPU work is issued by these calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fgh.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fgh_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1508_02045_amd import fgh
+    return fgh.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_binding_names_match_header():
+    from paper_1508_02045_amd import fgh
+    assert sorted(fgh.EXPORTS) == _declared()
+
+
+def test_status_strings(L):
+    from paper_1508_02045_amd import fgh
+    for s in range(8):
+        assert fgh.status_string(s)
+    assert "invalid" in fgh.status_string(fgh.FGH_E_INVALID)
+
+
+@pytest.mark.parametrize("d,N,ok", [(2, (63, 63), True), (3, (135, 135, 135), True), (2, (64, 63), False),
+                                    (3, (1, 3, 3), False), (4, (3, 3, 3, 3), False), (2, (3, 3), True)])
+def test_workspace_validation(d, N, ok):
+    from paper_1508_02045_amd import fgh
+    if ok:
+        b = fgh.fgh_plan_workspace(d, N, fgh.FGH_GANI, fgh.FGH_FP64, fgh.FGH_A_PHASE)
+        assert b > 0
+    else:
+        with pytest.raises(fgh.FghError) as ei:
+            fgh.fgh_plan_workspace(d, N, fgh.FGH_GANI, fgh.FGH_FP64, fgh.FGH_A_PHASE)
+        assert ei.value.status == fgh.FGH_E_INVALID
+
+
+def test_workspace_grows_with_double_grid_and_refinement():
+    from paper_1508_02045_amd import fgh
+    N = (63, 63, 63)
+    gani = fgh.fgh_plan_workspace(3, N, fgh.FGH_GANI, fgh.FGH_FP64, fgh.FGH_A_SYM)
+    ga = fgh.fgh_plan_workspace(3, N, fgh.FGH_GA, fgh.FGH_FP64, fgh.FGH_A_SYM)
+    ref = fgh.fgh_plan_workspace(3, N, fgh.FGH_GANI, fgh.FGH_FP32_REFINED, fgh.FGH_A_SYM)
+    assert ga > 4 * gani and ref > gani
+
+
+def test_create_rejects_null_arguments(L):
+    from paper_1508_02045_amd import fgh
+    h = ctypes.c_void_p()
+    N = (ctypes.c_int32 * 2)(5, 5)
+    # NULL workspace (checked before any device call)
+    st = L.fgh_plan_create(ctypes.byref(h), 2, N, 0, 0, fgh.FGH_A_ISO, ctypes.c_void_p(8), None, None, 0, 0.0, 0.0,
+                           None, 0, None)
+    assert st == fgh.FGH_E_WORKSPACE
+    st = L.fgh_plan_create(ctypes.byref(h), 2, N, 0, 0, fgh.FGH_A_PHASE, None, None, None, 0, 0.0, 0.0,
+                           None, 0, None)
+    assert st == fgh.FGH_E_INVALID
+    assert L.fgh_solve(None, 1, None, 1, 1e-6, 10, None, None) == fgh.FGH_E_INVALID
