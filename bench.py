@@ -1,0 +1,180 @@
+"""Benchmark: voxel-iterations/s of the Fourier-Galerkin operator G.A inside the paper's solvers.
+
+Default workload (one GPU): 3D, N = 135^3, two-phase Boolean model of overlapping spheres
+(radius 8 voxels, volume fraction 0.30), A = I in the matrix and 100 I in the spheres,
+E = (1, 0, 0), GaNi (trapezoidal rule on the N grid), FP64.  One step solves this cell with all
+four solvers -- Richardson, conjugate gradients, Chebyshev on [1, 100], Eyre-Milton -- each to
+1e-8 by its own stopping test, and evaluates A_H (the energy).  The metric counts one
+voxel-iteration per grid point per operator application inside the solver loops.
+
+Prints ONE JSON line.  Extra objects: "roofline" (dominant pass, measured with HIP events on the
+plan's stream during the timed steps, against the 8 TB/s HBM peak) and "cpu_baseline" (the FP64
+oracle timed on a bounded sample of the same workload on the host cores).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SOLVERS = ["richardson", "cg", "chebyshev", "eyre_milton"]
+PASS_KERNELS = {"first": "k_first", "axis_fwd": "k_axis<fwd>", "middle": "k_middle", "axis_inv": "k_axis<inv>",
+                "last": "k_last"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "middle_pass_135_fp64_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1508_02045_amd", "csrc", f) for f in
+                  ("fgh_kernels.hip", "fgh_fft.hpp", "fgh_internal.hpp")]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def pass_bytes(g, d, p_bytes):
+    """Algorithmic HBM bytes per launch of the fixed-traffic passes (read + write of the
+    half spectrum): the middle and strided-axis passes move d * s complex each way."""
+    N = g
+    H = (N[-1] + 1) // 2
+    s1 = N[0] * N[1] * H if d == 3 else N[0] * H
+    s2 = s1
+    cplx = 2 * p_bytes
+    return {"middle": 2 * d * s2 * cplx, "axis_fwd": d * (s1 + s2) * cplx, "axis_inv": d * (s1 + s2) * cplx}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=135)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not part "
+              f"of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1508_02045_amd import fgh, inputs
+
+    torch.cuda.set_device(0)
+    n = args.n
+    log(f"[bench] generating Boolean spheres {n}^3 r=8 f=0.30")
+    w = inputs.config2(N=n)
+    tab = np.stack([inputs.sym_pack(t[None])[:, 0] for t in w.tables])
+    phase_dev = torch.from_numpy(w.phase).cuda()
+    plan = fgh.Plan(w.N, phase=phase_dev, phase_table=tab, c_A=1.0, C_A=w.contrast)
+    d = 3
+    npts = plan.npts
+    tol = 1e-8
+    e = plan.field()
+
+    def step():
+        out = {}
+        for s in SOLVERS:
+            e_, st, stats = plan.solve(s, w.E, tol, max_iter=5000, e=e)
+            if st != fgh.FGH_OK:
+                raise RuntimeError(f"{s}: status {st} {stats}")
+            bil, flux = plan.effective(w.E, e)
+            out[s] = {"iters": stats[0]["iters"], "seconds": stats[0]["seconds"], "A_H_11": float(bil[0, 0]),
+                      "flux": [float(v) for v in flux[0]], "rel_res_true": stats[0]["rel_res_true"]}
+        return out
+
+    for i in range(args.warmup):
+        log(f"[bench] warmup step {i + 1}/{args.warmup}")
+        step()
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total_iters = 0
+    res = None
+    for i in range(args.steps):
+        res = step()
+        total_iters += sum(r["iters"] for r in res.values())
+        log(f"[bench] step {i + 1}/{args.steps}: " + ", ".join(f"{k} {v['iters']}" for k, v in res.items()))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = plan.read_profile()
+    plan.set_profiling(False)
+    elapsed = t1 - t0
+    value = total_iters * npts / elapsed
+
+    # roofline of the dominant fixed-traffic pass
+    pb = pass_bytes(w.N, d, 8)
+    dom = max(("middle", "axis_fwd", "axis_inv"), key=lambda k: prof[k][0])
+    ms_tot, launches = prof[dom]
+    avg_s = ms_tot / 1e3 / max(launches, 1)
+    achieved = pb[dom] / avg_s / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("pass") == dom:
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": PASS_KERNELS[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes_per_launch": pb[dom], "avg_launch_us": round(avg_s * 1e6, 2),
+                "launches": launches,
+                "per_pass_avg_us": {k: round(v[0] * 1e3 / max(v[1], 1), 2) for k, v in prof.items()},
+                "per_pass_share": {k: round(v[0] / max(sum(x[0] for x in prof.values()), 1e-30), 3)
+                                   for k, v in prof.items()}}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import orc
+        A_full = w.full()
+        log(f"[bench] cpu baseline: oracle CG, {args.cpu_iters} fixed iterations at {n}^3 "
+            f"on {orc.num_threads()} threads")
+        tc = time.perf_counter()
+        r = orc.solve(w.N, orc.GANI, A_full, w.E, "cg", 1.0, w.contrast, tol, fixed_iters=args.cpu_iters)
+        tcpu = time.perf_counter() - tc
+        cpu = {"value": args.cpu_iters * npts / tcpu, "unit": "voxel-iterations/s", "cores": orc.num_threads(),
+               "kind": "oracle",
+               "sample": f"FP64 oracle (naive DFT) CG with {args.cpu_iters} fixed iterations on the same {n}^3 "
+                         f"input, wall {tcpu:.1f} s including its right-hand side and exit-residual applies"}
+        del r
+
+    line = {
+        "metric": "voxel-iterations/s of G.A",
+        "value": value,
+        "unit": "voxel-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D Boolean spheres {n}^3 r=8 f={w.fraction:.4f} contrast 100, GaNi, FP64, "
+                               f"Richardson+CG+Chebyshev+Eyre-Milton to 1e-8, E=e1",
+                   "N": list(w.N), "solvers": SOLVERS, "tol": tol, "voxel_iterations_per_step": total_iters // args.steps * npts},
+        "solvers": res,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

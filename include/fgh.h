@@ -168,6 +168,16 @@ fgh_status fgh_solve_fixed(fgh_plan plan, fgh_solver solver, const double* E, in
 fgh_status fgh_effective(fgh_plan plan, const double* E, int nrhs, const double* e,
                          double* bilinear, double* flux);
 
+/* Per-pass device timing (profiling aid, not on by default).  While enabled, every pass launch of
+ * the plan -- 0 first (A multiply + forward transform of the last axis), 1 forward strided axis,
+ * 2 middle (transform of axis 0 with the Fourier multiplier), 3 inverse strided axis, 4 last
+ * (inverse transform of the last axis + solver epilogue) -- is bracketed by HIP events on the
+ * plan's stream and its duration accumulated.  Enabling resets the counters. */
+fgh_status fgh_plan_set_profiling(fgh_plan plan, int enable);
+
+/* Accumulated milliseconds and launch counts per pass kind (arrays of 5).  Synchronises. */
+fgh_status fgh_plan_read_profile(fgh_plan plan, double* ms, int64_t* launches);
+
 const char* fgh_status_string(fgh_status status);
 
 #ifdef __cplusplus

@@ -250,6 +250,7 @@ struct fgh_plan_s {
     float* p32;
     float* q32;
     double* host_buf;         // pinned host scalars
+    Profiler* prof;           // per-pass timing while enabled
 };
 
 namespace {
@@ -994,11 +995,49 @@ fgh_status fgh_plan_create(fgh_plan* out, int d, const int32_t* N, fgh_rule rule
 void fgh_plan_destroy(fgh_plan p)
 {
     if (!p) return;
+    if (p->prof) {
+        p->prof->destroy();
+        delete p->prof;
+    }
     if (p->host_buf) (void)hipHostFree(p->host_buf);
     delete p;
 }
 
 int64_t fgh_plan_grid_points(fgh_plan p) { return p ? p->g.npts : 0; }
+
+fgh_status fgh_plan_set_profiling(fgh_plan p, int enable)
+{
+    if (!p) return FGH_E_INVALID;
+    if (enable) {
+        if (!p->prof) {
+            p->prof = new (std::nothrow) Profiler();
+            if (!p->prof) return FGH_E_DEVICE;
+        }
+        HIPOK(p->prof->init(p->stream));
+        p->op64.prof = p->prof;
+        p->op32.prof = p->prof;
+    } else {
+        p->op64.prof = nullptr;
+        p->op32.prof = nullptr;
+    }
+    return FGH_OK;
+}
+
+fgh_status fgh_plan_read_profile(fgh_plan p, double* ms, int64_t* launches)
+{
+    if (!p || !ms || !launches) return FGH_E_INVALID;
+    for (int k = 0; k < PK_KINDS; k++) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    if (!p->prof) return FGH_OK;
+    HIPOK(p->prof->drain());
+    for (int k = 0; k < PK_KINDS; k++) {
+        ms[k] = p->prof->ms[k];
+        launches[k] = p->prof->n[k];
+    }
+    return FGH_OK;
+}
 
 fgh_status fgh_plan_bounds(fgh_plan p, double* c_A, double* C_A)
 {

@@ -924,6 +924,64 @@ static inline unsigned grid_for(long long n, int per = kThreads, int cap = 4096)
 
 int vec_blocks() { return kVecBlocks; }
 
+hipError_t Profiler::init(hipStream_t s)
+{
+    stream = s;
+    if (!ready) {
+        for (int i = 0; i < 2 * kPool; i++) {
+            hipError_t e = hipEventCreate(&ev[i]);
+            if (e != hipSuccess) return e;
+        }
+        ready = true;
+    }
+    used = 0;
+    for (int k = 0; k < PK_KINDS; k++) {
+        ms[k] = 0.0;
+        n[k] = 0;
+    }
+    return hipSuccess;
+}
+
+void Profiler::destroy()
+{
+    if (ready)
+        for (int i = 0; i < 2 * kPool; i++) (void)hipEventDestroy(ev[i]);
+    ready = false;
+}
+
+hipError_t Profiler::begin(int k)
+{
+    if (used == kPool) {
+        hipError_t e = drain();
+        if (e != hipSuccess) return e;
+    }
+    kind[used] = k;
+    return hipEventRecord(ev[2 * used], stream);
+}
+
+hipError_t Profiler::end()
+{
+    hipError_t e = hipEventRecord(ev[2 * used + 1], stream);
+    used++;
+    return e;
+}
+
+hipError_t Profiler::drain()
+{
+    if (used == 0) return hipSuccess;
+    hipError_t e = hipEventSynchronize(ev[2 * used - 1]);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < used; i++) {
+        float t = 0.0f;
+        e = hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
+        if (e != hipSuccess) return e;
+        ms[kind[i]] += t;
+        n[kind[i]]++;
+    }
+    used = 0;
+    return hipSuccess;
+}
+
 template <typename T, int D, int AK>
 static hipError_t launch_first_ak(const OpPlan& op, const FirstArgs<T>& fa, int opc, unsigned nblk)
 {
@@ -1022,7 +1080,9 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     fa.A = op.A;
     fa.out = SA;
     fa.twg = static_cast<const cpx<T>*>(op.tw[last]);
+    if (op.prof && (e = op.prof->begin(PK_FIRST)) != hipSuccess) return e;
     if ((e = launch_first<T, D>(op, fa, a.op, nblk)) != hipSuccess) return e;
+    if (op.prof && (e = op.prof->end()) != hipSuccess) return e;
 
     cpx<T>* mid = SA;
     if (D == 3) {
@@ -1042,7 +1102,9 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
         xa.in = SA;
         xa.out = SB;
         xa.twg = static_cast<const cpx<T>*>(op.tw[1]);
+        if (op.prof && (e = op.prof->begin(PK_AXIS_FWD)) != hipSuccess) return e;
         if ((e = launch_axis<T>(op, xa, false, g.L[0])) != hipSuccess) return e;
+        if (op.prof && (e = op.prof->end()) != hipSuccess) return e;
         mid = SB;
     }
 
@@ -1058,7 +1120,9 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     ma.scale = 1.0 / (double)g.npts;
     ma.buf = mid;
     ma.twg = static_cast<const cpx<T>*>(op.tw[0]);
+    if (op.prof && (e = op.prof->begin(PK_MIDDLE)) != hipSuccess) return e;
     if ((e = launch_middle<T, D>(op, ma, a.mult)) != hipSuccess) return e;
+    if (op.prof && (e = op.prof->end()) != hipSuccess) return e;
 
     if (D == 3) {
         AxisArgs<T> xa;
@@ -1077,7 +1141,9 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
         xa.in = SB;
         xa.out = SA;
         xa.twg = static_cast<const cpx<T>*>(op.tw[1]);
+        if (op.prof && (e = op.prof->begin(PK_AXIS_INV)) != hipSuccess) return e;
         if ((e = launch_axis<T>(op, xa, true, g.L[0])) != hipSuccess) return e;
+        if (op.prof && (e = op.prof->end()) != hipSuccess) return e;
     }
 
     LastArgs<T> la;
@@ -1100,7 +1166,9 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     la.A = op.A;
     la.partials = op.partials;
     la.twg = static_cast<const cpx<T>*>(op.tw[last]);
+    if (op.prof && (e = op.prof->begin(PK_LAST)) != hipSuccess) return e;
     if ((e = launch_last<T, D>(op, la, a.epi, nblk)) != hipSuccess) return e;
+    if (op.prof && (e = op.prof->end()) != hipSuccess) return e;
     if (nblocks_last) *nblocks_last = (int)nblk;
     return hipSuccess;
 }

@@ -6,6 +6,24 @@
 
 namespace fgh {
 
+// Per-pass device timing: launches bracketed by HIP events on the plan's stream.
+enum PassKind : int { PK_FIRST = 0, PK_AXIS_FWD = 1, PK_MIDDLE = 2, PK_AXIS_INV = 3, PK_LAST = 4, PK_KINDS = 5 };
+struct Profiler {
+    static constexpr int kPool = 256;
+    hipEvent_t ev[2 * kPool];
+    int kind[kPool];
+    int used = 0;
+    bool ready = false;
+    double ms[PK_KINDS] = {0, 0, 0, 0, 0};
+    long long n[PK_KINDS] = {0, 0, 0, 0, 0};
+    hipStream_t stream = nullptr;
+    hipError_t init(hipStream_t s);
+    void destroy();
+    hipError_t begin(int k);
+    hipError_t end();
+    hipError_t drain();
+};
+
 // Everything one operator application needs (one precision).
 struct OpPlan {
     Geo g;
@@ -20,6 +38,7 @@ struct OpPlan {
     double* partials;        // one double per block of the last pass (and of vector kernels)
     Scalars* sc;
     hipStream_t stream;
+    Profiler* prof = nullptr;  // non-null while profiling is enabled
 };
 
 // Parameters of one application: what the first pass reads, the multiplier, the epilogue.

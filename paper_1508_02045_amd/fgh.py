@@ -37,7 +37,9 @@ SOLVERS = {"richardson": FGH_RICHARDSON, "cg": FGH_CG, "chebyshev": FGH_CHEBYSHE
 
 EXPORTS = ["fgh_plan_workspace", "fgh_plan_create", "fgh_plan_destroy", "fgh_plan_grid_points",
            "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32", "fgh_ga_coefficients", "fgh_solve",
-           "fgh_solve_fixed", "fgh_effective", "fgh_status_string"]
+           "fgh_solve_fixed", "fgh_effective", "fgh_plan_set_profiling", "fgh_plan_read_profile",
+           "fgh_status_string"]
+PASS_NAMES = ["first", "axis_fwd", "middle", "axis_inv", "last"]
 
 
 class FghError(RuntimeError):
@@ -87,10 +89,13 @@ def lib():
         L.fgh_solve_fixed.argtypes = [_vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _vp,
                                       ctypes.POINTER(Stats)]
         L.fgh_effective.argtypes = [_vp, _dp, ctypes.c_int, _vp, _dp, _dp]
+        L.fgh_plan_set_profiling.argtypes = [_vp, ctypes.c_int]
+        L.fgh_plan_read_profile.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]
         L.fgh_status_string.argtypes = [ctypes.c_int]
         L.fgh_status_string.restype = ctypes.c_char_p
         for name in ("fgh_plan_workspace", "fgh_plan_create", "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32",
-                     "fgh_ga_coefficients", "fgh_solve", "fgh_solve_fixed", "fgh_effective"):
+                     "fgh_ga_coefficients", "fgh_solve", "fgh_solve_fixed", "fgh_effective",
+                     "fgh_plan_set_profiling", "fgh_plan_read_profile"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -267,6 +272,19 @@ class Plan:
         if st:
             raise FghError(st, "fgh_ga_coefficients")
         return out
+
+    def set_profiling(self, enable=True):
+        st = lib().fgh_plan_set_profiling(ctypes.c_void_p(self.handle), 1 if enable else 0)
+        if st:
+            raise FghError(st, "fgh_plan_set_profiling")
+
+    def read_profile(self):
+        ms = (ctypes.c_double * 5)()
+        n = (ctypes.c_int64 * 5)()
+        st = lib().fgh_plan_read_profile(ctypes.c_void_p(self.handle), ms, n)
+        if st:
+            raise FghError(st, "fgh_plan_read_profile")
+        return {PASS_NAMES[k]: (ms[k], n[k]) for k in range(5)}
 
     def close(self):
         if getattr(self, "handle", None):
