@@ -4,6 +4,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -11,13 +12,25 @@
 #include "../../include/fgh.h"
 #include "fgh_internal.hpp"
 #include "fgh_launch.hpp"
+#include "fgh_v2.hpp"
 
 using namespace fgh;
 
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr size_t kLdsBudget = 80 * 1024;
+constexpr size_t kLdsBudgetDefault = 80 * 1024;
+
+// LDS bytes per workgroup the launch configuration may use (tuning knob: FGH_LDS_BUDGET).
+size_t lds_budget()
+{
+    const char* v = std::getenv("FGH_LDS_BUDGET");
+    if (v) {
+        const long b = std::atol(v);
+        if (b >= 8192 && b <= 160 * 1024) return (size_t)b;
+    }
+    return kLdsBudgetDefault;
+}
 constexpr double kZeroRhs = 1e-12;      // b is taken as zero when ||b|| <= kZeroRhs ||A E||
 constexpr double kInnerTolMin = 1e-4;   // FP32 inner solves stop at this relative residual
 
@@ -50,41 +63,54 @@ bool factorize(int L, Axis* ax)
 struct Config {
     int rpb, npen, P_axis, P_mid;
     size_t lds_first, lds_axis, lds_mid;
+    bool v2_row, v2_axis, v2_mid;
 };
 
+// Tile choice per pass: the largest tile whose LDS footprint fits the budget.  The specialised
+// kernels hold one copy of the tile (plus the twiddle table); the generic ones two (ping-pong).
 Config choose_config(const Geo& g, size_t cs /* bytes per complex */, size_t rs /* bytes per real */)
 {
     Config c{};
+    const size_t kLdsBudget = lds_budget();
     const int d = g.d;
     const int Ll = g.L[d - 1];
-    // first/last: as many rows per block as fit, at most 32
+    const size_t tabb = kMaxPhases * 6 * rs;
+    c.v2_row = v2_supported(Ll);
+    c.v2_axis = d == 3 && v2_supported(g.L[1]);
+    c.v2_mid = v2_supported(g.L[0]);
     c.rpb = 1;
-    for (int rpb = 32; rpb >= 1; rpb--) {
+    for (int rpb = c.v2_row ? 16 : 32; rpb >= 1; rpb--) {
         const int npen = (rpb * d + 1) / 2;
-        const size_t lds = (size_t)(Ll + 2 * npen * Ll) * cs + kMaxPhases * 6 * rs;
-        if (lds <= kLdsBudget) {
+        const size_t lds = c.v2_row ? (size_t)(Ll + rpb * d * Ll) * cs + tabb
+                                    : (size_t)(Ll + 2 * npen * Ll) * cs + tabb;
+        if (lds <= kLdsBudget || rpb == 1) {
             c.rpb = rpb;
+            c.lds_first = lds;
             break;
         }
     }
     c.npen = (c.rpb * d + 1) / 2;
-    c.lds_first = (size_t)(Ll + 2 * c.npen * Ll) * cs + kMaxPhases * 6 * rs;
     const int Ps[5] = {16, 8, 4, 2, 1};
     c.P_axis = 1;
+    c.lds_axis = 0;
     if (d == 3)
-        for (int P : Ps)
-            if ((size_t)(g.L[1] + 2 * P * g.L[1]) * cs <= kLdsBudget) {
+        for (int P : Ps) {
+            const size_t lds = c.v2_axis ? (size_t)(g.L[1] + P * g.L[1]) * cs : (size_t)(g.L[1] + 2 * P * g.L[1]) * cs;
+            if (lds <= kLdsBudget || P == 1) {
                 c.P_axis = P;
+                c.lds_axis = lds;
                 break;
             }
-    c.lds_axis = (size_t)(g.L[1] + 2 * c.P_axis * g.L[1]) * cs;
+        }
     c.P_mid = 1;
-    for (int P : Ps)
-        if ((size_t)(g.L[0] + (d + 1) * P * g.L[0]) * cs <= kLdsBudget) {
+    for (int P : Ps) {
+        const size_t lds = c.v2_mid ? (size_t)(g.L[0] + d * P * g.L[0]) * cs : (size_t)(g.L[0] + (d + 1) * P * g.L[0]) * cs;
+        if (lds <= kLdsBudget || P == 1) {
             c.P_mid = P;
+            c.lds_mid = lds;
             break;
         }
-    c.lds_mid = (size_t)(g.L[0] + (d + 1) * c.P_mid * g.L[0]) * cs;
+    }
     return c;
 }
 
@@ -301,6 +327,9 @@ void fill_opplan(fgh_plan p, OpPlan* op, bool f32)
     op->lds_first = c.lds_first;
     op->lds_axis = c.lds_axis;
     op->lds_mid = c.lds_mid;
+    op->v2_row = c.v2_row;
+    op->v2_axis = c.v2_axis;
+    op->v2_mid = c.v2_mid;
     op->partials = reinterpret_cast<double*>(p->ws + p->lay.partials);
     op->sc = reinterpret_cast<Scalars*>(p->ws + p->lay.scalars);
     op->stream = p->stream;

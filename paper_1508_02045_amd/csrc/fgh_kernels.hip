@@ -3,100 +3,15 @@
 // and the set-up kernels (double-grid coefficients, spectral bounds).
 #include <hip/hip_runtime.h>
 
-#include "fgh_fft.hpp"
+#include "fgh_args.hpp"
 #include "fgh_launch.hpp"
+#include "fgh_v2.hpp"
 
 namespace fgh {
 
 // ------------------------------------------------------------------------------------------
-// Coefficient helpers: z = A(pt) u with A as the passes see it (eq:A, eq:GaNi, eq:Ga_eval).
-// ------------------------------------------------------------------------------------------
-template <typename T, int D>
-__device__ __forceinline__ void sym_mul(const T* a, const T* u, T* z)
-{
-    if (D == 2) {  // a00 a01 a11
-        z[0] = a[0] * u[0] + a[1] * u[1];
-        z[1] = a[1] * u[0] + a[2] * u[1];
-    } else {       // a00 a01 a02 a11 a12 a22
-        z[0] = a[0] * u[0] + a[1] * u[1] + a[2] * u[2];
-        z[1] = a[1] * u[0] + a[3] * u[1] + a[4] * u[2];
-        z[2] = a[2] * u[0] + a[4] * u[1] + a[5] * u[2];
-    }
-}
-
-template <int D>
-constexpr int ncoef_of() { return D == 2 ? 3 : 6; }
-
-// Load the packed coefficients of point pt into a[] (AK_ISO gives a scalar in a[0]).
-template <typename T, int D, int AK>
-__device__ __forceinline__ void load_coef(const CoefArgs& A, const T* tab, long long pt, long long npts, T* a)
-{
-    if (AK == AK_ISO) {
-        a[0] = static_cast<const T*>(A.coef)[pt];
-    } else if (AK == AK_PHASE) {
-        const int ph = A.phase[pt];
-#pragma unroll
-        for (int q = 0; q < ncoef_of<D>(); q++) a[q] = tab[ph * 6 + q];
-    } else {
-        const T* c = static_cast<const T*>(A.coef);
-#pragma unroll
-        for (int q = 0; q < ncoef_of<D>(); q++) a[q] = c[q * npts + pt];
-    }
-}
-
-template <typename T, int D, int AK>
-__device__ __forceinline__ void mul_A(const T* a, const T* u, T* z)
-{
-    if (AK == AK_ISO) {
-#pragma unroll
-        for (int c = 0; c < D; c++) z[c] = a[0] * u[c];
-    } else {
-        sym_mul<T, D>(a, u, z);
-    }
-}
-
-// Solve (A + w I) v = rhs at one point for packed symmetric A (closed-form inverse).
-template <typename T, int D>
-__device__ __forceinline__ void sym_shift_solve(const T* a, T w, const T* rhs, T* v)
-{
-    if (D == 2) {
-        const T m00 = a[0] + w, m01 = a[1], m11 = a[2] + w;
-        const T det = m00 * m11 - m01 * m01;
-        v[0] = (m11 * rhs[0] - m01 * rhs[1]) / det;
-        v[1] = (-m01 * rhs[0] + m00 * rhs[1]) / det;
-    } else {
-        const T m00 = a[0] + w, m01 = a[1], m02 = a[2], m11 = a[3] + w, m12 = a[4], m22 = a[5] + w;
-        const T c00 = m11 * m22 - m12 * m12;
-        const T c01 = m02 * m12 - m01 * m22;
-        const T c02 = m01 * m12 - m02 * m11;
-        const T c11 = m00 * m22 - m02 * m02;
-        const T c12 = m01 * m02 - m00 * m12;
-        const T c22 = m00 * m11 - m01 * m01;
-        const T det = m00 * c00 + m01 * c01 + m02 * c02;
-        v[0] = (c00 * rhs[0] + c01 * rhs[1] + c02 * rhs[2]) / det;
-        v[1] = (c01 * rhs[0] + c11 * rhs[1] + c12 * rhs[2]) / det;
-        v[2] = (c02 * rhs[0] + c12 * rhs[1] + c22 * rhs[2]) / det;
-    }
-}
-
-// ------------------------------------------------------------------------------------------
 // Pass 1: real rows along the last axis -> half spectra S1.
 // ------------------------------------------------------------------------------------------
-template <typename T>
-struct FirstArgs {
-    Geo g;
-    Axis ax;
-    int rpb, npen;
-    const T* x;
-    T* p;
-    const T* r;
-    const Scalars* sc;
-    double E[3];
-    double omega;
-    CoefArgs A;
-    cpx<T>* out;
-    const cpx<T>* twg;
-};
 
 template <typename T, int D, int AK, int OP>
 __global__ __launch_bounds__(kThreads) void k_first(FirstArgs<T> a)
@@ -190,17 +105,6 @@ __global__ __launch_bounds__(kThreads) void k_first(FirstArgs<T> a)
 // ------------------------------------------------------------------------------------------
 // Strided pass along a middle axis (3D axis 1), one component per workgroup.
 // ------------------------------------------------------------------------------------------
-template <typename T>
-struct AxisArgs {
-    Axis ax;
-    int nin, nout;          // stored counts along the axis
-    int bin, bout;          // 1: stored index is a band index (frequency signed(s, n)), 0: position
-    int inner, P, ntiles;
-    long long in_os, out_os, in_cs, out_cs;
-    const cpx<T>* in;
-    cpx<T>* out;
-    const cpx<T>* twg;
-};
 
 template <typename T, bool INV>
 __global__ __launch_bounds__(kThreads) void k_axis(AxisArgs<T> a)
@@ -245,15 +149,6 @@ __global__ __launch_bounds__(kThreads) void k_axis(AxisArgs<T> a)
 // components of a frequency at hand (eq:proj / eq:discrete_proj; Algorithm 4's I - 2G^),
 // inverse FFT.  Works in place on the spectrum.
 // ------------------------------------------------------------------------------------------
-template <typename T>
-struct MidArgs {
-    Axis ax;
-    int B0, cols, Hb, B1, P, ntiles;
-    long long cs;
-    double scale;  // 1 / |grid| (the forward DFT factor of eq:DFT)
-    cpx<T>* buf;
-    const cpx<T>* twg;
-};
 
 template <typename T, int D, int MULT>
 __global__ __launch_bounds__(kThreads) void k_middle(MidArgs<T> a)
@@ -356,24 +251,6 @@ __global__ __launch_bounds__(kThreads) void k_middle(MidArgs<T> a)
 // ------------------------------------------------------------------------------------------
 // Last pass: half spectra -> real rows, with the solver epilogue (Algorithms 1-4).
 // ------------------------------------------------------------------------------------------
-template <typename T>
-struct LastArgs {
-    Geo g;
-    Axis ax;
-    int rpb, npen;
-    const cpx<T>* in;
-    T* y;
-    T* x;
-    T* r;
-    T* p;
-    T* q;
-    const T* src;
-    double E[3];
-    double omega, alpha, beta, sgn;
-    CoefArgs A;
-    double* partials;
-    const cpx<T>* twg;
-};
 
 template <typename T, int D, int AK, int EPI>
 __global__ __launch_bounds__(kThreads) void k_last(LastArgs<T> a)
@@ -1056,6 +933,72 @@ static hipError_t launch_axis(const OpPlan& op, const AxisArgs<T>& xa, bool inv,
     return hipGetLastError();
 }
 
+// Size-specialised launches (lengths listed in kSplits).
+#define V2_ROW_CASES(X) X(45, 9, 5) X(63, 7, 9) X(81, 9, 9) X(125, 25, 5) X(135, 15, 9) X(243, 27, 9)
+#define V2_COL_CASES(X) X(45, 5, 9) X(63, 7, 9) X(81, 9, 9) X(125, 5, 25) X(135, 9, 15) X(243, 9, 27)
+
+template <typename T, int D>
+static hipError_t v2_first(const OpPlan& op, const FirstArgs<T>& fa, int opc, unsigned nblk)
+{
+    const size_t lds = op.lds_first;
+    switch (fa.ax.L) {
+#define C(LL, A1, A2) \
+    case LL: LAUNCH_LDS((k2_first<T, D, A1, A2>), dim3(nblk), lds, op.stream, fa, opc); break;
+        V2_ROW_CASES(C)
+#undef C
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int D>
+static hipError_t v2_last(const OpPlan& op, const LastArgs<T>& la, int epi, unsigned nblk)
+{
+    const size_t lds = op.lds_first;
+    switch (la.ax.L) {
+#define C(LL, A1, A2) \
+    case LL: LAUNCH_LDS((k2_last<T, D, A1, A2>), dim3(nblk), lds, op.stream, la, epi); break;
+        V2_ROW_CASES(C)
+#undef C
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int D>
+static hipError_t v2_middle(const OpPlan& op, const MidArgs<T>& ma, int mult)
+{
+    const size_t lds = op.lds_mid;
+    switch (ma.ax.L) {
+#define C(LL, A1, A2) \
+    case LL: LAUNCH_LDS((k2_middle<T, D, A1, A2>), dim3(ma.ntiles), lds, op.stream, ma, mult); break;
+        V2_COL_CASES(C)
+#undef C
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t v2_axis(const OpPlan& op, const AxisArgs<T>& xa, bool inv, int outer, int B)
+{
+    dim3 grid(xa.ntiles, outer, op.g.d);
+    const size_t lds = op.lds_axis;
+    switch (xa.ax.L) {
+#define C(LL, A1, A2)                                                                        \
+    case LL:                                                                                 \
+        if (inv)                                                                             \
+            LAUNCH_LDS((k2_axis<T, A1, A2, true>), grid, lds, op.stream, xa, B);             \
+        else                                                                                 \
+            LAUNCH_LDS((k2_axis<T, A1, A2, false>), grid, lds, op.stream, xa, B);            \
+        break;
+        V2_COL_CASES(C)
+#undef C
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename T, int D>
 static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_last)
 {
@@ -1081,7 +1024,8 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     fa.out = SA;
     fa.twg = static_cast<const cpx<T>*>(op.tw[last]);
     if (op.prof && (e = op.prof->begin(PK_FIRST)) != hipSuccess) return e;
-    if ((e = launch_first<T, D>(op, fa, a.op, nblk)) != hipSuccess) return e;
+    if ((e = op.v2_row ? v2_first<T, D>(op, fa, a.op, nblk) : launch_first<T, D>(op, fa, a.op, nblk)) != hipSuccess)
+        return e;
     if (op.prof && (e = op.prof->end()) != hipSuccess) return e;
 
     cpx<T>* mid = SA;
@@ -1103,7 +1047,8 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
         xa.out = SB;
         xa.twg = static_cast<const cpx<T>*>(op.tw[1]);
         if (op.prof && (e = op.prof->begin(PK_AXIS_FWD)) != hipSuccess) return e;
-        if ((e = launch_axis<T>(op, xa, false, g.L[0])) != hipSuccess) return e;
+        if ((e = op.v2_axis ? v2_axis<T>(op, xa, false, g.L[0], g.B[1]) : launch_axis<T>(op, xa, false, g.L[0])) != hipSuccess)
+            return e;
         if (op.prof && (e = op.prof->end()) != hipSuccess) return e;
         mid = SB;
     }
@@ -1121,7 +1066,7 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     ma.buf = mid;
     ma.twg = static_cast<const cpx<T>*>(op.tw[0]);
     if (op.prof && (e = op.prof->begin(PK_MIDDLE)) != hipSuccess) return e;
-    if ((e = launch_middle<T, D>(op, ma, a.mult)) != hipSuccess) return e;
+    if ((e = op.v2_mid ? v2_middle<T, D>(op, ma, a.mult) : launch_middle<T, D>(op, ma, a.mult)) != hipSuccess) return e;
     if (op.prof && (e = op.prof->end()) != hipSuccess) return e;
 
     if (D == 3) {
@@ -1142,7 +1087,8 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
         xa.out = SA;
         xa.twg = static_cast<const cpx<T>*>(op.tw[1]);
         if (op.prof && (e = op.prof->begin(PK_AXIS_INV)) != hipSuccess) return e;
-        if ((e = launch_axis<T>(op, xa, true, g.L[0])) != hipSuccess) return e;
+        if ((e = op.v2_axis ? v2_axis<T>(op, xa, true, g.L[0], g.B[1]) : launch_axis<T>(op, xa, true, g.L[0])) != hipSuccess)
+            return e;
         if (op.prof && (e = op.prof->end()) != hipSuccess) return e;
     }
 
@@ -1167,7 +1113,8 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     la.partials = op.partials;
     la.twg = static_cast<const cpx<T>*>(op.tw[last]);
     if (op.prof && (e = op.prof->begin(PK_LAST)) != hipSuccess) return e;
-    if ((e = launch_last<T, D>(op, la, a.epi, nblk)) != hipSuccess) return e;
+    if ((e = op.v2_row ? v2_last<T, D>(op, la, a.epi, nblk) : launch_last<T, D>(op, la, a.epi, nblk)) != hipSuccess)
+        return e;
     if (op.prof && (e = op.prof->end()) != hipSuccess) return e;
     if (nblocks_last) *nblocks_last = (int)nblk;
     return hipSuccess;

@@ -85,7 +85,8 @@ def test_apply_gani_matches_oracle(N, kind):
 
 
 @pytest.mark.parametrize("N,kind", [((9, 7), "phase"), ((5, 5), "sym"), ((15, 15), "iso"), ((7, 5, 9), "sym"),
-                                    ((5, 5, 5), "phase"), ((3, 5, 3), "iso")])
+                                    ((5, 5, 5), "phase"), ((3, 5, 3), "iso"), ((63, 41), "phase"),
+                                    ((41, 63), "sym"), ((23, 41, 23), "phase"), ((41, 5, 63), "iso")])
 def test_apply_ga_matches_oracle(N, kind):
     rng = np.random.default_rng(7 + N[0])
     d = len(N)
@@ -112,6 +113,37 @@ def test_apply_ga_matches_oracle(N, kind):
     y = plan.apply(dev(x)).cpu().numpy()
     y_ref = orc.apply(N, orc.GA, AM, x)
     assert rel(y, y_ref) <= 1e-12
+
+
+# Every length with a size-specialised kernel (45, 63, 81, 125, 135, 243) in every pass position:
+# middle (axis 0), strided (axis 1 of 3D) and row passes (last axis), three coefficient kinds.
+SPECIALISED_CASES = [
+    ((45, 63), "sym"), ((63, 81), "phase"), ((81, 45), "iso"), ((125, 135), "phase"), ((135, 243), "sym"),
+    ((243, 125), "iso"), ((63, 135), "phase"),
+    ((45, 63, 81), "phase"), ((81, 125, 45), "sym"), ((63, 45, 243), "iso"), ((243, 81, 63), "phase"),
+    ((135, 45, 125), "sym"), ((125, 135, 63), "phase"),
+]
+
+
+@pytest.mark.parametrize("N,kind", SPECIALISED_CASES)
+def test_apply_specialised_lengths(N, kind):
+    test_apply_gani_matches_oracle(N, kind)
+
+
+@pytest.mark.parametrize("N", [(45, 63, 81), (63, 45, 243), (25, 27, 23), (81, 45)])
+def test_apply_fp32_within_single_precision_bound(N):
+    """The FP32 operator of the refined precision mode: relative error within a few FP32 ulps
+    times the transform depth (bound 2e-6 on ||dy|| / ||y||)."""
+    rng = np.random.default_rng(21)
+    d = len(N)
+    phase = I.centred_box(N, max(1, N[0] // 4))
+    tables = I.iso_tables(d, [1.0, 1e3])
+    A = I.phase_to_full(phase, tables)
+    plan = make_plan(N, phase=phase, tables=tables, kind="phase", precision=1)
+    x = rng.standard_normal((d,) + tuple(N))
+    y = plan.apply(dev(x, torch.float32)).double().cpu().numpy()
+    y_ref = orc.apply(N, orc.GANI, A, x.astype(np.float32).astype(np.float64))
+    assert rel(y, y_ref) <= 2e-6
 
 
 # ----------------------------------------------------------------------------------------------
