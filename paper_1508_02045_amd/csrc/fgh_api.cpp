@@ -66,7 +66,16 @@ struct Config {
     bool v2_row, v2_axis, v2_mid;
 };
 
-// Tile choice per pass: the largest tile whose LDS footprint fits the budget.  The specialised
+int env_int(const char* name, int dflt)
+{
+    const char* v = std::getenv(name);
+    if (!v) return dflt;
+    const int x = std::atoi(v);
+    return x > 0 ? x : dflt;
+}
+
+// Tile choice per pass: the largest tile whose LDS footprint fits the budget (tuning knobs:
+// FGH_RPB, FGH_P_AXIS, FGH_P_MID cap the rows per block and the tile widths).  The specialised
 // kernels hold one copy of the tile (plus the twiddle table); the generic ones two (ping-pong).
 Config choose_config(const Geo& g, size_t cs /* bytes per complex */, size_t rs /* bytes per real */)
 {
@@ -79,9 +88,11 @@ Config choose_config(const Geo& g, size_t cs /* bytes per complex */, size_t rs 
     c.v2_axis = d == 3 && v2_supported(g.L[1]);
     c.v2_mid = v2_supported(g.L[0]);
     c.rpb = 1;
-    for (int rpb = c.v2_row ? 16 : 32; rpb >= 1; rpb--) {
+    const int rpb_cap = env_int("FGH_RPB", c.v2_row ? 8 : 32);
+    for (int rpb = rpb_cap; rpb >= 1; rpb--) {
         const int npen = (rpb * d + 1) / 2;
-        const size_t lds = c.v2_row ? (size_t)(Ll + rpb * d * Ll) * cs + tabb
+        // specialised: twiddles + two complex row buffers of npen rows (+1 element each) + table
+        const size_t lds = c.v2_row ? (size_t)(Ll + npen * Ll + npen * (Ll + 1)) * cs + tabb
                                     : (size_t)(Ll + 2 * npen * Ll) * cs + tabb;
         if (lds <= kLdsBudget || rpb == 1) {
             c.rpb = rpb;
@@ -93,8 +104,10 @@ Config choose_config(const Geo& g, size_t cs /* bytes per complex */, size_t rs 
     const int Ps[5] = {16, 8, 4, 2, 1};
     c.P_axis = 1;
     c.lds_axis = 0;
+    const int pax_cap = env_int("FGH_P_AXIS", 16), pmid_cap = env_int("FGH_P_MID", 16);
     if (d == 3)
         for (int P : Ps) {
+            if (P > pax_cap) continue;
             const size_t lds = c.v2_axis ? (size_t)(g.L[1] + P * g.L[1]) * cs : (size_t)(g.L[1] + 2 * P * g.L[1]) * cs;
             if (lds <= kLdsBudget || P == 1) {
                 c.P_axis = P;
@@ -104,6 +117,7 @@ Config choose_config(const Geo& g, size_t cs /* bytes per complex */, size_t rs 
         }
     c.P_mid = 1;
     for (int P : Ps) {
+        if (P > pmid_cap) continue;
         const size_t lds = c.v2_mid ? (size_t)(g.L[0] + d * P * g.L[0]) * cs : (size_t)(g.L[0] + (d + 1) * P * g.L[0]) * cs;
         if (lds <= kLdsBudget || P == 1) {
             c.P_mid = P;
@@ -385,96 +399,95 @@ fgh_status rhs(fgh_plan p, const double* E, T* r, double* bb, double* ae2)
 struct SolveOut {
     int iters = 0;
     int status = FGH_OK;
-    double res = 0.0;   // stopping-test quantity at exit
+    double res = 0.0;   // stopping-test quantity at exit, relative to its scale
 };
 
-// Conjugate gradients (Algorithm 2) for C x = b with b already in r, x = 0 on entry.
-// The right-hand side norm^2 is bb (raw sum).  Stops when ||r|| <= tol_rel sqrt(bb).
+static_assert(sizeof(Scalars) <= 64 * sizeof(double), "pinned readback buffer too small");
+
+// Run loop bodies in chunks; the device decides when to stop (Scalars::done) and counts the
+// bodies, so the host synchronises once per chunk instead of once per body.
+template <typename Body>
+fgh_status run_loop(fgh_plan p, const OpPlan& op, Body body, bool fixed, double scale, SolveOut* out)
+{
+    int chunk = 4;
+    const Scalars* h = reinterpret_cast<const Scalars*>(p->host_buf);
+    for (;;) {
+        for (int k = 0; k < chunk; k++) HIPOK(body());
+        HIPOK(hipMemcpyAsync(p->host_buf, op.sc, sizeof(Scalars), hipMemcpyDeviceToHost, p->stream));
+        HIPOK(hipStreamSynchronize(p->stream));
+        if (h->done) break;
+        if (chunk < 32) chunk *= 2;
+    }
+    out->iters = h->m;
+    out->res = scale > 0 ? h->last / scale : h->last;
+    if (h->done == 3)
+        out->status = FGH_E_DIVERGED;
+    else if (h->done == 2 && !fixed)
+        out->status = FGH_E_NO_CONVERGENCE;
+    else
+        out->status = FGH_OK;
+    return FGH_OK;
+}
+
+// Conjugate gradients (Algorithm 2) for C x = b with b already in r, x = 0 on entry.  Stops when
+// ||r_m|| <= tol_rel ||b|| (recursive residual) or after `fixed` bodies.
 template <typename T>
-fgh_status cg_core(fgh_plan p, T* x, T* r, T* pv, T* q, double bb, double tol_rel, int max_iter, int fixed,
-                   SolveOut* out)
+fgh_status cg_core(fgh_plan p, T* x, T* r, T* pv, T* q, double tol_rel, int max_iter, int fixed, SolveOut* out)
 {
     const OpPlan& op = opp<T>(p);
     const long long n = (long long)p->d * p->g.npts;
-    HIPOK(run_copy<T>(p->stream, n, pv, r));
     const double S = (double)p->g.npts;
-    // (r, r) of the vector actually iterated on, also the device scalar the first alpha uses
+    HIPOK(run_copy<T>(p->stream, n, pv, r));
+    double bb = 0.0;
     {
         int nb = 0;
         HIPOK(run_dot<T>(op, n, r, r, &nb));
-        fgh_status st0 = reduce_read(p, op, nb, RED_SET_RR, &bb);
+        fgh_status st0 = reduce_read(p, op, nb, RED_TOTAL, &bb);
         if (st0) return st0;
     }
     const double normb = std::sqrt(bb / S);
-    out->iters = 0;
-    out->res = 1.0;
-    double rr = bb;
-    if (!(fixed > 0) && std::sqrt(rr / S) <= tol_rel * normb) {
-        out->res = std::sqrt(rr / S) / normb;
-        return FGH_OK;
-    }
     const int limit = fixed > 0 ? fixed : max_iter;
-    int m = 0;
-    while (m < limit) {
+    HIPOK(run_init_loop(op, bb, 0.0, 0.0, fixed > 0 ? -1.0 : tol_rel * normb, S, 0.0, 0.0, 0.0, limit));
+    auto body = [&]() -> hipError_t {
         ApplyArgs a;
-        a.op = m == 0 ? OP_AX : OP_AP_CG;
-        a.x = pv;
+        a.op = OP_AP_CG;  // p <- r + beta p (beta = 0 before the first body, p = r)
         a.p_cg = pv;
         a.r_cg = r;
         a.epi = EPI_CG;
         a.eq = q;
         a.ep = pv;
+        a.loop = true;
         int nb = 0;
-        HIPOK(run_apply<T>(op, a, &nb));
-        HIPOK(run_reduce_async(op, nb, RED_CG_ALPHA));
-        HIPOK(run_cg_update<T>(op, n, x, r, pv, q));
-        double rr_new;
-        fgh_status st = reduce_read(p, op, vec_blocks(), RED_CG_BETA, &rr_new);
-        if (st) return st;
-        m++;
-        out->res = std::sqrt(rr_new / S) / normb;
-        if (!std::isfinite(rr_new)) {
-            out->iters = m;
-            out->status = FGH_E_DIVERGED;
-            return FGH_OK;
-        }
-        if (!(fixed > 0) && std::sqrt(rr_new / S) <= tol_rel * normb) break;
-        rr = rr_new;
-    }
-    out->iters = m;
-    if (!(fixed > 0) && !(out->res <= tol_rel)) out->status = FGH_E_NO_CONVERGENCE;
-    return FGH_OK;
+        hipError_t e = run_apply<T>(op, a, &nb);
+        if (e != hipSuccess) return e;
+        if ((e = run_reduce_async(op, nb, RED_CG_ALPHA)) != hipSuccess) return e;
+        if ((e = run_cg_update<T>(op, n, x, r, pv, q)) != hipSuccess) return e;
+        return run_reduce_async(op, vec_blocks(), RED_CG_END);
+    };
+    return run_loop(p, op, body, fixed > 0, normb, out);
 }
 
 // Chebyshev semi-iteration (Algorithm 3), b in r, x = 0.
 template <typename T>
-fgh_status cheb_core(fgh_plan p, T* x, T* r, T* pv, double bb, double tol_rel, int max_iter, int fixed,
-                     SolveOut* out)
+fgh_status cheb_core(fgh_plan p, T* x, T* r, T* pv, double tol_rel, int max_iter, int fixed, SolveOut* out)
 {
     const OpPlan& op = opp<T>(p);
     const long long n = (long long)p->d * p->g.npts;
-    HIPOK(run_copy<T>(p->stream, n, pv, r));
     const double S = (double)p->g.npts;
+    HIPOK(run_copy<T>(p->stream, n, pv, r));
+    double bb = 0.0;
     {
         int nb = 0;
         HIPOK(run_dot<T>(op, n, r, r, &nb));
-        fgh_status st0 = reduce_read(p, op, nb, RED_SET_RR, &bb);
+        fgh_status st0 = reduce_read(p, op, nb, RED_TOTAL, &bb);
         if (st0) return st0;
     }
     const double normb = std::sqrt(bb / S);
-    out->iters = 0;
-    out->res = 1.0;
-    if (!(fixed > 0) && std::sqrt(bb / S) <= tol_rel * normb) return FGH_OK;
     const double c = 0.5 * (p->CA - p->cA), delta = 0.5 * (p->cA + p->CA);
-    double alpha = 1.0 / delta;
-    double beta = -0.5 * (c / delta) * (c / delta);
     const int limit = fixed > 0 ? fixed : max_iter;
-    int m = 0;
-    while (m < limit) {
-        if (m + 1 > 1) {
-            alpha = 1.0 / (delta + beta / alpha);
-            beta = -(c * alpha / 2.0) * (c * alpha / 2.0);
-        }
+    HIPOK(run_init_loop(op, bb, 1.0 / delta, -0.5 * (c / delta) * (c / delta), fixed > 0 ? -1.0 : tol_rel * normb, S,
+                        0.0, c, delta, limit));
+    auto body = [&]() -> hipError_t {
         ApplyArgs a;
         a.op = OP_AX;
         a.x = pv;
@@ -482,31 +495,17 @@ fgh_status cheb_core(fgh_plan p, T* x, T* r, T* pv, double bb, double tol_rel, i
         a.ex = x;
         a.er = r;
         a.ep = pv;
-        a.alpha = alpha;
-        a.beta = beta;
+        a.loop = true;
+        a.cheb_dev = true;
         int nb = 0;
-        HIPOK(run_apply<T>(op, a, &nb));
-        double rr;
-        fgh_status st = reduce_read(p, op, nb, RED_TOTAL, &rr);
-        if (st) return st;
-        m++;
-        out->res = std::sqrt(rr / S) / normb;
-        if (!std::isfinite(rr)) {
-            out->iters = m;
-            out->status = FGH_E_DIVERGED;
-            return FGH_OK;
-        }
-        if (!(fixed > 0) && std::sqrt(rr / S) <= tol_rel * normb) break;
-    }
-    out->iters = m;
-    if (!(fixed > 0) && !(out->res <= tol_rel)) out->status = FGH_E_NO_CONVERGENCE;
-    return FGH_OK;
+        hipError_t e = run_apply<T>(op, a, &nb);
+        if (e != hipSuccess) return e;
+        return run_reduce_async(op, nb, RED_CHEB_END);
+    };
+    return run_loop(p, op, body, fixed > 0, normb, out);
 }
 
-// Richardson (Algorithm 1) on C x = b with b = -G A E0 implicit: step = -w G A (E0 + x).
-// With E0 = 0 and an explicit right-hand side this is used as an inner solver only through
-// the Moulinec-Suquet form, so the driver passes the load E0; stops when
-// ||x_m - x_{m-1}|| <= thr.
+// Richardson (Algorithm 1): step = -w G A (E0 + x); stops when ||x_m - x_{m-1}|| <= thr.
 template <typename T>
 fgh_status rich_core(fgh_plan p, T* x, const double* E0, double thr, int max_iter, int fixed, double scale,
                      SolveOut* out)
@@ -514,11 +513,9 @@ fgh_status rich_core(fgh_plan p, T* x, const double* E0, double thr, int max_ite
     const OpPlan& op = opp<T>(p);
     const double S = (double)p->g.npts;
     const double omega = 2.0 / (p->cA + p->CA);
-    out->iters = 0;
-    out->res = 1.0;
     const int limit = fixed > 0 ? fixed : max_iter;
-    int m = 0;
-    while (m < limit) {
+    HIPOK(run_init_loop(op, 0.0, 0.0, 0.0, fixed > 0 ? -1.0 : thr, S, 0.0, 0.0, 0.0, limit));
+    auto body = [&]() -> hipError_t {
         ApplyArgs a;
         a.op = OP_AX;
         a.x = x;
@@ -526,24 +523,13 @@ fgh_status rich_core(fgh_plan p, T* x, const double* E0, double thr, int max_ite
         a.epi = EPI_RICH;
         a.ex = x;
         a.omega = omega;
+        a.loop = true;
         int nb = 0;
-        HIPOK(run_apply<T>(op, a, &nb));
-        double ss;
-        fgh_status st = reduce_read(p, op, nb, RED_TOTAL, &ss);
-        if (st) return st;
-        m++;
-        const double step = std::sqrt(ss / S);
-        out->res = scale > 0 ? step / scale : step;
-        if (!std::isfinite(step)) {
-            out->iters = m;
-            out->status = FGH_E_DIVERGED;
-            return FGH_OK;
-        }
-        if (!(fixed > 0) && step <= thr) break;
-    }
-    out->iters = m;
-    if (!(fixed > 0) && !(out->res * (scale > 0 ? scale : 1.0) <= thr)) out->status = FGH_E_NO_CONVERGENCE;
-    return FGH_OK;
+        hipError_t e = run_apply<T>(op, a, &nb);
+        if (e != hipSuccess) return e;
+        return run_reduce_async(op, nb, RED_STEP_END);
+    };
+    return run_loop(p, op, body, fixed > 0, scale, out);
 }
 
 // Eyre-Milton (Algorithm 4).  Plain form (src == NULL): x holds E + e; correction form
@@ -555,11 +541,10 @@ fgh_status em_core(fgh_plan p, T* x, const double* E, const T* src, double thr, 
     const OpPlan& op = opp<T>(p);
     const double S = (double)p->g.npts;
     const double omega = std::sqrt(p->cA * p->CA);
-    out->iters = 0;
-    out->res = 1.0;
     const int limit = fixed > 0 ? fixed : max_iter;
-    int m = 0;
-    while (m < limit) {
+    HIPOK(run_init_loop(op, 0.0, 0.0, 0.0, fixed > 0 ? -1.0 : thr, S, 1e12 * (scale > 0 ? scale : 1.0), 0.0, 0.0,
+                        limit));
+    auto body = [&]() -> hipError_t {
         ApplyArgs a;
         a.op = OP_EM;
         a.x = x;
@@ -569,24 +554,13 @@ fgh_status em_core(fgh_plan p, T* x, const double* E, const T* src, double thr, 
         a.ex = x;
         a.src = src;
         for (int c = 0; c < p->d; c++) a.E[c] = E[c];
+        a.loop = true;
         int nb = 0;
-        HIPOK(run_apply<T>(op, a, &nb));
-        double ss;
-        fgh_status st = reduce_read(p, op, nb, RED_TOTAL, &ss);
-        if (st) return st;
-        m++;
-        const double step = std::sqrt(ss / S);
-        out->res = scale > 0 ? step / scale : step;
-        if (!std::isfinite(step) || step > 1e12 * (scale > 0 ? scale : 1.0)) {
-            out->iters = m;
-            out->status = FGH_E_DIVERGED;
-            return FGH_OK;
-        }
-        if (!(fixed > 0) && step <= thr) break;
-    }
-    out->iters = m;
-    if (!(fixed > 0) && !(out->res * (scale > 0 ? scale : 1.0) <= thr)) out->status = FGH_E_NO_CONVERGENCE;
-    return FGH_OK;
+        hipError_t e = run_apply<T>(op, a, &nb);
+        if (e != hipSuccess) return e;
+        return run_reduce_async(op, nb, RED_STEP_END);
+    };
+    return run_loop(p, op, body, fixed > 0, scale, out);
 }
 
 // ||b - C e|| / ||b|| for the fluctuation e (double): apply C to (E + e) and compare with 0.
@@ -627,9 +601,9 @@ fgh_status solve_one_fp64(fgh_plan p, int solver, const double* E, double tol, i
             so.iters = 0;
             so.res = 0.0;
         } else if (solver == FGH_CG) {
-            if ((s = cg_core<double>(p, e, p->r64, p->p64, p->q64, bb, tol, max_iter, fixed, &so))) return s;
+            if ((s = cg_core<double>(p, e, p->r64, p->p64, p->q64, tol, max_iter, fixed, &so))) return s;
         } else {
-            if ((s = cheb_core<double>(p, e, p->r64, p->p64, bb, tol, max_iter, fixed, &so))) return s;
+            if ((s = cheb_core<double>(p, e, p->r64, p->p64, tol, max_iter, fixed, &so))) return s;
         }
     } else if (solver == FGH_RICHARDSON) {
         HIPOK(run_fill<double>(p->stream, n, e, 0.0));
@@ -760,9 +734,9 @@ fgh_status solve_one_refined(fgh_plan p, int solver, const double* E, double tol
                 HIPOK(run_fill<float>(p->stream, n, p->x32, 0.0f));
                 SolveOut so;
                 if (solver == FGH_CG) {
-                    if ((s = cg_core<float>(p, p->x32, p->r32, p->p32, p->q32, rr, eta, max_iter, 0, &so))) return s;
+                    if ((s = cg_core<float>(p, p->x32, p->r32, p->p32, p->q32, eta, max_iter, 0, &so))) return s;
                 } else {
-                    if ((s = cheb_core<float>(p, p->x32, p->r32, p->p32, rr, eta, max_iter, 0, &so))) return s;
+                    if ((s = cheb_core<float>(p, p->x32, p->r32, p->p32, eta, max_iter, 0, &so))) return s;
                 }
                 inner_total += so.iters;
                 if (so.status == FGH_E_DIVERGED) {

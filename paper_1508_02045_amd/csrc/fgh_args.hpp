@@ -81,6 +81,7 @@ __device__ __forceinline__ void sym_shift_solve(const T* a, T w, const T* rhs, T
 
 template <typename T>
 struct FirstArgs {
+    const int* done;  // the loop's stop flag (nullptr: always run)
     Geo g;
     Axis ax;
     int rpb, npen;
@@ -97,6 +98,7 @@ struct FirstArgs {
 
 template <typename T>
 struct AxisArgs {
+    const int* done;  // the loop's stop flag (nullptr: always run)
     Axis ax;
     int nin, nout;          // stored counts along the axis
     int bin, bout;          // 1: stored index is a band index (frequency signed(s, n)), 0: position
@@ -109,6 +111,7 @@ struct AxisArgs {
 
 template <typename T>
 struct MidArgs {
+    const int* done;  // the loop's stop flag (nullptr: always run)
     Axis ax;
     int B0, cols, Hb, B1, P, ntiles;
     long long cs;
@@ -119,6 +122,8 @@ struct MidArgs {
 
 template <typename T>
 struct LastArgs {
+    const int* done;  // the loop's stop flag (nullptr: always run)
+    const Scalars* sc;  // Chebyshev alpha, beta (device) when non-null
     Geo g;
     Axis ax;
     int rpb, npen;

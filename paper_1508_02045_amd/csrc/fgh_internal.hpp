@@ -68,22 +68,35 @@ enum Epi : int {
     EPI_EM = 4      // x_new = (A + wI)^{-1} (y + 2 w E); acc += |x_new - x|^2; x = x_new
 };
 
-// Device-resident solver scalars (double).
+// Device-resident solver state.  The loop kernels of an iteration return at once when done != 0,
+// so the host can enqueue iterations in chunks and synchronise once per chunk: iterations after
+// the stopping test fired are no-ops and the count m stays exact.
 struct Scalars {
-    double rr;      // (r, r) of the current residual
+    double rr;          // (r, r) of the current residual (raw sum over the grid)
     double rr_new;
-    double qp;      // (C p, p)
+    double qp;          // (C p, p)
     double alpha;
     double beta;
-    double total;   // last reduced value
+    double total;       // last reduced value
+    double thr;         // stop when sqrt(value / npts) <= thr (value: (r,r) or |step|^2); < 0: never
+    double npts;
+    double blowup;      // diverged when sqrt(value / npts) > blowup (0: only non-finite values)
+    double cheb_c, cheb_delta;  // Chebyshev interval half-width and centre
+    double last;        // the stopping-test quantity sqrt(value / npts) of the last body
+    int done;           // 0 running, 1 stopping test met, 2 iteration cap, 3 diverged
+    int m;              // loop bodies executed
+    int limit;          // cap on m
+    int pad;
     double aux[40];     // [0, 16): loads for fgh_effective; [16, 40): multi-value reductions
 };
 
 enum RedOp : int {
     RED_TOTAL = 0,     // total -> s.total
     RED_CG_ALPHA = 1,  // s.qp = total; s.alpha = s.rr / s.qp
-    RED_CG_BETA = 2,   // s.rr_new = total; s.beta = s.rr_new / s.rr; s.rr = s.rr_new
-    RED_SET_RR = 3     // s.rr = total
+    RED_CG_END = 2,    // s.rr_new = total; s.beta = s.rr_new / s.rr; s.rr = s.rr_new; end of a body
+    RED_SET_RR = 3,    // s.rr = total
+    RED_STEP_END = 4,  // total = |step|^2 (Richardson, Eyre-Milton); end of a body
+    RED_CHEB_END = 5   // total = (r, r); end of a body; next alpha, beta of Algorithm 3
 };
 
 struct CoefArgs {

@@ -16,6 +16,7 @@ namespace fgh {
 template <typename T, int D, int AK, int OP>
 __global__ __launch_bounds__(kThreads) void k_first(FirstArgs<T> a)
 {
+    if (a.done && *a.done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const int L = a.ax.L;
     const int npen = a.npen;
@@ -109,6 +110,7 @@ __global__ __launch_bounds__(kThreads) void k_first(FirstArgs<T> a)
 template <typename T, bool INV>
 __global__ __launch_bounds__(kThreads) void k_axis(AxisArgs<T> a)
 {
+    if (a.done && *a.done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const int L = a.ax.L;
     const int P = a.P;
@@ -153,6 +155,7 @@ __global__ __launch_bounds__(kThreads) void k_axis(AxisArgs<T> a)
 template <typename T, int D, int MULT>
 __global__ __launch_bounds__(kThreads) void k_middle(MidArgs<T> a)
 {
+    if (a.done && *a.done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const int L = a.ax.L;
     const int P = a.P;
@@ -255,6 +258,7 @@ __global__ __launch_bounds__(kThreads) void k_middle(MidArgs<T> a)
 template <typename T, int D, int AK, int EPI>
 __global__ __launch_bounds__(kThreads) void k_last(LastArgs<T> a)
 {
+    if (a.done && *a.done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const int L = a.ax.L;
     const int npen = a.npen;
@@ -339,7 +343,7 @@ __global__ __launch_bounds__(kThreads) void k_last(LastArgs<T> a)
                 acc += double(y[c]) * double(a.p[c * npts + pt]);
             }
         } else if (EPI == EPI_CHEB) {
-            const T al = T(a.alpha), be = T(a.beta);
+            const T al = T(a.sc ? a.sc->alpha : a.alpha), be = T(a.sc ? a.sc->beta : a.beta);
 #pragma unroll
             for (int c = 0; c < D; c++) {
                 const long long o = c * npts + pt;
@@ -391,9 +395,24 @@ __global__ __launch_bounds__(kThreads) void k_last(LastArgs<T> a)
 // ------------------------------------------------------------------------------------------
 // Reductions and vector kernels.
 // ------------------------------------------------------------------------------------------
+__device__ __forceinline__ void end_body(Scalars* s, double v)
+{
+    s->m += 1;
+    const double q = sqrt(v / s->npts);
+    s->last = q;
+    if (!(v == v) || v > 1.0e300 || (s->blowup > 0.0 && q > s->blowup))
+        s->done = 3;
+    else if (s->thr >= 0.0 && q <= s->thr)
+        s->done = 1;
+    else if (s->m >= s->limit)
+        s->done = 2;
+}
+
 __global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ partials, int n, Scalars* s, int op)
 {
     __shared__ double red[kThreads / 64];
+    const bool in_loop = op == RED_CG_ALPHA || op == RED_CG_END || op == RED_STEP_END || op == RED_CHEB_END;
+    if (in_loop && s->done) return;
     double v = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) v += partials[i];
     const double tot = block_sum(v, red);
@@ -402,14 +421,41 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ 
         if (op == RED_CG_ALPHA) {
             s->qp = tot;
             s->alpha = s->rr / tot;
-        } else if (op == RED_CG_BETA) {
+        } else if (op == RED_CG_END) {
             s->rr_new = tot;
             s->beta = tot / s->rr;
             s->rr = tot;
+            end_body(s, tot);
         } else if (op == RED_SET_RR) {
             s->rr = tot;
+        } else if (op == RED_STEP_END) {
+            end_body(s, tot);
+        } else if (op == RED_CHEB_END) {
+            end_body(s, tot);
+            // Algorithm 3: alpha, beta of the next body
+            const double al = 1.0 / (s->cheb_delta + s->beta / s->alpha);
+            s->alpha = al;
+            s->beta = -(s->cheb_c * al * 0.5) * (s->cheb_c * al * 0.5);
         }
     }
+}
+
+// Start a solver loop: m = 0, done = 0 and the loop's constants (no memset: a plain kernel).
+__global__ void k_init_loop(Scalars* s, double rr, double alpha, double beta, double thr, double npts, double blowup,
+                            double cheb_c, double cheb_delta, int limit)
+{
+    s->rr = rr;
+    s->alpha = alpha;
+    s->beta = beta;
+    s->thr = thr;
+    s->npts = npts;
+    s->blowup = blowup;
+    s->cheb_c = cheb_c;
+    s->cheb_delta = cheb_delta;
+    s->done = 0;
+    s->m = 0;
+    s->limit = limit;
+    s->last = 0.0;
 }
 
 // Reduce nvals interleaved partial sums [nblocks][nvals] (fixed order).
@@ -434,6 +480,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(long long n, T* __restri
                                                         const Scalars* s, double* partials)
 {
     __shared__ double red[kThreads / 64];
+    if (s->done) return;
     const T alpha = T(s->alpha);
     double acc = 0.0;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
@@ -450,6 +497,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_cg_p(long long n, T* __restrict__ p, const T* __restrict__ r,
                                                    const Scalars* s)
 {
+    if (s->done) return;
     const T beta = T(s->beta);
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         p[i] = r[i] + beta * p[i];
@@ -934,7 +982,7 @@ static hipError_t launch_axis(const OpPlan& op, const AxisArgs<T>& xa, bool inv,
 }
 
 // Size-specialised launches (lengths listed in kSplits).
-#define V2_ROW_CASES(X) X(45, 9, 5) X(63, 7, 9) X(81, 9, 9) X(125, 25, 5) X(135, 15, 9) X(243, 27, 9)
+#define V2_ROW_CASES(X) X(45, 5, 9) X(63, 7, 9) X(81, 9, 9) X(125, 5, 25) X(135, 9, 15) X(243, 9, 27)
 #define V2_COL_CASES(X) X(45, 5, 9) X(63, 7, 9) X(81, 9, 9) X(125, 5, 25) X(135, 9, 15) X(243, 9, 27)
 
 template <typename T, int D>
@@ -951,18 +999,31 @@ static hipError_t v2_first(const OpPlan& op, const FirstArgs<T>& fa, int opc, un
     return hipGetLastError();
 }
 
-template <typename T, int D>
-static hipError_t v2_last(const OpPlan& op, const LastArgs<T>& la, int epi, unsigned nblk)
+template <typename T, int D, int EPI>
+static hipError_t v2_last_epi(const OpPlan& op, const LastArgs<T>& la, unsigned nblk)
 {
     const size_t lds = op.lds_first;
     switch (la.ax.L) {
 #define C(LL, A1, A2) \
-    case LL: LAUNCH_LDS((k2_last<T, D, A1, A2>), dim3(nblk), lds, op.stream, la, epi); break;
+    case LL: LAUNCH_LDS((k2_last<T, D, A1, A2, EPI>), dim3(nblk), lds, op.stream, la); break;
         V2_ROW_CASES(C)
 #undef C
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename T, int D>
+static hipError_t v2_last(const OpPlan& op, const LastArgs<T>& la, int epi, unsigned nblk)
+{
+    switch (epi) {
+        case EPI_STORE: return v2_last_epi<T, D, EPI_STORE>(op, la, nblk);
+        case EPI_RICH: return v2_last_epi<T, D, EPI_RICH>(op, la, nblk);
+        case EPI_CG: return v2_last_epi<T, D, EPI_CG>(op, la, nblk);
+        case EPI_CHEB: return v2_last_epi<T, D, EPI_CHEB>(op, la, nblk);
+        case EPI_EM: return v2_last_epi<T, D, EPI_EM>(op, la, nblk);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T, int D>
@@ -1018,6 +1079,8 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     fa.p = static_cast<T*>(a.p_cg);
     fa.r = static_cast<const T*>(a.r_cg);
     fa.sc = op.sc;
+    const int* done = a.loop ? &op.sc->done : nullptr;
+    fa.done = done;
     for (int c = 0; c < 3; c++) fa.E[c] = a.E[c];
     fa.omega = a.omega;
     fa.A = op.A;
@@ -1046,6 +1109,7 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
         xa.in = SA;
         xa.out = SB;
         xa.twg = static_cast<const cpx<T>*>(op.tw[1]);
+        xa.done = done;
         if (op.prof && (e = op.prof->begin(PK_AXIS_FWD)) != hipSuccess) return e;
         if ((e = op.v2_axis ? v2_axis<T>(op, xa, false, g.L[0], g.B[1]) : launch_axis<T>(op, xa, false, g.L[0])) != hipSuccess)
             return e;
@@ -1065,6 +1129,7 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     ma.scale = 1.0 / (double)g.npts;
     ma.buf = mid;
     ma.twg = static_cast<const cpx<T>*>(op.tw[0]);
+    ma.done = done;
     if (op.prof && (e = op.prof->begin(PK_MIDDLE)) != hipSuccess) return e;
     if ((e = op.v2_mid ? v2_middle<T, D>(op, ma, a.mult) : launch_middle<T, D>(op, ma, a.mult)) != hipSuccess) return e;
     if (op.prof && (e = op.prof->end()) != hipSuccess) return e;
@@ -1086,6 +1151,7 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
         xa.in = SB;
         xa.out = SA;
         xa.twg = static_cast<const cpx<T>*>(op.tw[1]);
+        xa.done = done;
         if (op.prof && (e = op.prof->begin(PK_AXIS_INV)) != hipSuccess) return e;
         if ((e = op.v2_axis ? v2_axis<T>(op, xa, true, g.L[0], g.B[1]) : launch_axis<T>(op, xa, true, g.L[0])) != hipSuccess)
             return e;
@@ -1112,6 +1178,8 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     la.A = op.A;
     la.partials = op.partials;
     la.twg = static_cast<const cpx<T>*>(op.tw[last]);
+    la.done = done;
+    la.sc = a.cheb_dev ? op.sc : nullptr;
     if (op.prof && (e = op.prof->begin(PK_LAST)) != hipSuccess) return e;
     if ((e = op.v2_row ? v2_last<T, D>(op, la, a.epi, nblk) : launch_last<T, D>(op, la, a.epi, nblk)) != hipSuccess)
         return e;
@@ -1128,6 +1196,14 @@ hipError_t run_apply(const OpPlan& op, const ApplyArgs& a, int* nblocks_last)
 }
 template hipError_t run_apply<float>(const OpPlan&, const ApplyArgs&, int*);
 template hipError_t run_apply<double>(const OpPlan&, const ApplyArgs&, int*);
+
+hipError_t run_init_loop(const OpPlan& op, double rr, double alpha, double beta, double thr, double npts,
+                         double blowup, double cheb_c, double cheb_delta, int limit)
+{
+    hipLaunchKernelGGL(k_init_loop, dim3(1), dim3(1), 0, op.stream, op.sc, rr, alpha, beta, thr, npts, blowup, cheb_c,
+                       cheb_delta, limit);
+    return hipGetLastError();
+}
 
 hipError_t run_set_scalar(const OpPlan& op, double* dst, double v)
 {

@@ -59,6 +59,8 @@ struct ApplyArgs {
     void* ep = nullptr;
     void* eq = nullptr;
     const void* src = nullptr; // EPI_EM: additive source field (refinement); nullptr: 2 w E
+    bool loop = false;       // part of a solver loop: kernels skip work once the stop flag is set
+    bool cheb_dev = false;   // Chebyshev alpha, beta from the device scalars
 };
 
 template <typename T>
@@ -67,6 +69,8 @@ hipError_t run_apply(const OpPlan& op, const ApplyArgs& a, int* nblocks_last);
 hipError_t run_reduce(const OpPlan& op, int n, int redop, double* host_out);
 hipError_t run_reduce_async(const OpPlan& op, int n, int redop);
 hipError_t run_set_scalar(const OpPlan& op, double* dst, double v);
+hipError_t run_init_loop(const OpPlan& op, double rr, double alpha, double beta, double thr, double npts,
+                         double blowup, double cheb_c, double cheb_delta, int limit);
 
 int vec_blocks();
 template <typename T>

@@ -124,91 +124,259 @@ __device__ __forceinline__ void coef_shift_solve_rt(const CoefArgs& A, const T* 
     }
 }
 
-// First-pass operand z at one point (FirstOp, runtime).
-template <typename T, int D>
-__device__ __forceinline__ void first_operand(const FirstArgs<T>& a, int op, const T* tab, T beta, long long pt,
-                                              T* z)
+// Batched point processing: the loads of kU points per thread are all issued before any of them
+// is used, so one memory latency covers kU points (a loop with a runtime trip count would wait
+// once per point).  The operation and coefficient kind are uniform across the launch, so their
+// branches sit outside the unrolled point loops; out-of-range points load from point 0 and are
+// discarded.
+constexpr int kU = 4;
+
+// Stage 0 of the first pass for kU points starting at this thread's index base + threadIdx.x:
+// z = A(pt) u with u per FirstOp; writes the real rows Zr[(r D + c) L + i].
+template <typename T, int D, int L>
+__device__ __forceinline__ void first_stage0_chunk(const FirstArgs<T>& a, int op, const T* tab, T beta, int base,
+                                                   int total, long long pt0, long long ptend, T* Zr)
 {
     const long long npts = a.g.npts;
-    T u[D];
+    long long pt[kU];
+    bool ok[kU];
 #pragma unroll
-    for (int c = 0; c < D; c++) {
-        if (op == OP_AX)
-            u[c] = a.x[c * npts + pt] + T(a.E[c]);
-        else if (op == OP_E)
-            u[c] = T(a.E[c]);
-        else if (op == OP_AP_CG) {
-            const T pn = a.r[c * npts + pt] + beta * a.p[c * npts + pt];
-            a.p[c * npts + pt] = pn;
-            u[c] = pn;
-        } else
-            u[c] = a.x[c * npts + pt];
+    for (int u = 0; u < kU; u++) {
+        const int idx = base + u * (int)blockDim.x + (int)threadIdx.x;
+        ok[u] = idx < total && pt0 + idx < ptend;
+        pt[u] = ok[u] ? pt0 + idx : 0;
     }
+    T uu[kU][D];
+    if (op == OP_E) {
+#pragma unroll
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) uu[u][c] = T(a.E[c]);
+    } else if (op == OP_AP_CG) {
+        T rr[kU][D], pp[kU][D];
+#pragma unroll
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                rr[u][c] = a.r[c * npts + pt[u]];
+                pp[u][c] = a.p[c * npts + pt[u]];
+            }
+#pragma unroll
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                uu[u][c] = rr[u][c] + beta * pp[u][c];
+                if (ok[u]) a.p[c * npts + pt[u]] = uu[u][c];
+            }
+    } else {
+#pragma unroll
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) uu[u][c] = a.x[c * npts + pt[u]];
+        if (op == OP_AX) {
+#pragma unroll
+            for (int u = 0; u < kU; u++)
+#pragma unroll
+                for (int c = 0; c < D; c++) uu[u][c] += T(a.E[c]);
+        }
+    }
+    T z[kU][D];
     if (op == OP_ID) {
 #pragma unroll
-        for (int c = 0; c < D; c++) z[c] = u[c];
-        return;
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) z[u][c] = uu[u][c];
+    } else if (a.A.kind == AK_PHASE) {
+        int ph[kU];
+#pragma unroll
+        for (int u = 0; u < kU; u++) ph[u] = a.A.phase[pt[u]];
+#pragma unroll
+        for (int u = 0; u < kU; u++) sym_mul<T, D>(tab + 6 * ph[u], uu[u], z[u]);
+    } else if (a.A.kind == AK_ISO) {
+        const T* cc = static_cast<const T*>(a.A.coef);
+        T co[kU];
+#pragma unroll
+        for (int u = 0; u < kU; u++) co[u] = cc[pt[u]];
+#pragma unroll
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) z[u][c] = co[u] * uu[u][c];
+    } else {
+        const T* cc = static_cast<const T*>(a.A.coef);
+        T co[kU][6];
+#pragma unroll
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int q = 0; q < ncoef_of<D>(); q++) co[u][q] = cc[q * npts + pt[u]];
+#pragma unroll
+        for (int u = 0; u < kU; u++) sym_mul<T, D>(co[u], uu[u], z[u]);
     }
-    coef_mul_rt<T, D>(a.A, tab, pt, npts, u, z);
     if (op == OP_EM) {
 #pragma unroll
-        for (int c = 0; c < D; c++) z[c] -= T(a.omega) * u[c];
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) z[u][c] -= T(a.omega) * uu[u][c];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+        const int idx = base + u * (int)blockDim.x + (int)threadIdx.x;
+        if (idx < total) {
+            const int r = idx / L;
+            const int i = idx - r * L;
+#pragma unroll
+            for (int c = 0; c < D; c++) Zr[(r * D + c) * L + i] = ok[u] ? z[u][c] : T(0);
+        }
     }
 }
 
-// Solver epilogue at one point (Epi, runtime); returns the point's contribution to the sum.
-template <typename T, int D>
-__device__ __forceinline__ double last_epilogue(const LastArgs<T>& a, int epi, const T* tabinv, long long pt,
-                                                const T* y)
+// Epilogue of the last pass for kU points: y from the real rows Zr, the solver update per Epi.
+template <typename T, int D, int L, int epi>
+__device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, const T* tabinv, int base,
+                                                      int total, long long pt0, long long ptend, const T* Zr)
 {
     const long long npts = a.g.npts;
+    long long pt[kU];
+    bool ok[kU];
+    T y[kU][D];
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+        const int idx = base + u * (int)blockDim.x + (int)threadIdx.x;
+        ok[u] = idx < total && pt0 + idx < ptend;
+        pt[u] = ok[u] ? pt0 + idx : 0;
+        const int ii = ok[u] ? idx : 0;
+        const int r = ii / L;
+        const int i = ii - r * L;
+#pragma unroll
+        for (int c = 0; c < D; c++) y[u][c] = Zr[(r * D + c) * L + i];
+    }
     double acc = 0.0;
-    if (epi == EPI_STORE) {
+    if constexpr (epi == EPI_STORE) {
+        const T sg = T(a.sgn);
 #pragma unroll
-        for (int c = 0; c < D; c++) {
-            const T v = T(a.sgn) * y[c];
-            a.y[c * npts + pt] = v;
-            acc += double(v) * double(v);
-        }
-    } else if (epi == EPI_RICH) {
+        for (int u = 0; u < kU; u++)
 #pragma unroll
-        for (int c = 0; c < D; c++) {
-            const T s = T(-a.omega) * y[c];
-            a.x[c * npts + pt] += s;
-            acc += double(s) * double(s);
-        }
-    } else if (epi == EPI_CG) {
+            for (int c = 0; c < D; c++) {
+                const T v = sg * y[u][c];
+                if (ok[u]) {
+                    a.y[c * npts + pt[u]] = v;
+                    acc += double(v) * double(v);
+                }
+            }
+    } else if constexpr (epi == EPI_RICH) {
+        T xv[kU][D];
 #pragma unroll
-        for (int c = 0; c < D; c++) {
-            a.q[c * npts + pt] = y[c];
-            acc += double(y[c]) * double(a.p[c * npts + pt]);
-        }
-    } else if (epi == EPI_CHEB) {
-        const T al = T(a.alpha), be = T(a.beta);
+        for (int u = 0; u < kU; u++)
 #pragma unroll
-        for (int c = 0; c < D; c++) {
-            const long long o = c * npts + pt;
-            const T pv = a.p[o];
-            const T rv = a.r[o] - al * y[c];
-            a.r[o] = rv;
-            a.x[o] += al * pv;
-            a.p[o] = rv - be * pv;
-            acc += double(rv) * double(rv);
-        }
+            for (int c = 0; c < D; c++) xv[u][c] = a.x[c * npts + pt[u]];
+        const T w = T(-a.omega);
+#pragma unroll
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                const T st = w * y[u][c];
+                if (ok[u]) {
+                    a.x[c * npts + pt[u]] = xv[u][c] + st;
+                    acc += double(st) * double(st);
+                }
+            }
+    } else if constexpr (epi == EPI_CG) {
+        T pv[kU][D];
+#pragma unroll
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) pv[u][c] = a.p[c * npts + pt[u]];
+#pragma unroll
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++)
+                if (ok[u]) {
+                    a.q[c * npts + pt[u]] = y[u][c];
+                    acc += double(y[u][c]) * double(pv[u][c]);
+                }
+    } else if constexpr (epi == EPI_CHEB) {
+        T xv[kU][D], rv[kU][D], pv[kU][D];
+#pragma unroll
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                const long long o = c * npts + pt[u];
+                xv[u][c] = a.x[o];
+                rv[u][c] = a.r[o];
+                pv[u][c] = a.p[o];
+            }
+        const T al = T(a.sc ? a.sc->alpha : a.alpha), be = T(a.sc ? a.sc->beta : a.beta);
+#pragma unroll
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                const T rn = rv[u][c] - al * y[u][c];
+                if (ok[u]) {
+                    const long long o = c * npts + pt[u];
+                    a.r[o] = rn;
+                    a.x[o] = xv[u][c] + al * pv[u][c];
+                    a.p[o] = rn - be * pv[u][c];
+                    acc += double(rn) * double(rn);
+                }
+            }
     } else {  // EPI_EM
+        T xv[kU][D], sv[kU][D];
+#pragma unroll
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                const long long o = c * npts + pt[u];
+                xv[u][c] = a.x[o];
+                sv[u][c] = a.src ? a.src[o] : T(2.0 * a.omega * a.E[c]);
+            }
         const T w = T(a.omega);
-        T v[D], xn[D];
+        T xn[kU][D];
+        if (a.A.kind == AK_PHASE) {
+            int ph[kU];
 #pragma unroll
-        for (int c = 0; c < D; c++) v[c] = a.src ? y[c] : y[c] + T(2.0 * a.omega * a.E[c]);
-        coef_shift_solve_rt<T, D>(a.A, tabinv, w, pt, npts, v, xn);
+            for (int u = 0; u < kU; u++) ph[u] = a.A.phase[pt[u]];
 #pragma unroll
-        for (int c = 0; c < D; c++) {
-            const long long o = c * npts + pt;
-            if (a.src) xn[c] += a.src[o];
-            const T s = xn[c] - a.x[o];
-            a.x[o] = xn[c];
-            acc += double(s) * double(s);
+            for (int u = 0; u < kU; u++) {
+                T v[D];
+#pragma unroll
+                for (int c = 0; c < D; c++) v[c] = a.src ? y[u][c] : y[u][c] + sv[u][c];
+                sym_mul<T, D>(tabinv + 6 * ph[u], v, xn[u]);
+            }
+        } else if (a.A.kind == AK_ISO) {
+            const T* cc = static_cast<const T*>(a.A.coef);
+            T co[kU];
+#pragma unroll
+            for (int u = 0; u < kU; u++) co[u] = cc[pt[u]];
+#pragma unroll
+            for (int u = 0; u < kU; u++)
+#pragma unroll
+                for (int c = 0; c < D; c++) xn[u][c] = (a.src ? y[u][c] : y[u][c] + sv[u][c]) / (co[u] + w);
+        } else {
+            const T* cc = static_cast<const T*>(a.A.coef);
+            T co[kU][6];
+#pragma unroll
+            for (int u = 0; u < kU; u++)
+#pragma unroll
+                for (int q = 0; q < ncoef_of<D>(); q++) co[u][q] = cc[q * npts + pt[u]];
+#pragma unroll
+            for (int u = 0; u < kU; u++) {
+                T v[D];
+#pragma unroll
+                for (int c = 0; c < D; c++) v[c] = a.src ? y[u][c] : y[u][c] + sv[u][c];
+                sym_shift_solve<T, D>(co[u], w, v, xn[u]);
+            }
         }
+#pragma unroll
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                T xnew = xn[u][c];
+                if (a.src) xnew += sv[u][c];
+                const T st = xnew - xv[u][c];
+                if (ok[u]) {
+                    a.x[c * npts + pt[u]] = xnew;
+                    acc += double(st) * double(st);
+                }
+            }
     }
     return acc;
 }
@@ -224,76 +392,101 @@ __device__ __forceinline__ bool band_index(int pos, int L, int B, int* s)
 }
 
 // ------------------------------------------------------------------------------------------
-// Pass 1 (rows of the last axis): z = A(x) op x, forward DFT, keep k < Hb.
-// Step A jobs (row r, n1) hold the d components; step B jobs (r, c, k2).
+// Workgroup -> tile mapping.  Workgroups are dispatched round-robin over the 8 XCDs (each with
+// its own L2); giving every XCD a contiguous range of tiles keeps neighbouring tiles, which share
+// cache lines at their edges, on the same L2.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ long long xcd_tile(long long b, long long nb)
+{
+    const long long q = nb >> 3, r = nb & 7;
+    const long long x = b & 7, slot = b >> 3;
+    return x * q + (x < r ? x : r) + slot;
+}
+
+// ------------------------------------------------------------------------------------------
+// Pass 1 (rows of the last axis), all global accesses whole-row contiguous:
+//   stage 0  coalesced loads, z = A(x) op x per point -> LDS (real rows)
+//   stage A  two real rows (pencils 2m, 2m+1) packed as one complex row, L2-point DFTs -> Y
+//   stage B  L1-point DFTs -> the full complex spectrum X of the packed row (LDS)
+//   stage S  split into the two real spectra, A(k) = (X(k) + conj X(L-k)) / 2,
+//            B(k) = (X(k) - conj X(L-k)) / 2i, and store k < Hb row by row.
+// LDS: twiddles | Y (npairs rows) | Zr reals (2 npairs rows), reused as X (npairs rows).
 // ------------------------------------------------------------------------------------------
 template <typename T, int D, int L1, int L2>
 __global__ __launch_bounds__(kThreads) void k2_first(FirstArgs<T> a, int op)
 {
+    if (a.done && *a.done) return;
     constexpr int L = L1 * L2;
     extern __shared__ __align__(16) unsigned char smem[];
+    const int npairs = (a.rpb * D + 1) / 2;
     cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
     cpx<T>* Y = tw + L;
-    T* tab = reinterpret_cast<T*>(Y + a.rpb * D * L);
+    cpx<T>* X = Y + npairs * L;
+    T* Zr = reinterpret_cast<T*>(X);
+    T* tab = reinterpret_cast<T*>(X + npairs * L);
     for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
     if (a.A.kind == AK_PHASE)
         for (int m = threadIdx.x; m < kMaxPhases * 6; m += blockDim.x) tab[m] = T(a.A.tab[m / 6][m % 6]);
+    if ((a.rpb * D) & 1)
+        for (int i = threadIdx.x; i < L; i += blockDim.x) Zr[(2 * npairs - 1) * L + i] = T(0);
     __syncthreads();
-    const long long row0 = (long long)blockIdx.x * a.rpb;
+    const long long row0 = xcd_tile(blockIdx.x, gridDim.x) * a.rpb;
     const T beta = (op == OP_AP_CG) ? T(a.sc->beta) : T(0);
-    for (int job = threadIdx.x; job < a.rpb * L1; job += blockDim.x) {
-        const int r = job / L1;
-        const int n1 = job - r * L1;
-        const long long row = row0 + r;
-        cpx<T> s[D][L2];
-        if (row < a.g.rows) {
+    {
+        const int total = a.rpb * L;
+        const long long pt0 = row0 * L;
+        const long long ptend = a.g.rows * (long long)L;
+        for (int base = 0; base < total; base += kU * blockDim.x)
+            first_stage0_chunk<T, D, L>(a, op, tab, beta, base, total, pt0, ptend, Zr);
+    }
+    __syncthreads();
+    for (int job = threadIdx.x; job < npairs * L1; job += blockDim.x) {
+        const int m = job / L1;
+        const int n1 = job - m * L1;
+        const T* z0 = Zr + (2 * m) * L + n1;
+        const T* z1 = z0 + L;
+        cpx<T> sv[L2];
 #pragma unroll
-            for (int n2 = 0; n2 < L2; n2++) {
-                T z[D];
-                first_operand<T, D>(a, op, tab, beta, row * L + n1 + L1 * n2, z);
+        for (int n2 = 0; n2 < L2; n2++) sv[n2] = {z0[L1 * n2], z1[L1 * n2]};
+        reg_dft<T, L2, false>(sv);
+        cpx<T>* y = Y + m * L + n1 * L2;
+        int w = 0;
 #pragma unroll
-                for (int c = 0; c < D; c++) s[c][n2] = {z[c], T(0)};
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < D; c++)
-#pragma unroll
-                for (int n2 = 0; n2 < L2; n2++) s[c][n2] = {T(0), T(0)};
-        }
-#pragma unroll
-        for (int c = 0; c < D; c++) {
-            reg_dft<T, L2, false>(s[c]);
-            cpx<T>* y = Y + (r * D + c) * L + n1 * L2;
-            int m = 0;
-#pragma unroll
-            for (int k2 = 0; k2 < L2; k2++) {
-                y[k2] = k2 ? cmul(s[c][k2], tw[m]) : s[c][k2];
-                m += n1;
-                if (m >= L) m -= L;
-            }
+        for (int k2 = 0; k2 < L2; k2++) {
+            y[k2] = k2 ? cmul(sv[k2], tw[w]) : sv[k2];
+            w += n1;
+            if (w >= L) w -= L;
         }
     }
     __syncthreads();
+    for (int job = threadIdx.x; job < npairs * L2; job += blockDim.x) {
+        const int m = job / L2;
+        const int k2 = job - m * L2;
+        cpx<T> sv[L1];
+        const cpx<T>* y = Y + m * L + k2;
+#pragma unroll
+        for (int n1 = 0; n1 < L1; n1++) sv[n1] = y[n1 * L2];
+        reg_dft<T, L1, false>(sv);
+        cpx<T>* x = X + m * L + k2;
+#pragma unroll
+        for (int k1 = 0; k1 < L1; k1++) x[L2 * k1] = sv[k1];
+    }
+    __syncthreads();
     const int Hb = a.g.Hb;
-    for (int job = threadIdx.x; job < a.rpb * D * L2; job += blockDim.x) {
-        const int rc = job / L2;
-        const int k2 = job - rc * L2;
-        const int r = rc / D;
-        const int c = rc - r * D;
+    const int nreal = a.rpb * D;
+    for (int idx = threadIdx.x; idx < nreal * Hb; idx += blockDim.x) {
+        const int q = idx / Hb;
+        const int k = idx - q * Hb;
+        const int r = q / D;
+        const int c = q - r * D;
         const long long row = row0 + r;
-        cpx<T> s[L1];
-        const cpx<T>* y = Y + rc * L + k2;
-#pragma unroll
-        for (int n1 = 0; n1 < L1; n1++) s[n1] = y[n1 * L2];
-        reg_dft<T, L1, false>(s);
-        if (row < a.g.rows) {
-            cpx<T>* out = a.out + c * a.g.s1 + row * Hb;
-#pragma unroll
-            for (int k1 = 0; k1 < L1; k1++) {
-                const int k = k2 + L2 * k1;
-                if (k < Hb) out[k] = s[k1];
-            }
-        }
+        if (row >= a.g.rows) continue;
+        const cpx<T>* x = X + (q >> 1) * L;
+        const cpx<T> Z = x[k];
+        const cpx<T> Zm = x[k ? L - k : 0];
+        const cpx<T> v = (q & 1) ? cpx<T>{T(0.5) * (Z.y + Zm.y), T(-0.5) * (Z.x - Zm.x)}
+                                 : cpx<T>{T(0.5) * (Z.x + Zm.x), T(0.5) * (Z.y - Zm.y)};
+        a.out[c * a.g.s1 + row * Hb + k] = v;
     }
 }
 
@@ -303,12 +496,17 @@ __global__ __launch_bounds__(kThreads) void k2_first(FirstArgs<T> a, int op)
 template <typename T, int L1, int L2, bool INV>
 __global__ __launch_bounds__(kThreads) void k2_axis(AxisArgs<T> a, int B)
 {
+    if (a.done && *a.done) return;
     constexpr int L = L1 * L2;
     extern __shared__ __align__(16) unsigned char smem[];
     cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
     cpx<T>* Y = tw + L;
     const int P = a.P;
-    const int tile = blockIdx.x, o = blockIdx.y, c = blockIdx.z;
+    const long long lin = xcd_tile(blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z),
+                                   (long long)gridDim.x * gridDim.y * gridDim.z);
+    const int tile = (int)(lin % gridDim.x);
+    const int o = (int)((lin / gridDim.x) % gridDim.y);
+    const int c = (int)(lin / ((long long)gridDim.x * gridDim.y));
     for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
     __syncthreads();
     const cpx<T>* in = a.in + c * a.in_cs + o * a.in_os;
@@ -365,13 +563,14 @@ __global__ __launch_bounds__(kThreads) void k2_axis(AxisArgs<T> a, int B)
 template <typename T, int D, int L1, int L2>
 __global__ __launch_bounds__(kThreads) void k2_middle(MidArgs<T> a, int mult)
 {
+    if (a.done && *a.done) return;
     constexpr int L = L1 * L2;
     extern __shared__ __align__(16) unsigned char smem[];
     cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
     cpx<T>* Y = tw + L;
     const int P = a.P;
     const int PL = P * L;
-    const int tile = blockIdx.x;
+    const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);
     for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
     __syncthreads();
     // forward step A: jobs (c, n1, p), p fastest
@@ -483,85 +682,114 @@ __global__ __launch_bounds__(kThreads) void k2_middle(MidArgs<T> a, int mult)
 }
 
 // ------------------------------------------------------------------------------------------
-// Last pass: inverse step B from the half spectra (Hermitian completion), LDS, inverse step A
-// with the d components of a point together, solver epilogue.
+// Last pass, all global accesses whole-row contiguous:
+//   stage L   coalesced loads of the half spectra of the rows -> LDS (Sx)
+//   stage B'  packed row Z = A + iB of pencils 2m, 2m+1 with Hermitian completion
+//             (A(L-k) = conj A(k)), inverse L1-point DFTs -> Y
+//   stage A'  inverse L2-point DFTs; real and imaginary parts are the two real rows (Zr)
+//   stage E   solver epilogue per point, the d components together.
+// LDS: twiddles | Y (npairs rows) | Sx (nreal half rows) sharing space with Zr (2 npairs rows).
 // ------------------------------------------------------------------------------------------
-template <typename T, int D, int L1, int L2>
-__global__ __launch_bounds__(kThreads) void k2_last(LastArgs<T> a, int epi)
+template <typename T, int D, int L1, int L2, int epi>
+__global__ __launch_bounds__(kThreads) void k2_last(LastArgs<T> a)
 {
+    if (a.done && *a.done) return;
     constexpr int L = L1 * L2;
     extern __shared__ __align__(16) unsigned char smem[];
+    const int npairs = (a.rpb * D + 1) / 2;
     cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
     cpx<T>* Y = tw + L;
-    T* tab = reinterpret_cast<T*>(Y + a.rpb * D * L);
+    cpx<T>* Sx = Y + npairs * L;
+    T* Zr = reinterpret_cast<T*>(Sx);
+    T* tab = reinterpret_cast<T*>(Sx + npairs * (L + 1));
     __shared__ double red[kThreads / 64];
     for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
     if (epi == EPI_EM && a.A.kind == AK_PHASE)
         for (int m = threadIdx.x; m < kMaxPhases * 6; m += blockDim.x) tab[m] = T(a.A.tab_inv[m / 6][m % 6]);
-    __syncthreads();
-    const long long row0 = (long long)blockIdx.x * a.rpb;
+    const long long row0 = xcd_tile(blockIdx.x, gridDim.x) * a.rpb;
     const int Hb = a.g.Hb;
-    for (int job = threadIdx.x; job < a.rpb * D * L2; job += blockDim.x) {
-        const int rc = job / L2;
-        const int k2 = job - rc * L2;
-        const int r = rc / D;
-        const int c = rc - r * D;
-        const long long row = row0 + r;
-        cpx<T> s[L1];
-        const cpx<T>* in = a.in + c * a.g.s1 + row * Hb;
-        const bool ok = row < a.g.rows;
+    const int nreal = a.rpb * D;
+    for (int base = 0; base < 2 * npairs * Hb; base += kU * blockDim.x) {
+        cpx<T> v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+            const int idx = base + u * blockDim.x + threadIdx.x;
+            const int q = idx / Hb;
+            const int k = idx - q * Hb;
+            const int r = q / D;
+            const int c = q - r * D;
+            const long long row = row0 + r;
+            v[u] = {T(0), T(0)};
+            if (q < nreal && row < a.g.rows) v[u] = a.in[c * a.g.s1 + row * Hb + k];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+            const int idx = base + u * blockDim.x + threadIdx.x;
+            if (idx < 2 * npairs * Hb) Sx[idx] = v[u];
+        }
+    }
+    __syncthreads();
+    for (int job = threadIdx.x; job < npairs * L2; job += blockDim.x) {
+        const int m = job / L2;
+        const int k2 = job - m * L2;
+        const cpx<T>* s0 = Sx + (2 * m) * Hb;
+        const cpx<T>* s1 = s0 + Hb;
+        cpx<T> sv[L1];
 #pragma unroll
         for (int k1 = 0; k1 < L1; k1++) {
             const int k = k2 + L2 * k1;
-            cpx<T> v = {T(0), T(0)};
-            if (ok) {
-                if (k < Hb)
-                    v = in[k];
-                else if (L - k < Hb)
-                    v = conj(in[L - k]);
+            cpx<T> A = {T(0), T(0)}, B = {T(0), T(0)};
+            if (k < Hb) {
+                A = s0[k];
+                B = s1[k];
+            } else if (L - k < Hb) {
+                A = conj(s0[L - k]);
+                B = conj(s1[L - k]);
             }
-            s[k1] = v;
+            sv[k1] = {A.x - B.y, A.y + B.x};
         }
-        reg_dft<T, L1, true>(s);
-        cpx<T>* y = Y + rc * L + k2;
-        int m = 0;
+        reg_dft<T, L1, true>(sv);
+        cpx<T>* y = Y + m * L + k2;
+        int w = 0;
 #pragma unroll
         for (int n1 = 0; n1 < L1; n1++) {
-            y[n1 * L2] = n1 ? cmul(s[n1], conj(tw[m])) : s[n1];
-            m += k2;
-            if (m >= L) m -= L;
+            y[n1 * L2] = n1 ? cmul(sv[n1], conj(tw[w])) : sv[n1];
+            w += k2;
+            if (w >= L) w -= L;
+        }
+    }
+    __syncthreads();
+    for (int job = threadIdx.x; job < npairs * L1; job += blockDim.x) {
+        const int m = job / L1;
+        const int n1 = job - m * L1;
+        cpx<T> sv[L2];
+        const cpx<T>* y = Y + m * L + n1 * L2;
+#pragma unroll
+        for (int k2 = 0; k2 < L2; k2++) sv[k2] = y[k2];
+        reg_dft<T, L2, true>(sv);
+        T* z0 = Zr + (2 * m) * L + n1;
+        T* z1 = z0 + L;
+#pragma unroll
+        for (int n2 = 0; n2 < L2; n2++) {
+            z0[L1 * n2] = sv[n2].x;
+            z1[L1 * n2] = sv[n2].y;
         }
     }
     __syncthreads();
     double acc = 0.0;
-    for (int job = threadIdx.x; job < a.rpb * L1; job += blockDim.x) {
-        const int r = job / L1;
-        const int n1 = job - r * L1;
-        const long long row = row0 + r;
-        cpx<T> s[D][L2];
-#pragma unroll
-        for (int c = 0; c < D; c++) {
-            const cpx<T>* y = Y + (r * D + c) * L + n1 * L2;
-#pragma unroll
-            for (int k2 = 0; k2 < L2; k2++) s[c][k2] = y[k2];
-            reg_dft<T, L2, true>(s[c]);
-        }
-        if (row < a.g.rows) {
-#pragma unroll
-            for (int n2 = 0; n2 < L2; n2++) {
-                T yv[D];
-#pragma unroll
-                for (int c = 0; c < D; c++) yv[c] = s[c][n2].x;
-                acc += last_epilogue<T, D>(a, epi, tab, row * L + n1 + L1 * n2, yv);
-            }
-        }
+    {
+        const int total = a.rpb * L;
+        const long long pt0 = row0 * L;
+        const long long ptend = a.g.rows * (long long)L;
+        for (int base = 0; base < total; base += kU * blockDim.x)
+            acc += last_epilogue_chunk<T, D, L, epi>(a, tab, base, total, pt0, ptend, Zr);
     }
     const double tot = block_sum(acc, red);
     if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
 }
 
-// Lengths with a specialised kernel, and their split for the row passes (first/last: step A
-// holds d x L2 values) and the column passes (axis/middle: step B holds d x L1 values).
+// Lengths with a specialised kernel and their split L = L1 * L2 (L1 small: the middle pass holds
+// d x L1 values per job in registers, the row passes 2 x L1).
 struct Split {
     int L, row_L1, row_L2, col_L1, col_L2;
 };
