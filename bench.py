@@ -56,6 +56,66 @@ def pass_bytes(g, d, p_bytes):
     return {"middle": 2 * d * s2 * cplx, "axis_fwd": d * (s1 + s2) * cplx, "axis_inv": d * (s1 + s2) * cplx}
 
 
+def c4_section(fgh, inputs, torch, np, n):
+    """243^3 Boolean spheres (r = 12, f = 0.25), A = I / rho I, E = e1: CG in plain FP64 versus
+    FP32 transforms inside FP64 defect correction, for rho = 1e3 and 1e4 (A_H relative difference
+    against the FP64 CG solved to 1e-10), plus the FP32 operator's per-pass times and its
+    algorithmic-bytes fraction of the HBM peak."""
+    out = {"N": n}
+    for rho in (1e3, 1e4):
+        w = inputs.config4(rho, N=n)
+        tab = np.stack([inputs.sym_pack(t[None])[:, 0] for t in w.tables])
+        ph = torch.from_numpy(w.phase).cuda()
+        rec = {"fraction": round(w.fraction, 4)}
+        ref = None
+        for name, prec, tol in (("fp64_reference", fgh.FGH_FP64, 1e-10), ("fp64_cg", fgh.FGH_FP64, 1e-8),
+                                ("fp32_refined_cg", fgh.FGH_FP32_REFINED, 1e-8)):
+            plan = fgh.Plan(w.N, precision=prec, phase=ph, phase_table=tab, c_A=1.0, C_A=rho)
+            e = plan.field()
+            if name != "fp64_reference":
+                plan.solve("cg", w.E, tol, max_iter=20000, e=e)  # warm-up (graph capture)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st, stats = plan.solve("cg", w.E, tol, max_iter=20000, e=e)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            bil, _ = plan.effective(w.E, e)
+            r = {"status": st, "iters": stats[0]["iters"], "outer": stats[0]["outer_iters"],
+                 "fp64_applies": stats[0]["fp64_applies"], "seconds": round(dt, 4), "A_H_11": float(bil[0, 0]),
+                 "rel_res_true": stats[0]["rel_res_true"]}
+            if name == "fp64_reference":
+                ref = float(bil[0, 0])
+            else:
+                r["A_H_rel_err_vs_fp64_1e-10"] = abs(float(bil[0, 0]) - ref) / ref
+            rec[name] = r
+            del plan, e
+            log(f"[bench] c4 rho={rho:g} {name}: {r['iters']} it {dt:.3f} s")
+        rec["speedup_fp32_refined_vs_fp64"] = round(rec["fp64_cg"]["seconds"] / rec["fp32_refined_cg"]["seconds"], 3)
+        out[f"rho_{rho:g}"] = rec
+    # FP32 operator per-pass times
+    w = inputs.config4(1e3, N=n)
+    tab = np.stack([inputs.sym_pack(t[None])[:, 0] for t in w.tables])
+    plan = fgh.Plan(w.N, precision=fgh.FGH_FP32_REFINED, phase=torch.from_numpy(w.phase).cuda(), phase_table=tab)
+    x = torch.randn((3,) + w.N, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        plan.apply(x, y)
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    for _ in range(10):
+        plan.apply(x, y)
+    prof = plan.read_profile()
+    plan.set_profiling(False)
+    per = {k: round(v[0] * 1e3 / max(v[1], 1), 2) for k, v in prof.items()}
+    tot_us = sum(per.values())
+    b_alg = (5 * 2 * 3 * 4 * (1 + 1 / n) + 1) * n ** 3  # five passes of the half spectrum, phase map
+    out["apply_fp32"] = {"per_pass_avg_us": per, "sum_us": round(tot_us, 1), "B_alg_bytes": b_alg,
+                         "alg_GBs": round(b_alg / (tot_us * 1e-6) / 1e9, 1),
+                         "frac_of_8TBs": round(b_alg / (tot_us * 1e-6) / 8e12, 4),
+                         "voxel_iterations_per_s": round(n ** 3 / (tot_us * 1e-6))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +124,10 @@ def main():
     ap.add_argument("--n", type=int, default=135)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--no-c4", action="store_true", help="skip the 243^3 FP32-refinement section")
+    ap.add_argument("--c4-n", type=int, default=243)
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time without the per-pass HIP events (solver loops then replay HIP graphs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not part "
@@ -101,8 +165,17 @@ def main():
     for i in range(args.warmup):
         log(f"[bench] warmup step {i + 1}/{args.warmup}")
         step()
-    torch.cuda.synchronize()
+    # untimed: per-pass breakdown of one step, to name the dominant fixed-traffic pass
     plan.set_profiling(True)
+    step()
+    prof_all = plan.read_profile()
+    plan.set_profiling(False)
+    pb = pass_bytes(w.N, d, 8)
+    dom = max(("middle", "axis_fwd", "axis_inv"), key=lambda k: prof_all[k][0])
+
+    torch.cuda.synchronize()
+    if not args.no_profile:
+        plan.set_profiling(True, passes=[dom])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     total_iters = 0
@@ -118,25 +191,24 @@ def main():
     elapsed = t1 - t0
     value = total_iters * npts / elapsed
 
-    # roofline of the dominant fixed-traffic pass
-    pb = pass_bytes(w.N, d, 8)
-    dom = max(("middle", "axis_fwd", "axis_inv"), key=lambda k: prof[k][0])
+    # roofline of the dominant fixed-traffic pass, timed with HIP events inside the timed steps
     ms_tot, launches = prof[dom]
-    avg_s = ms_tot / 1e3 / max(launches, 1)
-    achieved = pb[dom] / avg_s / 1e9
+    avg_s = ms_tot / 1e3 / max(launches, 1) if launches else float("nan")
+    achieved = pb[dom] / avg_s / 1e9 if launches else None
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
         if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("pass") == dom:
             traffic = tr.get("bytes_per_launch")
-    roofline = {"bound": "hbm", "kernel": PASS_KERNELS[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "algorithmic_bytes_per_launch": pb[dom], "avg_launch_us": round(avg_s * 1e6, 2),
-                "launches": launches,
-                "per_pass_avg_us": {k: round(v[0] * 1e3 / max(v[1], 1), 2) for k, v in prof.items()},
-                "per_pass_share": {k: round(v[0] / max(sum(x[0] for x in prof.values()), 1e-30), 3)
-                                   for k, v in prof.items()}}
+    roofline = {"bound": "hbm", "kernel": PASS_KERNELS[dom], "achieved": None if achieved is None else round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes_per_launch": pb[dom], "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+                "per_pass_avg_us_untimed_step": {k: round(v[0] * 1e3 / max(v[1], 1), 2) for k, v in prof_all.items()},
+                "per_pass_share_untimed_step": {k: round(v[0] / max(sum(x[0] for x in prof_all.values()), 1e-30), 3)
+                                                for k, v in prof_all.items()}}
+    extra = None if args.no_c4 else c4_section(fgh, inputs, torch, np, args.c4_n)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -172,6 +244,7 @@ def main():
         "solvers": res,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "c4_fp32_refined_243": extra,
     }
     print(json.dumps(line), flush=True)
 

@@ -168,11 +168,12 @@ fgh_status fgh_solve_fixed(fgh_plan plan, fgh_solver solver, const double* E, in
 fgh_status fgh_effective(fgh_plan plan, const double* E, int nrhs, const double* e,
                          double* bilinear, double* flux);
 
-/* Per-pass device timing (profiling aid, not on by default).  While enabled, every pass launch of
- * the plan -- 0 first (A multiply + forward transform of the last axis), 1 forward strided axis,
- * 2 middle (transform of axis 0 with the Fourier multiplier), 3 inverse strided axis, 4 last
- * (inverse transform of the last axis + solver epilogue) -- is bracketed by HIP events on the
- * plan's stream and its duration accumulated.  Enabling resets the counters. */
+/* Per-pass device timing (profiling aid, off by default).  `enable` is a bit mask of pass kinds
+ * -- bit 0 first (A multiply + forward transform of the last axis), bit 1 forward strided axis,
+ * bit 2 middle (transform of axis 0 with the Fourier multiplier), bit 3 inverse strided axis,
+ * bit 4 last (inverse transform of the last axis + solver epilogue); 0 turns timing off.  Every
+ * launch of a selected kind is bracketed by HIP events on the stream it runs on and its duration
+ * accumulated; solver loops then run without graph replay.  Enabling resets the counters. */
 fgh_status fgh_plan_set_profiling(fgh_plan plan, int enable);
 
 /* Accumulated milliseconds and launch counts per pass kind (arrays of 5).  Synchronises. */

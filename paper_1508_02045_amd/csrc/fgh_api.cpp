@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <new>
 #include <vector>
 
@@ -291,6 +292,11 @@ struct fgh_plan_s {
     float* q32;
     double* host_buf;         // pinned host scalars
     Profiler* prof;           // per-pass timing while enabled
+    hipStream_t caller;       // the caller's stream
+    hipStream_t sstream;      // plan-internal stream of fgh_solve (graph capture needs one)
+    hipGraph_t graph;         // captured loop bodies (reused while the key matches)
+    hipGraphExec_t gexec;
+    uint64_t gkey;
 };
 
 namespace {
@@ -404,19 +410,79 @@ struct SolveOut {
 
 static_assert(sizeof(Scalars) <= 64 * sizeof(double), "pinned readback buffer too small");
 
-// Run loop bodies in chunks; the device decides when to stop (Scalars::done) and counts the
-// bodies, so the host synchronises once per chunk instead of once per body.
-template <typename Body>
-fgh_status run_loop(fgh_plan p, const OpPlan& op, Body body, bool fixed, double scale, SolveOut* out)
+constexpr int kGraphBodies = 8;
+
+uint64_t mix_key(uint64_t h, uint64_t v)
 {
-    int chunk = 4;
+    h ^= v + 0x9e3779b97f4a7c15ULL + (h << 6) + (h >> 2);
+    return h;
+}
+uint64_t key_of(std::initializer_list<uint64_t> vals)
+{
+    uint64_t h = 1469598103934665603ULL;
+    for (uint64_t v : vals) h = mix_key(h, v);
+    return h;
+}
+uint64_t bits(double v)
+{
+    uint64_t u;
+    std::memcpy(&u, &v, sizeof u);
+    return u;
+}
+uint64_t bits(const void* ptr) { return (uint64_t)(uintptr_t)ptr; }
+
+bool graphs_enabled()
+{
+    const char* v = std::getenv("FGH_GRAPHS");
+    return !(v && v[0] == '0');
+}
+
+void drop_graph(fgh_plan p)
+{
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->gexec = nullptr;
+    p->graph = nullptr;
+    p->gkey = 0;
+}
+
+// Run loop bodies in chunks; the device decides when to stop (Scalars::done) and counts the
+// bodies, so the host synchronises once per chunk instead of once per body.  When the plan's
+// stream can be captured, kGraphBodies bodies are captured once into a HIP graph (keyed by the
+// body's operands) and the graph is replayed; otherwise the bodies are launched one by one.
+template <typename Body>
+fgh_status run_loop(fgh_plan p, const OpPlan& op, Body body, uint64_t key, bool fixed, double scale, SolveOut* out)
+{
     const Scalars* h = reinterpret_cast<const Scalars*>(p->host_buf);
+    const bool use_graph = graphs_enabled() && !op.prof && op.stream != nullptr;
+    if (use_graph && (p->gkey != key || !p->gexec)) {
+        drop_graph(p);
+        HIPOK(hipStreamBeginCapture(op.stream, hipStreamCaptureModeThreadLocal));
+        hipError_t ce = hipSuccess;
+        for (int k = 0; k < kGraphBodies && ce == hipSuccess; k++) ce = body();
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(op.stream, &g);
+        if (ce != hipSuccess || ee != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return FGH_E_DEVICE;
+        }
+        p->graph = g;
+        HIPOK(hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0));
+        p->gkey = key;
+    }
+    int chunk = 1;
     for (;;) {
-        for (int k = 0; k < chunk; k++) HIPOK(body());
-        HIPOK(hipMemcpyAsync(p->host_buf, op.sc, sizeof(Scalars), hipMemcpyDeviceToHost, p->stream));
-        HIPOK(hipStreamSynchronize(p->stream));
+        for (int k = 0; k < chunk; k++) {
+            if (use_graph) {
+                HIPOK(hipGraphLaunch(p->gexec, op.stream));
+            } else {
+                for (int b = 0; b < kGraphBodies; b++) HIPOK(body());
+            }
+        }
+        HIPOK(hipMemcpyAsync(p->host_buf, op.sc, sizeof(Scalars), hipMemcpyDeviceToHost, op.stream));
+        HIPOK(hipStreamSynchronize(op.stream));
         if (h->done) break;
-        if (chunk < 32) chunk *= 2;
+        if (chunk < 4) chunk *= 2;
     }
     out->iters = h->m;
     out->res = scale > 0 ? h->last / scale : h->last;
@@ -464,7 +530,8 @@ fgh_status cg_core(fgh_plan p, T* x, T* r, T* pv, T* q, double tol_rel, int max_
         if ((e = run_cg_update<T>(op, n, x, r, pv, q)) != hipSuccess) return e;
         return run_reduce_async(op, vec_blocks(), RED_CG_END);
     };
-    return run_loop(p, op, body, fixed > 0, normb, out);
+    const uint64_t key = key_of({1, sizeof(T), bits(x), bits(r), bits(pv), bits(q)});
+    return run_loop(p, op, body, key, fixed > 0, normb, out);
 }
 
 // Chebyshev semi-iteration (Algorithm 3), b in r, x = 0.
@@ -502,7 +569,8 @@ fgh_status cheb_core(fgh_plan p, T* x, T* r, T* pv, double tol_rel, int max_iter
         if (e != hipSuccess) return e;
         return run_reduce_async(op, nb, RED_CHEB_END);
     };
-    return run_loop(p, op, body, fixed > 0, normb, out);
+    const uint64_t key = key_of({2, sizeof(T), bits(x), bits(r), bits(pv)});
+    return run_loop(p, op, body, key, fixed > 0, normb, out);
 }
 
 // Richardson (Algorithm 1): step = -w G A (E0 + x); stops when ||x_m - x_{m-1}|| <= thr.
@@ -529,7 +597,9 @@ fgh_status rich_core(fgh_plan p, T* x, const double* E0, double thr, int max_ite
         if (e != hipSuccess) return e;
         return run_reduce_async(op, nb, RED_STEP_END);
     };
-    return run_loop(p, op, body, fixed > 0, scale, out);
+    const uint64_t key = key_of({3, sizeof(T), bits(x), bits(E0[0]), bits(E0[1]), bits(p->d == 3 ? E0[2] : 0.0),
+                                 bits(omega)});
+    return run_loop(p, op, body, key, fixed > 0, scale, out);
 }
 
 // Eyre-Milton (Algorithm 4).  Plain form (src == NULL): x holds E + e; correction form
@@ -560,7 +630,9 @@ fgh_status em_core(fgh_plan p, T* x, const double* E, const T* src, double thr, 
         if (e != hipSuccess) return e;
         return run_reduce_async(op, nb, RED_STEP_END);
     };
-    return run_loop(p, op, body, fixed > 0, scale, out);
+    const uint64_t key = key_of({4, sizeof(T), bits(x), bits(src), bits(E[0]), bits(E[1]),
+                                 bits(p->d == 3 ? E[2] : 0.0), bits(omega)});
+    return run_loop(p, op, body, key, fixed > 0, scale, out);
 }
 
 // ||b - C e|| / ||b|| for the fluctuation e (double): apply C to (E + e) and compare with 0.
@@ -831,8 +903,14 @@ fgh_status fgh_plan_create(fgh_plan* out, int d, const int32_t* N, fgh_rule rule
     p->lay = make_layout(p->g, N, rule, precision, a_kind);
     p->ws = static_cast<char*>(workspace);
     p->stream = static_cast<hipStream_t>(stream);
+    p->caller = p->stream;
     p->ncoef_op = (a_kind == FGH_A_SYM) ? ncoef_for(d) : 1;
     if (hipHostMalloc(reinterpret_cast<void**>(&p->host_buf), 64 * sizeof(double)) != hipSuccess) {
+        delete p;
+        return FGH_E_DEVICE;
+    }
+    if (hipStreamCreateWithFlags(&p->sstream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipHostFree(p->host_buf);
         delete p;
         return FGH_E_DEVICE;
     }
@@ -998,6 +1076,8 @@ fgh_status fgh_plan_create(fgh_plan* out, int d, const int32_t* N, fgh_rule rule
 void fgh_plan_destroy(fgh_plan p)
 {
     if (!p) return;
+    drop_graph(p);
+    if (p->sstream) (void)hipStreamDestroy(p->sstream);
     if (p->prof) {
         p->prof->destroy();
         delete p->prof;
@@ -1017,6 +1097,7 @@ fgh_status fgh_plan_set_profiling(fgh_plan p, int enable)
             if (!p->prof) return FGH_E_DEVICE;
         }
         HIPOK(p->prof->init(p->stream));
+        p->prof->mask = (unsigned)enable & ((1u << PK_KINDS) - 1u);
         p->op64.prof = p->prof;
         p->op32.prof = p->prof;
     } else {
@@ -1100,6 +1181,22 @@ static fgh_status solve_common(fgh_plan p, fgh_solver solver, const double* E, i
         if (!std::isfinite(E[j])) return FGH_E_INVALID;
     const long long n = (long long)p->d * p->g.npts;
     int worst = FGH_OK;
+    // Work runs on the plan-internal stream after everything already queued on the caller's.
+    if (hipStreamSynchronize(p->caller) != hipSuccess) return FGH_E_DEVICE;
+    struct StreamSwap {
+        fgh_plan p;
+        explicit StreamSwap(fgh_plan q) : p(q)
+        {
+            p->stream = p->op64.stream = p->op32.stream = p->sstream;
+            if (p->prof) p->prof->stream = p->sstream;
+        }
+        ~StreamSwap()
+        {
+            (void)hipStreamSynchronize(p->sstream);
+            p->stream = p->op64.stream = p->op32.stream = p->caller;
+            if (p->prof) p->prof->stream = p->caller;
+        }
+    } swap_guard(p);
     for (int j = 0; j < nrhs; j++) {
         const double* Ej = E + j * p->d;
         double* ej = e + j * n;

@@ -833,10 +833,16 @@ static hipError_t allow_lds(const void* fn, size_t bytes)
     if (bytes <= 65536) return hipSuccess;
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
+// The attribute is raised once per kernel and never lowered, so that no attribute call is made
+// while a stream is being captured into a graph (the largest request is what counts).
 #define LAUNCH_LDS(KERNEL, GRID, LDS, STREAM, ...)                                              \
     do {                                                                                        \
-        hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&KERNEL), (LDS));               \
-        if (e_ != hipSuccess) return e_;                                                        \
+        static size_t lds_set_ = 65536;                                                         \
+        if ((LDS) > lds_set_) {                                                                 \
+            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&KERNEL), (LDS));           \
+            if (e_ != hipSuccess) return e_;                                                    \
+            lds_set_ = (LDS);                                                                   \
+        }                                                                                       \
         hipLaunchKernelGGL(KERNEL, GRID, dim3(kThreads), (LDS), (STREAM), __VA_ARGS__);          \
     } while (0)
 static inline unsigned grid_for(long long n, int per = kThreads, int cap = 4096)
@@ -1086,10 +1092,11 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     fa.A = op.A;
     fa.out = SA;
     fa.twg = static_cast<const cpx<T>*>(op.tw[last]);
-    if (op.prof && (e = op.prof->begin(PK_FIRST)) != hipSuccess) return e;
+    const bool prof_PK_FIRST = op.prof && op.prof->wants(PK_FIRST);
+    if (prof_PK_FIRST && (e = op.prof->begin(PK_FIRST)) != hipSuccess) return e;
     if ((e = op.v2_row ? v2_first<T, D>(op, fa, a.op, nblk) : launch_first<T, D>(op, fa, a.op, nblk)) != hipSuccess)
         return e;
-    if (op.prof && (e = op.prof->end()) != hipSuccess) return e;
+    if (prof_PK_FIRST && (e = op.prof->end()) != hipSuccess) return e;
 
     cpx<T>* mid = SA;
     if (D == 3) {
@@ -1110,10 +1117,11 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
         xa.out = SB;
         xa.twg = static_cast<const cpx<T>*>(op.tw[1]);
         xa.done = done;
-        if (op.prof && (e = op.prof->begin(PK_AXIS_FWD)) != hipSuccess) return e;
+        const bool prof_PK_AXIS_FWD = op.prof && op.prof->wants(PK_AXIS_FWD);
+        if (prof_PK_AXIS_FWD && (e = op.prof->begin(PK_AXIS_FWD)) != hipSuccess) return e;
         if ((e = op.v2_axis ? v2_axis<T>(op, xa, false, g.L[0], g.B[1]) : launch_axis<T>(op, xa, false, g.L[0])) != hipSuccess)
             return e;
-        if (op.prof && (e = op.prof->end()) != hipSuccess) return e;
+        if (prof_PK_AXIS_FWD && (e = op.prof->end()) != hipSuccess) return e;
         mid = SB;
     }
 
@@ -1130,9 +1138,10 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     ma.buf = mid;
     ma.twg = static_cast<const cpx<T>*>(op.tw[0]);
     ma.done = done;
-    if (op.prof && (e = op.prof->begin(PK_MIDDLE)) != hipSuccess) return e;
+    const bool prof_PK_MIDDLE = op.prof && op.prof->wants(PK_MIDDLE);
+    if (prof_PK_MIDDLE && (e = op.prof->begin(PK_MIDDLE)) != hipSuccess) return e;
     if ((e = op.v2_mid ? v2_middle<T, D>(op, ma, a.mult) : launch_middle<T, D>(op, ma, a.mult)) != hipSuccess) return e;
-    if (op.prof && (e = op.prof->end()) != hipSuccess) return e;
+    if (prof_PK_MIDDLE && (e = op.prof->end()) != hipSuccess) return e;
 
     if (D == 3) {
         AxisArgs<T> xa;
@@ -1152,10 +1161,11 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
         xa.out = SA;
         xa.twg = static_cast<const cpx<T>*>(op.tw[1]);
         xa.done = done;
-        if (op.prof && (e = op.prof->begin(PK_AXIS_INV)) != hipSuccess) return e;
+        const bool prof_PK_AXIS_INV = op.prof && op.prof->wants(PK_AXIS_INV);
+        if (prof_PK_AXIS_INV && (e = op.prof->begin(PK_AXIS_INV)) != hipSuccess) return e;
         if ((e = op.v2_axis ? v2_axis<T>(op, xa, true, g.L[0], g.B[1]) : launch_axis<T>(op, xa, true, g.L[0])) != hipSuccess)
             return e;
-        if (op.prof && (e = op.prof->end()) != hipSuccess) return e;
+        if (prof_PK_AXIS_INV && (e = op.prof->end()) != hipSuccess) return e;
     }
 
     LastArgs<T> la;
@@ -1180,10 +1190,11 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     la.twg = static_cast<const cpx<T>*>(op.tw[last]);
     la.done = done;
     la.sc = a.cheb_dev ? op.sc : nullptr;
-    if (op.prof && (e = op.prof->begin(PK_LAST)) != hipSuccess) return e;
+    const bool prof_PK_LAST = op.prof && op.prof->wants(PK_LAST);
+    if (prof_PK_LAST && (e = op.prof->begin(PK_LAST)) != hipSuccess) return e;
     if ((e = op.v2_row ? v2_last<T, D>(op, la, a.epi, nblk) : launch_last<T, D>(op, la, a.epi, nblk)) != hipSuccess)
         return e;
-    if (op.prof && (e = op.prof->end()) != hipSuccess) return e;
+    if (prof_PK_LAST && (e = op.prof->end()) != hipSuccess) return e;
     if (nblocks_last) *nblocks_last = (int)nblk;
     return hipSuccess;
 }

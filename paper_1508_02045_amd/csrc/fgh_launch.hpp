@@ -17,6 +17,8 @@ struct Profiler {
     double ms[PK_KINDS] = {0, 0, 0, 0, 0};
     long long n[PK_KINDS] = {0, 0, 0, 0, 0};
     hipStream_t stream = nullptr;
+    unsigned mask = 0u;  // pass kinds timed (bit k: PassKind k)
+    bool wants(int k) const { return (mask >> k) & 1u; }
     hipError_t init(hipStream_t s);
     void destroy();
     hipError_t begin(int k);

@@ -273,8 +273,14 @@ class Plan:
             raise FghError(st, "fgh_ga_coefficients")
         return out
 
-    def set_profiling(self, enable=True):
-        st = lib().fgh_plan_set_profiling(ctypes.c_void_p(self.handle), 1 if enable else 0)
+    def set_profiling(self, enable=True, passes=None):
+        """enable: switch per-pass timing on/off; passes: names from PASS_NAMES (default all)."""
+        mask = 0
+        if enable:
+            names = PASS_NAMES if passes is None else passes
+            for n in names:
+                mask |= 1 << PASS_NAMES.index(n)
+        st = lib().fgh_plan_set_profiling(ctypes.c_void_p(self.handle), mask)
         if st:
             raise FghError(st, "fgh_plan_set_profiling")
 
