@@ -179,6 +179,71 @@ fgh_status fgh_plan_set_profiling(fgh_plan plan, int enable);
 /* Accumulated milliseconds and launch counts per pass kind (arrays of 5).  Synchronises. */
 fgh_status fgh_plan_read_profile(fgh_plan plan, double* ms, int64_t* launches);
 
+/* ------------------------------------------------------------------------------------------
+ * Serving.  Solves of mixed d, N, rule, contrast, solver and tolerance are submitted as they
+ * arrive and run by a pool of worker slots, each with its own HIP stream; the fields and solver
+ * state of an admitted request stay in HBM until it retires.  A request is admitted (FIFO) once
+ * its footprint -- plan workspace, fluctuation field on the integration grid (the 2N-1 grid for
+ * Ga), phase map -- fits into the free part of the caller's device pool; concurrently running
+ * requests overlap on the device.  Each request's arithmetic is that of fgh_solve on its own plan,
+ * so its result does not depend on what else is in flight.  The coefficients of a request are a
+ * phase map (host uint8, copied at submission) and a phase table, as for FGH_A_PHASE.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct fgh_server_s* fgh_server;
+
+typedef struct {
+    int32_t d;
+    int32_t N[3];
+    int32_t rule;          /* fgh_rule */
+    int32_t precision;     /* fgh_precision */
+    int32_t solver;        /* fgh_solver */
+    int32_t max_iter;
+    double tol;
+    double E[3];
+    const uint8_t* phase;  /* host [N grid], copied by fgh_server_submit */
+    const double* phase_table; /* host [n_phases][ncoef], copied */
+    int32_t n_phases;
+    int32_t pad;
+    double c_A, C_A;       /* <= 0: derived from the phases present */
+} fgh_request;
+
+typedef struct {
+    int64_t id;
+    int32_t status;        /* fgh_status of the solve */
+    int32_t iters, outer_iters, pad;
+    double energy;         /* (A(E + e), E + e)_2 */
+    double flux[3];        /* <A(E + e)> */
+    double rel_res_true;
+    double t_submit, t_admit, t_done;  /* seconds since fgh_server_create */
+    double solve_seconds;
+} fgh_result;
+
+/* Pool bytes a request holds while admitted. */
+fgh_status fgh_request_footprint(const fgh_request* request, size_t* bytes);
+
+/* Create a server over the device pool [pool, pool + pool_bytes) (256-byte aligned, caller-owned,
+ * on device `device`) with max_active worker slots (1..16). */
+fgh_status fgh_server_create(fgh_server* out, void* pool, size_t pool_bytes, int max_active, int device);
+
+/* Queue a request (thread-safe, non-blocking).  FGH_E_WORKSPACE if it can never fit the pool,
+ * FGH_E_UNSUPPORTED for Eyre-Milton with Ga, FGH_E_INVALID for bad fields. */
+fgh_status fgh_server_submit(fgh_server server, const fgh_request* request, int64_t* id);
+
+/* FGH_OK and the result if request `id` has finished, FGH_E_NO_CONVERGENCE while it is pending. */
+fgh_status fgh_server_poll(fgh_server server, int64_t id, fgh_result* out);
+
+/* Block until request `id` has finished. */
+fgh_status fgh_server_wait(fgh_server server, int64_t id, fgh_result* out);
+
+/* Block until every submitted request has finished. */
+fgh_status fgh_server_drain(fgh_server server);
+
+/* Server clock, peak pool bytes in use and peak number of concurrently active requests. */
+fgh_status fgh_server_stats(fgh_server server, double* now_seconds, size_t* peak_pool_bytes, int* peak_active);
+
+/* Stop the workers after the requests already admitted; requests still queued are discarded. */
+void fgh_server_destroy(fgh_server server);
+
 const char* fgh_status_string(fgh_status status);
 
 #ifdef __cplusplus

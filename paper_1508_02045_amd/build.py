@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfgh.so")
-SOURCES = ["fgh_kernels.hip", "fgh_api.cpp"]
+SOURCES = ["fgh_kernels.hip", "fgh_api.cpp", "fgh_server.cpp"]
 ARCH = os.environ.get("FGH_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are kept out of the generated code; hipcc's host pass warns that it
@@ -18,7 +18,7 @@ ARCH = os.environ.get("FGH_OFFLOAD_ARCH", "gfx950")
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def build(verbose: bool = False, jobs: int = 2) -> str:
+def build(verbose: bool = False, jobs: int = 3) -> str:
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
     objs = []

@@ -3,6 +3,8 @@
 // and the set-up kernels (double-grid coefficients, spectral bounds).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "fgh_args.hpp"
 #include "fgh_launch.hpp"
 #include "fgh_v2.hpp"
@@ -837,11 +839,11 @@ static hipError_t allow_lds(const void* fn, size_t bytes)
 // while a stream is being captured into a graph (the largest request is what counts).
 #define LAUNCH_LDS(KERNEL, GRID, LDS, STREAM, ...)                                              \
     do {                                                                                        \
-        static size_t lds_set_ = 65536;                                                         \
-        if ((LDS) > lds_set_) {                                                                 \
+        static std::atomic<size_t> lds_set_{65536};                                            \
+        if ((LDS) > lds_set_.load(std::memory_order_relaxed)) {                                 \
             hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&KERNEL), (LDS));           \
             if (e_ != hipSuccess) return e_;                                                    \
-            lds_set_ = (LDS);                                                                   \
+            lds_set_.store((LDS), std::memory_order_relaxed);                                   \
         }                                                                                       \
         hipLaunchKernelGGL(KERNEL, GRID, dim3(kThreads), (LDS), (STREAM), __VA_ARGS__);          \
     } while (0)

@@ -38,6 +38,8 @@ SOLVERS = {"richardson": FGH_RICHARDSON, "cg": FGH_CG, "chebyshev": FGH_CHEBYSHE
 EXPORTS = ["fgh_plan_workspace", "fgh_plan_create", "fgh_plan_destroy", "fgh_plan_grid_points",
            "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32", "fgh_ga_coefficients", "fgh_solve",
            "fgh_solve_fixed", "fgh_effective", "fgh_plan_set_profiling", "fgh_plan_read_profile",
+           "fgh_request_footprint", "fgh_server_create", "fgh_server_submit", "fgh_server_poll",
+           "fgh_server_wait", "fgh_server_drain", "fgh_server_stats", "fgh_server_destroy",
            "fgh_status_string"]
 PASS_NAMES = ["first", "axis_fwd", "middle", "axis_inv", "last"]
 
@@ -56,6 +58,26 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("N", ctypes.c_int32 * 3), ("rule", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("solver", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("E", ctypes.c_double * 3), ("phase", ctypes.c_void_p),
+                ("phase_table", ctypes.c_void_p), ("n_phases", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("c_A", ctypes.c_double), ("C_A", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("outer_iters", ctypes.c_int32), ("pad", ctypes.c_int32), ("energy", ctypes.c_double),
+                ("flux", ctypes.c_double * 3), ("rel_res_true", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("solve_seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        out = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        out["flux"] = list(self.flux)
+        return out
 
 
 _lib = None
@@ -91,6 +113,18 @@ def lib():
         L.fgh_effective.argtypes = [_vp, _dp, ctypes.c_int, _vp, _dp, _dp]
         L.fgh_plan_set_profiling.argtypes = [_vp, ctypes.c_int]
         L.fgh_plan_read_profile.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]
+        L.fgh_request_footprint.argtypes = [ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_size_t)]
+        L.fgh_server_create.argtypes = [ctypes.POINTER(_vp), _vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int]
+        L.fgh_server_submit.argtypes = [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_int64)]
+        L.fgh_server_poll.argtypes = [_vp, ctypes.c_int64, ctypes.POINTER(Result)]
+        L.fgh_server_wait.argtypes = [_vp, ctypes.c_int64, ctypes.POINTER(Result)]
+        L.fgh_server_drain.argtypes = [_vp]
+        L.fgh_server_stats.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int)]
+        L.fgh_server_destroy.argtypes = [_vp]
+        L.fgh_server_destroy.restype = None
+        for name in ("fgh_request_footprint", "fgh_server_create", "fgh_server_submit", "fgh_server_poll",
+                     "fgh_server_wait", "fgh_server_drain", "fgh_server_stats"):
+            getattr(L, name).restype = ctypes.c_int
         L.fgh_status_string.argtypes = [ctypes.c_int]
         L.fgh_status_string.restype = ctypes.c_char_p
         for name in ("fgh_plan_workspace", "fgh_plan_create", "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32",
@@ -296,6 +330,96 @@ class Plan:
         if getattr(self, "handle", None):
             fgh_plan_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------- serving
+def make_request(d, N, phase, table, E, solver, tol, rule=FGH_GANI, precision=FGH_FP32_REFINED, max_iter=20000,
+                 c_A=0.0, C_A=0.0):
+    """Build a Request; returns (request, keep) -- keep the arrays alive until submission."""
+    phase = np.ascontiguousarray(phase, dtype=np.uint8)
+    table = np.ascontiguousarray(table, dtype=np.float64)
+    r = Request()
+    r.d = d
+    for a in range(3):
+        r.N[a] = int(N[a]) if a < d else 1
+    r.rule = int(rule)
+    r.precision = int(precision)
+    r.solver = int(SOLVERS.get(solver, solver))
+    r.max_iter = int(max_iter)
+    r.tol = float(tol)
+    for a in range(3):
+        r.E[a] = float(E[a]) if a < d else 0.0
+    r.phase = phase.ctypes.data
+    r.phase_table = table.ctypes.data
+    r.n_phases = table.shape[0]
+    r.c_A = float(c_A)
+    r.C_A = float(C_A)
+    return r, (phase, table)
+
+
+def fgh_request_footprint(request) -> int:
+    out = ctypes.c_size_t()
+    st = lib().fgh_request_footprint(ctypes.byref(request), ctypes.byref(out))
+    if st:
+        raise FghError(st, "fgh_request_footprint")
+    return out.value
+
+
+class Server:
+    """Serving loop over a device pool (torch uint8 tensor) with `max_active` worker slots."""
+
+    def __init__(self, pool_bytes, max_active=4, device=0):
+        import torch
+
+        self.pool = torch.empty(int(pool_bytes) + 256, dtype=torch.uint8, device=f"cuda:{device}")
+        off = (-self.pool.data_ptr()) % 256
+        self.handle = ctypes.c_void_p()
+        st = lib().fgh_server_create(ctypes.byref(self.handle), ctypes.c_void_p(self.pool.data_ptr() + off),
+                                     int(pool_bytes), int(max_active), int(device))
+        if st:
+            raise FghError(st, "fgh_server_create")
+
+    def submit(self, request) -> int:
+        rid = ctypes.c_int64()
+        st = lib().fgh_server_submit(self.handle, ctypes.byref(request), ctypes.byref(rid))
+        if st:
+            raise FghError(st, "fgh_server_submit")
+        return rid.value
+
+    def poll(self, rid):
+        res = Result()
+        st = lib().fgh_server_poll(self.handle, int(rid), ctypes.byref(res))
+        return res.as_dict() if st == FGH_OK else None
+
+    def wait(self, rid):
+        res = Result()
+        st = lib().fgh_server_wait(self.handle, int(rid), ctypes.byref(res))
+        if st:
+            raise FghError(st, "fgh_server_wait")
+        return res.as_dict()
+
+    def drain(self):
+        st = lib().fgh_server_drain(self.handle)
+        if st:
+            raise FghError(st, "fgh_server_drain")
+
+    def stats(self):
+        now = ctypes.c_double()
+        peak = ctypes.c_size_t()
+        act = ctypes.c_int()
+        lib().fgh_server_stats(self.handle, ctypes.byref(now), ctypes.byref(peak), ctypes.byref(act))
+        return {"now": now.value, "peak_pool_bytes": peak.value, "peak_active": act.value}
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().fgh_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
 
     def __del__(self):
         try:

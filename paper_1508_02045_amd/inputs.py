@@ -84,6 +84,7 @@ def boolean_spheres(N: Sequence[int], radius: float, target_fraction: float,
     rad = int(np.ceil(r))
     offs = np.arange(-rad - 1, rad + 2)
     total = float(np.prod(N))
+    inside = 0
     count = 0
     for count in range(1, max_spheres + 1):
         c = rng.uniform(0.0, 1.0, size=d) * np.asarray(N, dtype=np.float64)
@@ -98,11 +99,15 @@ def boolean_spheres(N: Sequence[int], radius: float, target_fraction: float,
             dist2 = dist2 + (delta ** 2).reshape(shape)
         mask = dist2 <= r * r
         sub = np.ix_(*idx)
-        phase[sub] |= mask
-        frac = phase.sum() / total
-        if frac >= target_fraction:
+        block = phase[sub]
+        phase[sub] = block | mask
+        if len(offs) <= min(N):
+            inside += int(np.count_nonzero(mask & ~block))
+        else:  # the candidate block wraps onto itself: recount
+            inside = int(np.count_nonzero(phase))
+        if inside / total >= target_fraction:
             break
-    return phase.astype(np.uint8), float(phase.sum() / total), count
+    return phase.astype(np.uint8), float(inside / total), count
 
 
 def haar_rotations(n: int, d: int, rng: np.random.Generator) -> np.ndarray:
@@ -205,3 +210,49 @@ def config4(contrast: float, N: int = 243, radius: float = 12.0, fraction: float
     ph, frac, ns = boolean_spheres((N, N, N), radius, fraction, config_rng(3))
     return Workload(f"c4_spheres3d_{N}_rho{contrast:g}", (N, N, N), ph, iso_tables(3, [1.0, contrast]),
                     None, np.array([1.0, 0.0, 0.0]), contrast, frac, note=f"{ns} spheres")
+
+
+def cube_side_for_fraction(n: int, d: int, f: float) -> int:
+    """Odd side (pixels) of a centred square/cube whose area fraction is nearest f."""
+    best = 1
+    for side in range(1, n + 1, 2):
+        if abs((side / n) ** d - f) < abs((best / n) ** d - f):
+            best = side
+    return best
+
+
+def serving_requests(count: int, rng: np.random.Generator):
+    """A seeded stream of homogenization requests of mixed shape (the served workload).
+
+    d uniform in {2, 3}; exact integration (Ga) with probability 0.2 for N in {41, 63};
+    otherwise 2D N in {81, 243, 729} or 3D N in {45, 81, 135, 243}.  Microstructure: a centred
+    square/cube or a Boolean model of discs/spheres of radius max(2, round(N / 20)), inclusion
+    fraction U[0.1, 0.4]; A = I / rho I with rho log-uniform in [10, 1e4]; E = e1; solver CG or
+    Eyre-Milton (CG for Ga); tolerance 1e-6 or 1e-8."""
+    reqs = []
+    for _ in range(count):
+        d = int(rng.integers(2, 4))
+        ga = rng.uniform() < 0.2
+        if ga:
+            n = int(rng.choice([41, 63]))
+        elif d == 2:
+            n = int(rng.choice([81, 243, 729]))
+        else:
+            n = int(rng.choice([45, 81, 135, 243]))
+        N = (n,) * d
+        f = float(rng.uniform(0.1, 0.4))
+        rho = float(10.0 ** rng.uniform(1.0, 4.0))
+        if rng.uniform() < 0.5:
+            phase = centred_box(N, cube_side_for_fraction(n, d, f) // 2)
+            micro = "box"
+        else:
+            phase, f, _ = boolean_spheres(N, max(2, round(n / 20)), f, rng)
+            micro = "spheres"
+        solver = "cg" if ga or rng.uniform() < 0.5 else "eyre_milton"
+        tol = float(rng.choice([1e-6, 1e-8]))
+        E = np.zeros(d)
+        E[0] = 1.0
+        reqs.append({"d": d, "N": N, "rule": 1 if ga else 0, "phase": phase, "tables": iso_tables(d, [1.0, rho]),
+                     "rho": rho, "fraction": float(phase.mean()), "micro": micro, "solver": solver, "tol": tol,
+                     "E": E})
+    return reqs

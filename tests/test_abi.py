@@ -75,3 +75,19 @@ def test_create_rejects_null_arguments(L):
                            None, 0, None)
     assert st == fgh.FGH_E_INVALID
     assert L.fgh_solve(None, 1, None, 1, 1e-6, 10, None, None) == fgh.FGH_E_INVALID
+
+
+def test_request_footprint_counts_double_grid_and_refinement():
+    import numpy as np
+    from paper_1508_02045_amd import fgh
+    tab = np.array([[1.0, 0, 0, 1, 0, 1], [10.0, 0, 0, 10, 0, 10]])
+    ph = np.zeros((63, 63, 63), np.uint8)
+    sizes = {}
+    for rule in (0, 1):
+        for prec in (0, 1):
+            r, keep = fgh.make_request(3, (63, 63, 63), ph, tab, [1, 0, 0], "cg", 1e-6, rule=rule, precision=prec)
+            sizes[(rule, prec)] = fgh.fgh_request_footprint(r)
+    assert sizes[(1, 0)] > 6 * sizes[(0, 0)]  # the 125^3 double grid
+    assert sizes[(0, 1)] > sizes[(0, 0)]
+    ws = fgh.fgh_plan_workspace(3, (63, 63, 63), 1, 0, fgh.FGH_A_PHASE)
+    assert sizes[(1, 0)] >= ws + 3 * 125 ** 3 * 8
