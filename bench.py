@@ -116,6 +116,80 @@ def c4_section(fgh, inputs, torch, np, n):
     return out
 
 
+def served_section(fgh, inputs, np, n_req, max_active=4, pool_gb=24):
+    """Served stream (mixed d, N, rule, contrast, solver, tolerance; see inputs.serving_requests).
+    Baseline: the same requests one at a time in plain FP64; its mean service time S sets the
+    Poisson arrival rate 1/S (load 1 for the baseline).  Served: FP32 transforms with FP64
+    defect correction, `max_active` concurrent slots, admission by HBM footprint."""
+    reqs = inputs.serving_requests(n_req, inputs.config_rng(4))
+
+    def pack(tables):
+        return np.stack([inputs.sym_pack(t[None])[:, 0] for t in tables])
+
+    def submit(srv, q, prec):
+        r, keep = fgh.make_request(q["d"], q["N"], q["phase"], pack(q["tables"]), q["E"], q["solver"], q["tol"],
+                                   rule=q["rule"], precision=prec)
+        rid = srv.submit(r)
+        del keep
+        return rid
+
+    # baseline: sequential plain FP64
+    srv = fgh.Server(int(pool_gb * (1 << 30)), max_active=1)
+    ids = [submit(srv, q, fgh.FGH_FP64) for q in reqs]
+    res64 = [srv.wait(i) for i in ids]
+    srv.close()
+    service = np.array([r["t_done"] - r["t_admit"] for r in res64])
+    s_mean = float(service.mean())
+    log(f"[bench] served: sequential FP64 baseline {n_req} requests, mean service {s_mean * 1e3:.1f} ms")
+    rng = np.random.default_rng(np.random.SeedSequence(inputs.ROOT_SEED + 5))
+    arrivals = np.cumsum(rng.exponential(s_mean, size=n_req))
+    arrivals -= arrivals[0]
+    # the baseline's latencies under the same arrivals (single FIFO server, measured service times)
+    t_free = 0.0
+    lat64 = []
+    for a, sv in zip(arrivals, service):
+        start = max(a, t_free)
+        t_free = start + sv
+        lat64.append(t_free - a)
+    lat64 = np.array(lat64)
+    # served
+    srv = fgh.Server(int(pool_gb * (1 << 30)), max_active=max_active)
+    t0 = time.perf_counter()
+    ids = []
+    for a, q in zip(arrivals, reqs):
+        dt = t0 + a - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        ids.append(submit(srv, q, fgh.FGH_FP32_REFINED))
+    res = [srv.wait(i) for i in ids]
+    st = srv.stats()
+    srv.close()
+    # capacity: the whole stream submitted at once
+    srv = fgh.Server(int(pool_gb * (1 << 30)), max_active=max_active)
+    tc = time.perf_counter()
+    cids = [submit(srv, q, fgh.FGH_FP32_REFINED) for q in reqs]
+    cres = [srv.wait(i) for i in cids]
+    cap_span = max(r["t_done"] for r in cres) - min(r["t_submit"] for r in cres)
+    srv.close()
+    del tc
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+    rel = np.array([abs(r["energy"] - b["energy"]) / abs(b["energy"]) for r, b in zip(res, res64)])
+    ok = sum(1 for r in res if r["status"] == 0)
+    ok64 = sum(1 for r in res64 if r["status"] == 0)
+    return {"requests": n_req, "max_active": max_active, "pool_GB": pool_gb,
+            "arrival_rate_per_s": round(1.0 / s_mean, 3),
+            "served_fp32_refined": {"solves_per_s": round(n_req / span, 3),
+                                    "capacity_solves_per_s_all_submitted_at_once": round(n_req / cap_span, 3), "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+                                    "p99_latency_s": round(float(np.percentile(lat, 99)), 4), "status_ok": ok,
+                                    "peak_active": st["peak_active"], "peak_pool_GB": round(st["peak_pool_bytes"] / 2 ** 30, 2)},
+            "sequential_fp64": {"solves_per_s": round(1.0 / s_mean, 3), "p50_latency_s": round(float(np.percentile(lat64, 50)), 4),
+                                "p99_latency_s": round(float(np.percentile(lat64, 99)), 4), "status_ok": ok64},
+            "energy_rel_diff_served_vs_fp64": {"max": float(rel.max()), "median": float(np.median(rel))},
+            "mix": {"d3": sum(q["d"] == 3 for q in reqs), "ga": sum(q["rule"] == 1 for q in reqs),
+                    "eyre_milton": sum(q["solver"] == "eyre_milton" for q in reqs)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +199,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=4)
     ap.add_argument("--no-c4", action="store_true", help="skip the 243^3 FP32-refinement section")
+    ap.add_argument("--no-served", action="store_true", help="skip the served-stream section")
+    ap.add_argument("--served-n", type=int, default=64)
     ap.add_argument("--c4-n", type=int, default=243)
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-pass HIP events (solver loops then replay HIP graphs)")
@@ -209,6 +285,7 @@ def main():
                 "per_pass_share_untimed_step": {k: round(v[0] / max(sum(x[0] for x in prof_all.values()), 1e-30), 3)
                                                 for k, v in prof_all.items()}}
     extra = None if args.no_c4 else c4_section(fgh, inputs, torch, np, args.c4_n)
+    served = None if args.no_served else served_section(fgh, inputs, np, args.served_n)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -245,6 +322,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "c4_fp32_refined_243": extra,
+        "served": served,
     }
     print(json.dumps(line), flush=True)
 
