@@ -168,6 +168,19 @@ fgh_status fgh_solve_fixed(fgh_plan plan, fgh_solver solver, const double* E, in
 fgh_status fgh_effective(fgh_plan plan, const double* E, int nrhs, const double* e,
                          double* bilinear, double* flux);
 
+/* Guaranteed upper bound of the GaNi solution (Sec. 2.3, eq:ev_bounds_GaNi; Sec. 4.3): the GaNi
+ * fluctuation e_N is read as a trigonometric polynomial, so its prolongation R e_N to the double
+ * grid 2N-1 (interpolate on N, evaluate on 2N-1) is conforming and the exactly integrated energy
+ *   bound = (A_{2N-1}(E + R e_N), E + R e_N)_{2N-1}
+ * bounds (A_H E, E) from above (eq:bounds).
+ * gani: a GaNi plan; ga: a Ga plan on the same N and microstructure (it supplies A_{2N-1} and is
+ * used as scratch: its spectrum and one FP64 vector are overwritten).  E: host double[d];
+ * e: device double[d][N grid] (e.g. from fgh_solve on `gani`).  bound: host double.  Waits for
+ * the GaNi plan's stream, runs on the Ga plan's stream and blocks.  FGH_E_INVALID when the
+ * rules, d or N do not match. */
+fgh_status fgh_gani_bound(fgh_plan gani, fgh_plan ga, const double* E, const double* e,
+                          double* bound);
+
 /* Per-pass device timing (profiling aid, off by default).  `enable` is a bit mask of pass kinds
  * -- bit 0 first (A multiply + forward transform of the last axis), bit 1 forward strided axis,
  * bit 2 middle (transform of axis 0 with the Fourier multiplier), bit 3 inverse strided axis,

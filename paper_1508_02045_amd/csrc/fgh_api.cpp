@@ -1259,4 +1259,24 @@ fgh_status fgh_effective(fgh_plan p, const double* E, int nrhs, const double* e,
     return FGH_OK;
 }
 
+fgh_status fgh_gani_bound(fgh_plan gani, fgh_plan ga, const double* E, const double* e, double* bound)
+{
+    if (!gani || !ga || !E || !e || !bound) return FGH_E_INVALID;
+    if (gani->rule != FGH_GANI || ga->rule != FGH_GA || gani->d != ga->d) return FGH_E_INVALID;
+    for (int a = 0; a < gani->d; a++)
+        if (gani->N[a] != ga->N[a]) return FGH_E_INVALID;
+    for (int c = 0; c < gani->d; c++)
+        if (!std::isfinite(E[c])) return FGH_E_INVALID;
+    // e may still be in flight on the GaNi plan's stream; the work below runs on the Ga plan's.
+    HIPOK(hipStreamSynchronize(gani->stream));
+    OpPlan opn = gani->op64;
+    opn.stream = ga->stream;
+    opn.prof = nullptr;
+    OpPlan opm = ga->op64;
+    opm.prof = nullptr;
+    double* y = ga->q64;  // R e on the double grid
+    HIPOK(run_prolong(opn, opm, e, y));
+    return fgh_effective(ga, E, 1, y, bound, nullptr);
+}
+
 }  // extern "C"

@@ -1201,6 +1201,114 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     return hipSuccess;
 }
 
+// One strided-axis launch with explicit geometry (generic kernel, any length): transform along
+// an axis of length ax.L for `outer` blocks of `inner` contiguous columns per component.
+static hipError_t axis_custom(const OpPlan& op, const Axis& ax, const void* tw, bool inv, int nin, int bin, int nout,
+                              int bout, int inner, int outer, long long in_os, long long out_os, long long in_cs,
+                              long long out_cs, const double2* in, double2* out)
+{
+    AxisArgs<double> xa{};
+    xa.done = nullptr;
+    xa.ax = ax;
+    xa.nin = nin;
+    xa.nout = nout;
+    xa.bin = bin;
+    xa.bout = bout;
+    xa.inner = inner;
+    int P = 16;
+    while (P > 1 && (size_t)(ax.L + 2 * P * ax.L) * 16 > 80 * 1024) P >>= 1;
+    xa.P = P;
+    xa.ntiles = (inner + P - 1) / P;
+    xa.in_os = in_os;
+    xa.out_os = out_os;
+    xa.in_cs = in_cs;
+    xa.out_cs = out_cs;
+    xa.in = reinterpret_cast<const cpx<double>*>(in);
+    xa.out = reinterpret_cast<cpx<double>*>(out);
+    xa.twg = static_cast<const cpx<double>*>(tw);
+    OpPlan o = op;
+    o.lds_axis = (size_t)(ax.L + 2 * P * ax.L) * 16;
+    return launch_axis<double>(o, xa, inv, outer);
+}
+
+hipError_t run_prolong(const OpPlan& opn, const OpPlan& opm, const double* xn, double* ym)
+{
+    const Geo& gn = opn.g;
+    const Geo& gm = opm.g;
+    const int d = gn.d;
+    hipError_t e;
+    double2* A = static_cast<double2*>(opm.SA);
+    double2* B = static_cast<double2*>(opm.SB);
+    // 1. forward transform of the rows on the N grid into A: [c][rows_N][Hb]
+    {
+        FirstArgs<double> fa{};
+        fa.done = nullptr;
+        fa.g = gn;
+        fa.ax = opn.ax[d - 1];
+        fa.rpb = opn.rpb;
+        fa.npen = opn.npen;
+        fa.x = xn;
+        fa.A = opn.A;
+        fa.out = reinterpret_cast<cpx<double>*>(A);
+        fa.twg = static_cast<const cpx<double>*>(opn.tw[d - 1]);
+        const unsigned nblk = (unsigned)((gn.rows + opn.rpb - 1) / opn.rpb);
+        if (d == 2)
+            e = opn.v2_row ? v2_first<double, 2>(opn, fa, OP_ID, nblk) : launch_first<double, 2>(opn, fa, OP_ID, nblk);
+        else
+            e = opn.v2_row ? v2_first<double, 3>(opn, fa, OP_ID, nblk) : launch_first<double, 3>(opn, fa, OP_ID, nblk);
+        if (e != hipSuccess) return e;
+    }
+    const int Hb = gn.Hb;  // (N_last + 1) / 2, the same band on both grids
+    const int N0 = gn.L[0], M0 = gm.L[0];
+    if (d == 3) {
+        const int N1 = gn.L[1], M1 = gm.L[1];
+        const long long colsN = (long long)N1 * Hb;
+        // 2. forward along axis 1 (N1): A -> B
+        if ((e = axis_custom(opn, opn.ax[1], opn.tw[1], false, N1, 0, N1, 0, Hb, N0, (long long)N1 * Hb,
+                             (long long)N1 * Hb, gn.s1, gn.s1, A, B)) != hipSuccess)
+            return e;
+        // 3. forward along axis 0 (N0): B -> A, columns (k1, k2)
+        if ((e = axis_custom(opn, opn.ax[0], opn.tw[0], false, N0, 0, N0, 0, (int)colsN, 1, 0, 0, N0 * colsN,
+                             N0 * colsN, B, A)) != hipSuccess)
+            return e;
+        // 4. inverse along axis 0 on M0 from the N0 band: A -> B [c][M0][N1 Hb]
+        if ((e = axis_custom(opm, opm.ax[0], opm.tw[0], true, N0, 1, M0, 0, (int)colsN, 1, 0, 0, N0 * colsN,
+                             M0 * colsN, A, B)) != hipSuccess)
+            return e;
+        // 5. inverse along axis 1 on M1 from the N1 band: B -> A [c][M0][M1][Hb]
+        if ((e = axis_custom(opm, opm.ax[1], opm.tw[1], true, N1, 1, M1, 0, Hb, M0, (long long)N1 * Hb,
+                             (long long)M1 * Hb, M0 * colsN, gm.s1, B, A)) != hipSuccess)
+            return e;
+    } else {
+        // 3. forward along axis 0 (N0): A -> B
+        if ((e = axis_custom(opn, opn.ax[0], opn.tw[0], false, N0, 0, N0, 0, Hb, 1, 0, 0, (long long)N0 * Hb,
+                             (long long)N0 * Hb, A, B)) != hipSuccess)
+            return e;
+        // 4. inverse along axis 0 on M0 from the band: B -> A [c][M0][Hb]
+        if ((e = axis_custom(opm, opm.ax[0], opm.tw[0], true, N0, 1, M0, 0, Hb, 1, 0, 0, (long long)N0 * Hb,
+                             (long long)M0 * Hb, B, A)) != hipSuccess)
+            return e;
+    }
+    // 6. rows back to real values on the double grid, scaled by the forward factor 1/|N|
+    LastArgs<double> la{};
+    la.done = nullptr;
+    la.sc = nullptr;
+    la.g = gm;
+    la.ax = opm.ax[d - 1];
+    la.rpb = opm.rpb;
+    la.npen = opm.npen;
+    la.in = reinterpret_cast<const cpx<double>*>(A);
+    la.y = ym;
+    la.sgn = 1.0 / (double)gn.npts;
+    la.A = opm.A;
+    la.partials = opm.partials;
+    la.twg = static_cast<const cpx<double>*>(opm.tw[d - 1]);
+    const unsigned nblk = (unsigned)((gm.rows + opm.rpb - 1) / opm.rpb);
+    if (d == 2)
+        return opm.v2_row ? v2_last<double, 2>(opm, la, EPI_STORE, nblk) : launch_last<double, 2>(opm, la, EPI_STORE, nblk);
+    return opm.v2_row ? v2_last<double, 3>(opm, la, EPI_STORE, nblk) : launch_last<double, 3>(opm, la, EPI_STORE, nblk);
+}
+
 template <typename T>
 hipError_t run_apply(const OpPlan& op, const ApplyArgs& a, int* nblocks_last)
 {

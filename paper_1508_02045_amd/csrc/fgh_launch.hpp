@@ -69,6 +69,10 @@ template <typename T>
 hipError_t run_apply(const OpPlan& op, const ApplyArgs& a, int* nblocks_last);
 
 hipError_t run_reduce(const OpPlan& op, int n, int redop, double* host_out);
+
+// Trigonometric prolongation of a real vector field from the N grid of `opn` to the 2N-1 grid of
+// `opm` (both double precision; opm's spectrum buffers are used as scratch).
+hipError_t run_prolong(const OpPlan& opn, const OpPlan& opm, const double* xn, double* ym);
 hipError_t run_reduce_async(const OpPlan& op, int n, int redop);
 hipError_t run_set_scalar(const OpPlan& op, double* dst, double v);
 hipError_t run_init_loop(const OpPlan& op, double rr, double alpha, double beta, double thr, double npts,

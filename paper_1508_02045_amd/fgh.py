@@ -37,8 +37,8 @@ SOLVERS = {"richardson": FGH_RICHARDSON, "cg": FGH_CG, "chebyshev": FGH_CHEBYSHE
 
 EXPORTS = ["fgh_plan_workspace", "fgh_plan_create", "fgh_plan_destroy", "fgh_plan_grid_points",
            "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32", "fgh_ga_coefficients", "fgh_solve",
-           "fgh_solve_fixed", "fgh_effective", "fgh_plan_set_profiling", "fgh_plan_read_profile",
-           "fgh_request_footprint", "fgh_server_create", "fgh_server_submit", "fgh_server_poll",
+           "fgh_solve_fixed", "fgh_effective", "fgh_gani_bound", "fgh_plan_set_profiling",
+           "fgh_plan_read_profile", "fgh_request_footprint", "fgh_server_create", "fgh_server_submit", "fgh_server_poll",
            "fgh_server_wait", "fgh_server_drain", "fgh_server_stats", "fgh_server_destroy",
            "fgh_status_string"]
 PASS_NAMES = ["first", "axis_fwd", "middle", "axis_inv", "last"]
@@ -111,6 +111,7 @@ def lib():
         L.fgh_solve_fixed.argtypes = [_vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _vp,
                                       ctypes.POINTER(Stats)]
         L.fgh_effective.argtypes = [_vp, _dp, ctypes.c_int, _vp, _dp, _dp]
+        L.fgh_gani_bound.argtypes = [_vp, _vp, _dp, _vp, _dp]
         L.fgh_plan_set_profiling.argtypes = [_vp, ctypes.c_int]
         L.fgh_plan_read_profile.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]
         L.fgh_request_footprint.argtypes = [ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_size_t)]
@@ -129,7 +130,7 @@ def lib():
         L.fgh_status_string.restype = ctypes.c_char_p
         for name in ("fgh_plan_workspace", "fgh_plan_create", "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32",
                      "fgh_ga_coefficients", "fgh_solve", "fgh_solve_fixed", "fgh_effective",
-                     "fgh_plan_set_profiling", "fgh_plan_read_profile"):
+                     "fgh_gani_bound", "fgh_plan_set_profiling", "fgh_plan_read_profile"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -223,6 +224,16 @@ def fgh_effective(plan, E, nrhs, e, d):
     return bil, flux
 
 
+def fgh_gani_bound(gani, ga, E, e):
+    """Guaranteed upper bound (A_{2N-1}(E + R e), E + R e) of a GaNi solution e (eq:ev_bounds_GaNi)."""
+    Ek, Ep = _hostd(E)
+    out = ctypes.c_double()
+    st = lib().fgh_gani_bound(ctypes.c_void_p(gani), ctypes.c_void_p(ga), Ep, _ptr(e), ctypes.byref(out))
+    if st:
+        raise FghError(st, "fgh_gani_bound")
+    return out.value
+
+
 # ----------------------------------------------------------------------------- convenience owner
 class Plan:
     """Owns the workspace (a torch uint8 tensor on the device) and keeps A alive.
@@ -298,6 +309,11 @@ class Plan:
     def effective(self, E, e):
         E = np.atleast_2d(np.asarray(E, dtype=np.float64))
         return fgh_effective(self.handle, E, E.shape[0], e, self.d)
+
+    def gani_bound(self, ga_plan, E, e):
+        """This GaNi plan's solution e prolonged to the double grid of `ga_plan` (a Ga plan of the
+        same microstructure) and integrated exactly there: an upper bound of (A_H E, E)."""
+        return fgh_gani_bound(self.handle, ga_plan.handle, np.asarray(E, dtype=np.float64), e)
 
     def ga_coefficients(self):
         ncoef = (3 if self.d == 2 else 6) if self.a_kind == FGH_A_SYM else 1
