@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <initializer_list>
 #include <new>
 #include <vector>
@@ -297,6 +298,13 @@ struct fgh_plan_s {
     hipGraph_t graph;         // captured loop bodies (reused while the key matches)
     hipGraphExec_t gexec;
     uint64_t gkey;
+    // loop history (fgh_plan_set_history): device ring buffers [nrhs][hist_cap], nullptr: off
+    double* hist_res;
+    double* hist_en;
+    int hist_cap;
+    fgh_plan hist_ga;                    // Ga plan of the GaNi bound monitor, or nullptr
+    std::function<hipError_t()> hist_fn;  // records the entry of the current body count
+    uint64_t hist_key;
 };
 
 namespace {
@@ -455,11 +463,23 @@ fgh_status run_loop(fgh_plan p, const OpPlan& op, Body body, uint64_t key, bool 
 {
     const Scalars* h = reinterpret_cast<const Scalars*>(p->host_buf);
     const bool use_graph = graphs_enabled() && !op.prof && op.stream != nullptr;
+    if (p->hist_fn) {
+        // history scale of the stopping-test quantity and its value before the first body
+        const double hv[2] = {scale > 0 ? 1.0 / scale : 1.0, 1.0};
+        HIPOK(hipMemcpyAsync(op.sc->aux + 12, hv, sizeof hv, hipMemcpyHostToDevice, op.stream));
+        HIPOK(p->hist_fn());
+        key = mix_key(key, p->hist_key);
+    }
+    auto step = [&]() -> hipError_t {
+        hipError_t e = body();
+        if (e != hipSuccess || !p->hist_fn) return e;
+        return p->hist_fn();
+    };
     if (use_graph && (p->gkey != key || !p->gexec)) {
         drop_graph(p);
         HIPOK(hipStreamBeginCapture(op.stream, hipStreamCaptureModeThreadLocal));
         hipError_t ce = hipSuccess;
-        for (int k = 0; k < kGraphBodies && ce == hipSuccess; k++) ce = body();
+        for (int k = 0; k < kGraphBodies && ce == hipSuccess; k++) ce = step();
         hipGraph_t g = nullptr;
         const hipError_t ee = hipStreamEndCapture(op.stream, &g);
         if (ce != hipSuccess || ee != hipSuccess) {
@@ -476,7 +496,7 @@ fgh_status run_loop(fgh_plan p, const OpPlan& op, Body body, uint64_t key, bool 
             if (use_graph) {
                 HIPOK(hipGraphLaunch(p->gexec, op.stream));
             } else {
-                for (int b = 0; b < kGraphBodies; b++) HIPOK(body());
+                for (int b = 0; b < kGraphBodies; b++) HIPOK(step());
             }
         }
         HIPOK(hipMemcpyAsync(p->host_buf, op.sc, sizeof(Scalars), hipMemcpyDeviceToHost, op.stream));
@@ -654,9 +674,67 @@ fgh_status true_residual(fgh_plan p, const double* E, const double* e, double bb
     return FGH_OK;
 }
 
-fgh_status solve_one_fp64(fgh_plan p, int solver, const double* E, double tol, int max_iter, int fixed, double* e,
-                          fgh_stats* st)
+// History entry of plan p's loop for the iterate x (device [d][grid]) at the current body count.
+// Plain: the energy (A(E + x), E + x) on the integration grid, with E read from the loop's
+// scalar block (aux[0..3), or the zeros at aux[3..6) when x is the whole field of Eyre-Milton).
+// Bound monitor (GaNi plan with a Ga plan): the energy of E + R G_N x on the double grid, the
+// guaranteed bound of the iterate (eq:guar_upper_bound_m); G_N also strips the mean of a whole
+// field, so E is added in either case.
+hipError_t hist_record(fgh_plan p, const double* x, bool whole)
 {
+    const OpPlan& op = p->op64;
+    const int nvals = 1 + p->d;
+    if (!p->hist_en) return run_hist(op.stream, op.partials, 0, nvals, op.sc, p->hist_res, nullptr, p->hist_cap, 0.0);
+    hipError_t e;
+    int nb = 0;
+    if (!p->hist_ga) {
+        if ((e = run_effective(op, 1, op.sc->aux + (whole ? 3 : 0), x, &nb)) != hipSuccess) return e;
+        return run_hist(op.stream, op.partials, nb, nvals, op.sc, p->hist_res, p->hist_en, p->hist_cap,
+                        1.0 / (double)p->g.npts);
+    }
+    fgh_plan ga = p->hist_ga;
+    OpPlan opn = op;
+    opn.prof = nullptr;
+    OpPlan opm = ga->op64;
+    opm.stream = op.stream;
+    opm.prof = nullptr;
+    ApplyArgs a;  // ga->r64 <- G_N x
+    a.op = OP_ID;
+    a.x = x;
+    a.mult = MULT_G;
+    a.epi = EPI_STORE;
+    a.sgn = 1.0;
+    a.y = ga->r64;
+    if ((e = run_apply<double>(opn, a, &nb)) != hipSuccess) return e;
+    if ((e = run_prolong(opn, opm, ga->r64, ga->q64)) != hipSuccess) return e;
+    if ((e = run_effective(opm, 1, opm.sc->aux, ga->q64, &nb)) != hipSuccess) return e;
+    return run_hist(op.stream, opm.partials, nb, nvals, op.sc, p->hist_res, p->hist_en, p->hist_cap,
+                    1.0 / (double)ga->g.npts);
+}
+
+// Arms the history recorder for load j of a solve (x: the loop's iterate).
+fgh_status hist_arm(fgh_plan p, const double* E, int j, const double* x, bool whole)
+{
+    if (!p->hist_res && !p->hist_en) return FGH_OK;
+    double v[15] = {0};
+    for (int c = 0; c < p->d; c++) v[c] = E[c];
+    v[14] = (double)((long long)j * p->hist_cap);
+    HIPOK(hipMemcpyAsync(p->op64.sc->aux, v, sizeof v, hipMemcpyHostToDevice, p->stream));
+    if (p->hist_ga) HIPOK(hipMemcpyAsync(p->hist_ga->op64.sc->aux, v, 3 * sizeof(double), hipMemcpyHostToDevice,
+                                         p->stream));
+    p->hist_fn = [p, x, whole]() { return hist_record(p, x, whole); };
+    p->hist_key = key_of({7, bits(p->hist_res), bits(p->hist_en), (uint64_t)p->hist_cap, bits(p->hist_ga),
+                          bits(x), (uint64_t)whole});
+    return FGH_OK;
+}
+
+fgh_status solve_one_fp64(fgh_plan p, int solver, const double* E, double tol, int max_iter, int fixed, double* e,
+                          fgh_stats* st, int load)
+{
+    struct Disarm {
+        fgh_plan p;
+        ~Disarm() { p->hist_fn = nullptr; }
+    } disarm{p};
     const long long n = (long long)p->d * p->g.npts;
     const double S = (double)p->g.npts;
     double normE = 0.0;
@@ -669,9 +747,16 @@ fgh_status solve_one_fp64(fgh_plan p, int solver, const double* E, double tol, i
         if ((s = rhs<double>(p, E, p->r64, &bb, &ae2))) return s;
         HIPOK(run_fill<double>(p->stream, n, e, 0.0));
         const bool zero = !(std::sqrt(bb / S) > kZeroRhs * std::sqrt(ae2 / S));
+        if ((s = hist_arm(p, E, load, e, false))) return s;
         if (zero) {
             so.iters = 0;
             so.res = 0.0;
+            if (p->hist_fn) {  // the single entry m = 0 with the test quantity 0
+                HIPOK(run_init_loop(p->op64, 0.0, 0.0, 0.0, -1.0, S, 0.0, 0.0, 0.0, 0));
+                const double hv[2] = {1.0, 0.0};
+                HIPOK(hipMemcpyAsync(p->op64.sc->aux + 12, hv, sizeof hv, hipMemcpyHostToDevice, p->stream));
+                HIPOK(p->hist_fn());
+            }
         } else if (solver == FGH_CG) {
             if ((s = cg_core<double>(p, e, p->r64, p->p64, p->q64, tol, max_iter, fixed, &so))) return s;
         } else {
@@ -679,9 +764,11 @@ fgh_status solve_one_fp64(fgh_plan p, int solver, const double* E, double tol, i
         }
     } else if (solver == FGH_RICHARDSON) {
         HIPOK(run_fill<double>(p->stream, n, e, 0.0));
+        if ((s = hist_arm(p, E, load, e, false))) return s;
         if ((s = rich_core<double>(p, e, E, tol * normE, max_iter, fixed, normE, &so))) return s;
     } else {
         HIPOK(run_fill_field<double>(p->stream, p->d, p->g.npts, e, E));
+        if ((s = hist_arm(p, E, load, e, true))) return s;
         if ((s = em_core<double>(p, e, E, nullptr, tol * normE, max_iter, fixed, normE, &so))) return s;
         double negE[3] = {-E[0], -E[1], p->d == 3 ? -E[2] : 0.0};
         // e <- x - E
@@ -1206,7 +1293,7 @@ static fgh_status solve_common(fgh_plan p, fgh_solver solver, const double* E, i
         if (p->prec == FGH_FP32_REFINED && fixed <= 0)
             s = solve_one_refined(p, solver, Ej, tol, max_iter, ej, &st);
         else
-            s = solve_one_fp64(p, solver, Ej, tol, max_iter, fixed, ej, &st);
+            s = solve_one_fp64(p, solver, Ej, tol, max_iter, fixed, ej, &st, j);
         if (s) return s;
         if (hipStreamSynchronize(p->stream) != hipSuccess) return FGH_E_DEVICE;
         const auto t1 = std::chrono::steady_clock::now();
@@ -1256,6 +1343,30 @@ fgh_status fgh_effective(fgh_plan p, const double* E, int nrhs, const double* e,
         for (int q = 0; q < nrhs * nrhs; q++) bilinear[q] = host[q] / S;
     if (flux)
         for (int q = 0; q < nrhs * d; q++) flux[q] = host[nrhs * nrhs + q] / S;
+    return FGH_OK;
+}
+
+fgh_status fgh_plan_set_history(fgh_plan p, double* res_hist, double* energy_hist, int capacity, fgh_plan ga)
+{
+    if (!p) return FGH_E_INVALID;
+    if (!res_hist && !energy_hist) {
+        if (ga) return FGH_E_INVALID;
+        p->hist_res = p->hist_en = nullptr;
+        p->hist_cap = 0;
+        p->hist_ga = nullptr;
+        return FGH_OK;
+    }
+    if (capacity < 1) return FGH_E_INVALID;
+    if (p->prec != FGH_FP64) return FGH_E_UNSUPPORTED;
+    if (ga) {
+        if (!energy_hist || p->rule != FGH_GANI || ga->rule != FGH_GA || ga->d != p->d) return FGH_E_INVALID;
+        for (int a = 0; a < p->d; a++)
+            if (ga->N[a] != p->N[a]) return FGH_E_INVALID;
+    }
+    p->hist_res = res_hist;
+    p->hist_en = energy_hist;
+    p->hist_cap = capacity;
+    p->hist_ga = ga;
     return FGH_OK;
 }
 

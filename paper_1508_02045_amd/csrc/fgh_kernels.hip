@@ -1462,6 +1462,33 @@ hipError_t run_effective(const OpPlan& op, int nrhs, const double* E, const doub
     return hipGetLastError();
 }
 
+// One entry of a solver's history at body count m = s->m, slot base + m mod cap: the stopping-test
+// quantity (s->last times aux[12]; aux[13] before the first body) and, when `en` is set, the
+// energy reduced from the first of the nvals interleaved partial sums, times en_scale.
+__global__ __launch_bounds__(kThreads) void k_hist(const double* __restrict__ partials, int nb, int nvals,
+                                                   const Scalars* s, double* res, double* en, int cap,
+                                                   double en_scale)
+{
+    __shared__ double red[kThreads / 64];
+    double v = 0.0;
+    if (en)
+        for (int i = threadIdx.x; i < nb; i += blockDim.x) v += partials[(long long)i * nvals];
+    const double tot = block_sum(v, red);
+    if (threadIdx.x == 0) {
+        const int m = s->m;
+        const long long slot = (long long)s->aux[14] + m % cap;
+        if (res) res[slot] = m == 0 ? s->aux[13] : s->last * s->aux[12];
+        if (en) en[slot] = tot * en_scale;
+    }
+}
+
+hipError_t run_hist(hipStream_t stream, const double* partials, int nb, int nvals, const Scalars* sc, double* res,
+                    double* en, int cap, double en_scale)
+{
+    hipLaunchKernelGGL(k_hist, dim3(1), dim3(kThreads), 0, stream, partials, nb, nvals, sc, res, en, cap, en_scale);
+    return hipGetLastError();
+}
+
 hipError_t run_reduce_multi(const OpPlan& op, int nblocks, int nvals, double* host_out)
 {
     double* dev_out = op.sc->aux + 16;

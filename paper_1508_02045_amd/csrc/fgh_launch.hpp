@@ -99,6 +99,9 @@ hipError_t run_dot(const OpPlan& op, long long n, const T* a, const T* b, int* n
 
 // Effective quantities: partials [nblocks][nrhs*nrhs + nrhs*d].
 hipError_t run_effective(const OpPlan& op, int nrhs, const double* E, const double* e, int* nblocks);
+// History entry of a solver loop (stopping-test quantity, energy from k_effective partial sums).
+hipError_t run_hist(hipStream_t stream, const double* partials, int nb, int nvals, const Scalars* sc, double* res,
+                    double* en, int cap, double en_scale);
 hipError_t run_reduce_multi(const OpPlan& op, int nblocks, int nvals, double* host_out);
 
 // Coefficient preparation.

@@ -37,7 +37,7 @@ SOLVERS = {"richardson": FGH_RICHARDSON, "cg": FGH_CG, "chebyshev": FGH_CHEBYSHE
 
 EXPORTS = ["fgh_plan_workspace", "fgh_plan_create", "fgh_plan_destroy", "fgh_plan_grid_points",
            "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32", "fgh_ga_coefficients", "fgh_solve",
-           "fgh_solve_fixed", "fgh_effective", "fgh_gani_bound", "fgh_plan_set_profiling",
+           "fgh_solve_fixed", "fgh_effective", "fgh_gani_bound", "fgh_plan_set_history", "fgh_plan_set_profiling",
            "fgh_plan_read_profile", "fgh_request_footprint", "fgh_server_create", "fgh_server_submit", "fgh_server_poll",
            "fgh_server_wait", "fgh_server_drain", "fgh_server_stats", "fgh_server_destroy",
            "fgh_status_string"]
@@ -112,6 +112,7 @@ def lib():
                                       ctypes.POINTER(Stats)]
         L.fgh_effective.argtypes = [_vp, _dp, ctypes.c_int, _vp, _dp, _dp]
         L.fgh_gani_bound.argtypes = [_vp, _vp, _dp, _vp, _dp]
+        L.fgh_plan_set_history.argtypes = [_vp, _vp, _vp, ctypes.c_int, _vp]
         L.fgh_plan_set_profiling.argtypes = [_vp, ctypes.c_int]
         L.fgh_plan_read_profile.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]
         L.fgh_request_footprint.argtypes = [ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_size_t)]
@@ -130,7 +131,7 @@ def lib():
         L.fgh_status_string.restype = ctypes.c_char_p
         for name in ("fgh_plan_workspace", "fgh_plan_create", "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32",
                      "fgh_ga_coefficients", "fgh_solve", "fgh_solve_fixed", "fgh_effective",
-                     "fgh_gani_bound", "fgh_plan_set_profiling", "fgh_plan_read_profile"):
+                     "fgh_gani_bound", "fgh_plan_set_history", "fgh_plan_set_profiling", "fgh_plan_read_profile"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -314,6 +315,28 @@ class Plan:
         """This GaNi plan's solution e prolonged to the double grid of `ga_plan` (a Ga plan of the
         same microstructure) and integrated exactly there: an upper bound of (A_H E, E)."""
         return fgh_gani_bound(self.handle, ga_plan.handle, np.asarray(E, dtype=np.float64), e)
+
+    def set_history(self, capacity=0, nrhs=1, residual=True, energy=True, bound_plan=None):
+        """Record per-iteration histories of later solves into device arrays [nrhs][capacity]
+        (residual quantity of the stopping test; energy U_E of the iterate, or with bound_plan, a Ga
+        plan of the same N, the GaNi guaranteed bound of the iterate).  capacity 0 turns it off.
+        Returns (res, energy) tensors (None where not recorded)."""
+        if capacity <= 0:
+            st = lib().fgh_plan_set_history(ctypes.c_void_p(self.handle), None, None, 0, None)
+            self._hist = None
+            if st:
+                raise FghError(st, "fgh_plan_set_history")
+            return None, None
+        mk = lambda on: (self.torch.full((nrhs, capacity), float("nan"), dtype=self.torch.float64,
+                                         device=self.workspace.device) if on else None)
+        res, en = mk(residual), mk(energy)
+        st = lib().fgh_plan_set_history(ctypes.c_void_p(self.handle), _ptr(res) if res is not None else None,
+                                        _ptr(en) if en is not None else None, int(capacity),
+                                        ctypes.c_void_p(bound_plan.handle) if bound_plan is not None else None)
+        if st:
+            raise FghError(st, "fgh_plan_set_history")
+        self._hist = (res, en, bound_plan)  # keep alive while recording
+        return res, en
 
     def ga_coefficients(self):
         ncoef = (3 if self.d == 2 else 6) if self.a_kind == FGH_A_SYM else 1
