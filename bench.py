@@ -30,7 +30,7 @@ PASS_KERNELS = {"first": "k_first", "axis_fwd": "k_axis<fwd>", "middle": "k_midd
                 "last": "k_last"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "middle_pass_135_fp64_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1508_02045_amd", "csrc", f) for f in
-                  ("fgh_kernels.hip", "fgh_fft.hpp", "fgh_internal.hpp")]
+                  ("fgh_kernels.hip", "fgh_fft.hpp", "fgh_internal.hpp", "fgh_v2.hpp", "fgh_args.hpp")]
 
 
 def log(msg):
@@ -53,7 +53,13 @@ def pass_bytes(g, d, p_bytes):
     s1 = N[0] * N[1] * H if d == 3 else N[0] * H
     s2 = s1
     cplx = 2 * p_bytes
-    return {"middle": 2 * d * s2 * cplx, "axis_fwd": d * (s1 + s2) * cplx, "axis_inv": d * (s1 + s2) * cplx}
+    npts = 1
+    for v in N:
+        npts *= v
+    # first (plain apply, phase map): read x and one byte of phase per point, write the spectrum;
+    # last (plain store): read the spectrum, write y
+    return {"middle": 2 * d * s2 * cplx, "axis_fwd": d * (s1 + s2) * cplx, "axis_inv": d * (s1 + s2) * cplx,
+            "first": d * npts * p_bytes + npts + d * s1 * cplx, "last": d * s1 * cplx + d * npts * p_bytes}
 
 
 def c4_section(fgh, inputs, torch, np, n):
@@ -190,6 +196,43 @@ def served_section(fgh, inputs, np, n_req, max_active=4, pool_gb=24):
                     "eyre_milton": sum(q["solver"] == "eyre_milton" for q in reqs)}}
 
 
+COPY_BYTES = 512 * 1024 * 1024
+
+
+def applies_only(args, fgh, inputs, torch, np):
+    """K plain applications y = G A x of the bench workload with per-pass timing, then a plain
+    device copy of COPY_BYTES (read COPY_BYTES, write COPY_BYTES) that calibrates the HBM byte
+    counters of a profiler run."""
+    w = inputs.config2(N=args.n) if args.workload == "spheres135" else inputs.config4(1e3, N=243)
+    tab = np.stack([inputs.sym_pack(t[None])[:, 0] for t in w.tables])
+    prec = fgh.FGH_FP64 if args.precision == "fp64" else fgh.FGH_FP32_REFINED
+    plan = fgh.Plan(w.N, precision=prec, phase=torch.from_numpy(w.phase).cuda(), phase_table=tab, c_A=1.0,
+                    C_A=w.contrast)
+    dt = torch.float64 if prec == fgh.FGH_FP64 else torch.float32
+    x = torch.randn((3,) + w.N, dtype=dt, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        plan.apply(x, y)
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    for i in range(args.applies_only):
+        plan.apply(x, y)
+    prof = plan.read_profile()
+    plan.set_profiling(False)
+    torch.cuda.synchronize()
+    log(f"[bench] {args.applies_only} applies done")
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    pb = pass_bytes(w.N, 3, 8 if prec == fgh.FGH_FP64 else 4)
+    per = {k: round(v[0] * 1e3 / max(v[1], 1), 2) for k, v in prof.items()}
+    print(json.dumps({"workload": w.name, "precision": args.precision, "applies": args.applies_only,
+                      "per_pass_avg_us": per, "algorithmic_bytes_per_launch": pb,
+                      "copy_bytes_each_way": COPY_BYTES}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +247,12 @@ def main():
     ap.add_argument("--c4-n", type=int, default=243)
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-pass HIP events (solver loops then replay HIP graphs)")
+    ap.add_argument("--applies-only", type=int, default=0, metavar="K",
+                    help="counter runs: K plain operator applications of the workload (and a copy of known "
+                         "size for calibration), a summary line, nothing else")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64", help="with --applies-only")
+    ap.add_argument("--workload", choices=["spheres135", "spheres243"], default="spheres135",
+                    help="with --applies-only: the 135^3 r=8 f=0.30 or the 243^3 r=12 f=0.25 Boolean spheres")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not part "
@@ -216,6 +265,9 @@ def main():
     from paper_1508_02045_amd import fgh, inputs
 
     torch.cuda.set_device(0)
+    if args.applies_only > 0:
+        applies_only(args, fgh, inputs, torch, np)
+        return
     n = args.n
     log(f"[bench] generating Boolean spheres {n}^3 r=8 f=0.30")
     w = inputs.config2(N=n)

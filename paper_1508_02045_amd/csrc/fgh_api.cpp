@@ -2,6 +2,7 @@
 // solver drivers of Algorithms 1-4 (Sec. 3) on top of the gfx950 passes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -86,9 +87,12 @@ Config choose_config(const Geo& g, size_t cs /* bytes per complex */, size_t rs 
     const int d = g.d;
     const int Ll = g.L[d - 1];
     const size_t tabb = kMaxPhases * 6 * rs;
-    c.v2_row = v2_supported(Ll);
-    c.v2_axis = d == 3 && v2_supported(g.L[1]);
-    c.v2_mid = v2_supported(g.L[0]);
+    // the specialised kernels index within a vector or spectrum with 32-bit offsets
+    const long long span = (long long)d * std::max(g.npts, std::max(g.s1, g.s2));
+    const bool small = span < (1LL << 31);
+    c.v2_row = small && v2_supported(Ll);
+    c.v2_axis = small && d == 3 && v2_supported(g.L[1]);
+    c.v2_mid = small && v2_supported(g.L[0]);
     c.rpb = 1;
     const int rpb_cap = env_int("FGH_RPB", c.v2_row ? 8 : 32);
     for (int rpb = rpb_cap; rpb >= 1; rpb--) {

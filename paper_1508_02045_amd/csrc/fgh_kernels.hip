@@ -1039,8 +1039,10 @@ static hipError_t v2_middle(const OpPlan& op, const MidArgs<T>& ma, int mult)
 {
     const size_t lds = op.lds_mid;
     switch (ma.ax.L) {
-#define C(LL, A1, A2) \
-    case LL: LAUNCH_LDS((k2_middle<T, D, A1, A2>), dim3(ma.ntiles), lds, op.stream, ma, mult); break;
+#define C(LL, A1, A2)                                                                          \
+    case LL:                                                                                   \
+        LAUNCH_LDS((k2_middle<T, D, A1, A2>), dim3(ma.ntiles), lds, op.stream, ma, mult); \
+        break;
         V2_COL_CASES(C)
 #undef C
         default: return hipErrorInvalidValue;

@@ -131,38 +131,45 @@ __device__ __forceinline__ void coef_shift_solve_rt(const CoefArgs& A, const T* 
 // discarded.
 constexpr int kU = 4;
 
+// Points per thread and chunk for a row length L: one chunk covers a tile of up to 8 rows.
+constexpr int ku_for(int L)
+{
+    const int k = (8 * L + kThreads - 1) / kThreads;
+    return k < 2 ? 2 : (k > 8 ? 8 : k);
+}
+
 // Stage 0 of the first pass for kU points starting at this thread's index base + threadIdx.x:
 // z = A(pt) u with u per FirstOp; writes the real rows Zr[(r D + c) L + i].
-template <typename T, int D, int L>
+template <typename T, int D, int L, int KU>
 __device__ __forceinline__ void first_stage0_chunk(const FirstArgs<T>& a, int op, const T* tab, T beta, int base,
-                                                   int total, long long pt0, long long ptend, T* Zr)
+                                                   int total, int lim, long long pt0, T* Zr)
 {
-    const long long npts = a.g.npts;
-    long long pt[kU];
-    bool ok[kU];
+    const unsigned npts = (unsigned)a.g.npts;  // 32-bit offsets: d |grid| < 2^31 here
+    unsigned pt[KU];
+    bool ok[KU];
 #pragma unroll
-    for (int u = 0; u < kU; u++) {
+    for (int u = 0; u < KU; u++) {
         const int idx = base + u * (int)blockDim.x + (int)threadIdx.x;
-        ok[u] = idx < total && pt0 + idx < ptend;
-        pt[u] = ok[u] ? pt0 + idx : 0;
+        ok[u] = idx < lim;
+        pt[u] = ok[u] ? (unsigned)(pt0 + idx) : 0u;
     }
-    T uu[kU][D];
+    T uu[KU][D];
     if (op == OP_E) {
 #pragma unroll
-        for (int u = 0; u < kU; u++)
+        for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) uu[u][c] = T(a.E[c]);
     } else if (op == OP_AP_CG) {
-        T rr[kU][D], pp[kU][D];
+        T rr[KU][D], pp[KU][D];
 #pragma unroll
-        for (int u = 0; u < kU; u++)
+        for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) {
                 rr[u][c] = a.r[c * npts + pt[u]];
                 pp[u][c] = a.p[c * npts + pt[u]];
             }
 #pragma unroll
-        for (int u = 0; u < kU; u++)
+        for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) {
                 uu[u][c] = rr[u][c] + beta * pp[u][c];
@@ -170,55 +177,55 @@ __device__ __forceinline__ void first_stage0_chunk(const FirstArgs<T>& a, int op
             }
     } else {
 #pragma unroll
-        for (int u = 0; u < kU; u++)
+        for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) uu[u][c] = a.x[c * npts + pt[u]];
         if (op == OP_AX) {
 #pragma unroll
-            for (int u = 0; u < kU; u++)
+            for (int u = 0; u < KU; u++)
 #pragma unroll
                 for (int c = 0; c < D; c++) uu[u][c] += T(a.E[c]);
         }
     }
-    T z[kU][D];
+    T z[KU][D];
     if (op == OP_ID) {
 #pragma unroll
-        for (int u = 0; u < kU; u++)
+        for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) z[u][c] = uu[u][c];
     } else if (a.A.kind == AK_PHASE) {
-        int ph[kU];
+        int ph[KU];
 #pragma unroll
-        for (int u = 0; u < kU; u++) ph[u] = a.A.phase[pt[u]];
+        for (int u = 0; u < KU; u++) ph[u] = a.A.phase[pt[u]];
 #pragma unroll
-        for (int u = 0; u < kU; u++) sym_mul<T, D>(tab + 6 * ph[u], uu[u], z[u]);
+        for (int u = 0; u < KU; u++) sym_mul<T, D>(tab + 6 * ph[u], uu[u], z[u]);
     } else if (a.A.kind == AK_ISO) {
         const T* cc = static_cast<const T*>(a.A.coef);
-        T co[kU];
+        T co[KU];
 #pragma unroll
-        for (int u = 0; u < kU; u++) co[u] = cc[pt[u]];
+        for (int u = 0; u < KU; u++) co[u] = cc[pt[u]];
 #pragma unroll
-        for (int u = 0; u < kU; u++)
+        for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) z[u][c] = co[u] * uu[u][c];
     } else {
         const T* cc = static_cast<const T*>(a.A.coef);
-        T co[kU][6];
+        T co[KU][6];
 #pragma unroll
-        for (int u = 0; u < kU; u++)
+        for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int q = 0; q < ncoef_of<D>(); q++) co[u][q] = cc[q * npts + pt[u]];
 #pragma unroll
-        for (int u = 0; u < kU; u++) sym_mul<T, D>(co[u], uu[u], z[u]);
+        for (int u = 0; u < KU; u++) sym_mul<T, D>(co[u], uu[u], z[u]);
     }
     if (op == OP_EM) {
 #pragma unroll
-        for (int u = 0; u < kU; u++)
+        for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) z[u][c] -= T(a.omega) * uu[u][c];
     }
 #pragma unroll
-    for (int u = 0; u < kU; u++) {
+    for (int u = 0; u < KU; u++) {
         const int idx = base + u * (int)blockDim.x + (int)threadIdx.x;
         if (idx < total) {
             const int r = idx / L;
@@ -230,19 +237,19 @@ __device__ __forceinline__ void first_stage0_chunk(const FirstArgs<T>& a, int op
 }
 
 // Epilogue of the last pass for kU points: y from the real rows Zr, the solver update per Epi.
-template <typename T, int D, int L, int epi>
+template <typename T, int D, int L, int epi, int KU>
 __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, const T* tabinv, int base,
-                                                      int total, long long pt0, long long ptend, const T* Zr)
+                                                      int total, int lim, long long pt0, const T* Zr)
 {
-    const long long npts = a.g.npts;
-    long long pt[kU];
-    bool ok[kU];
-    T y[kU][D];
+    const unsigned npts = (unsigned)a.g.npts;  // 32-bit offsets: d |grid| < 2^31 here
+    unsigned pt[KU];
+    bool ok[KU];
+    T y[KU][D];
 #pragma unroll
-    for (int u = 0; u < kU; u++) {
+    for (int u = 0; u < KU; u++) {
         const int idx = base + u * (int)blockDim.x + (int)threadIdx.x;
-        ok[u] = idx < total && pt0 + idx < ptend;
-        pt[u] = ok[u] ? pt0 + idx : 0;
+        ok[u] = idx < lim;
+        pt[u] = ok[u] ? (unsigned)(pt0 + idx) : 0u;
         const int ii = ok[u] ? idx : 0;
         const int r = ii / L;
         const int i = ii - r * L;
@@ -253,7 +260,7 @@ __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, cons
     if constexpr (epi == EPI_STORE) {
         const T sg = T(a.sgn);
 #pragma unroll
-        for (int u = 0; u < kU; u++)
+        for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) {
                 const T v = sg * y[u][c];
@@ -263,14 +270,14 @@ __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, cons
                 }
             }
     } else if constexpr (epi == EPI_RICH) {
-        T xv[kU][D];
+        T xv[KU][D];
 #pragma unroll
-        for (int u = 0; u < kU; u++)
+        for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) xv[u][c] = a.x[c * npts + pt[u]];
         const T w = T(-a.omega);
 #pragma unroll
-        for (int u = 0; u < kU; u++)
+        for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) {
                 const T st = w * y[u][c];
@@ -280,13 +287,13 @@ __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, cons
                 }
             }
     } else if constexpr (epi == EPI_CG) {
-        T pv[kU][D];
+        T pv[KU][D];
 #pragma unroll
-        for (int u = 0; u < kU; u++)
+        for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) pv[u][c] = a.p[c * npts + pt[u]];
 #pragma unroll
-        for (int u = 0; u < kU; u++)
+        for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++)
                 if (ok[u]) {
@@ -294,24 +301,24 @@ __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, cons
                     acc += double(y[u][c]) * double(pv[u][c]);
                 }
     } else if constexpr (epi == EPI_CHEB) {
-        T xv[kU][D], rv[kU][D], pv[kU][D];
+        T xv[KU][D], rv[KU][D], pv[KU][D];
 #pragma unroll
-        for (int u = 0; u < kU; u++)
+        for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) {
-                const long long o = c * npts + pt[u];
+                const unsigned o = c * npts + pt[u];
                 xv[u][c] = a.x[o];
                 rv[u][c] = a.r[o];
                 pv[u][c] = a.p[o];
             }
         const T al = T(a.sc ? a.sc->alpha : a.alpha), be = T(a.sc ? a.sc->beta : a.beta);
 #pragma unroll
-        for (int u = 0; u < kU; u++)
+        for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) {
                 const T rn = rv[u][c] - al * y[u][c];
                 if (ok[u]) {
-                    const long long o = c * npts + pt[u];
+                    const unsigned o = c * npts + pt[u];
                     a.r[o] = rn;
                     a.x[o] = xv[u][c] + al * pv[u][c];
                     a.p[o] = rn - be * pv[u][c];
@@ -319,23 +326,23 @@ __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, cons
                 }
             }
     } else {  // EPI_EM
-        T xv[kU][D], sv[kU][D];
+        T xv[KU][D], sv[KU][D];
 #pragma unroll
-        for (int u = 0; u < kU; u++)
+        for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) {
-                const long long o = c * npts + pt[u];
+                const unsigned o = c * npts + pt[u];
                 xv[u][c] = a.x[o];
                 sv[u][c] = a.src ? a.src[o] : T(2.0 * a.omega * a.E[c]);
             }
         const T w = T(a.omega);
-        T xn[kU][D];
+        T xn[KU][D];
         if (a.A.kind == AK_PHASE) {
-            int ph[kU];
+            int ph[KU];
 #pragma unroll
-            for (int u = 0; u < kU; u++) ph[u] = a.A.phase[pt[u]];
+            for (int u = 0; u < KU; u++) ph[u] = a.A.phase[pt[u]];
 #pragma unroll
-            for (int u = 0; u < kU; u++) {
+            for (int u = 0; u < KU; u++) {
                 T v[D];
 #pragma unroll
                 for (int c = 0; c < D; c++) v[c] = a.src ? y[u][c] : y[u][c] + sv[u][c];
@@ -343,22 +350,22 @@ __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, cons
             }
         } else if (a.A.kind == AK_ISO) {
             const T* cc = static_cast<const T*>(a.A.coef);
-            T co[kU];
+            T co[KU];
 #pragma unroll
-            for (int u = 0; u < kU; u++) co[u] = cc[pt[u]];
+            for (int u = 0; u < KU; u++) co[u] = cc[pt[u]];
 #pragma unroll
-            for (int u = 0; u < kU; u++)
+            for (int u = 0; u < KU; u++)
 #pragma unroll
                 for (int c = 0; c < D; c++) xn[u][c] = (a.src ? y[u][c] : y[u][c] + sv[u][c]) / (co[u] + w);
         } else {
             const T* cc = static_cast<const T*>(a.A.coef);
-            T co[kU][6];
+            T co[KU][6];
 #pragma unroll
-            for (int u = 0; u < kU; u++)
+            for (int u = 0; u < KU; u++)
 #pragma unroll
                 for (int q = 0; q < ncoef_of<D>(); q++) co[u][q] = cc[q * npts + pt[u]];
 #pragma unroll
-            for (int u = 0; u < kU; u++) {
+            for (int u = 0; u < KU; u++) {
                 T v[D];
 #pragma unroll
                 for (int c = 0; c < D; c++) v[c] = a.src ? y[u][c] : y[u][c] + sv[u][c];
@@ -366,7 +373,7 @@ __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, cons
             }
         }
 #pragma unroll
-        for (int u = 0; u < kU; u++)
+        for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) {
                 T xnew = xn[u][c];
@@ -435,9 +442,11 @@ __global__ __launch_bounds__(kThreads) void k2_first(FirstArgs<T> a, int op)
     {
         const int total = a.rpb * L;
         const long long pt0 = row0 * L;
-        const long long ptend = a.g.rows * (long long)L;
-        for (int base = 0; base < total; base += kU * blockDim.x)
-            first_stage0_chunk<T, D, L>(a, op, tab, beta, base, total, pt0, ptend, Zr);
+        const long long left = a.g.rows * (long long)L - pt0;
+        const int lim = left < total ? (int)left : total;
+        constexpr int KU = ku_for(L);
+        for (int base = 0; base < total; base += KU * blockDim.x)
+            first_stage0_chunk<T, D, L, KU>(a, op, tab, beta, base, total, lim, pt0, Zr);
     }
     __syncthreads();
     for (int job = threadIdx.x; job < npairs * L1; job += blockDim.x) {
@@ -472,22 +481,27 @@ __global__ __launch_bounds__(kThreads) void k2_first(FirstArgs<T> a, int op)
         for (int k1 = 0; k1 < L1; k1++) x[L2 * k1] = sv[k1];
     }
     __syncthreads();
+    // stage S: thread (tq, k) stores frequency k of the real rows q = tq, tq + qstep, ...
+    // (32-bit element offsets: the plan keeps d |spectrum| below 2^31 for these kernels)
     const int Hb = a.g.Hb;
-    const int nreal = a.rpb * D;
-    for (int idx = threadIdx.x; idx < nreal * Hb; idx += blockDim.x) {
-        const int q = idx / Hb;
-        const int k = idx - q * Hb;
-        const int r = q / D;
-        const int c = q - r * D;
-        const long long row = row0 + r;
-        if (row >= a.g.rows) continue;
-        const cpx<T>* x = X + (q >> 1) * L;
-        const cpx<T> Z = x[k];
-        const cpx<T> Zm = x[k ? L - k : 0];
-        const cpx<T> v = (q & 1) ? cpx<T>{T(0.5) * (Z.y + Zm.y), T(-0.5) * (Z.x - Zm.x)}
-                                 : cpx<T>{T(0.5) * (Z.x + Zm.x), T(0.5) * (Z.y - Zm.y)};
-        a.out[c * a.g.s1 + row * Hb + k] = v;
-    }
+    const int qstep = (int)blockDim.x / Hb;
+    const int tq = (int)threadIdx.x / Hb;
+    const int k = (int)threadIdx.x - tq * Hb;
+    const int nrows = (int)(a.g.rows - row0 < a.rpb ? a.g.rows - row0 : a.rpb);
+    const int qend = nrows * D;
+    const unsigned s1 = (unsigned)a.g.s1;
+    cpx<T>* outb = a.out + row0 * Hb + k;
+    if (tq < qstep)
+        for (int q = tq; q < qend; q += qstep) {
+            const int r = q / D;
+            const int c = q - r * D;
+            const cpx<T>* x = X + (q >> 1) * L;
+            const cpx<T> Z = x[k];
+            const cpx<T> Zm = x[k ? L - k : 0];
+            const cpx<T> v = (q & 1) ? cpx<T>{T(0.5) * (Z.y + Zm.y), T(-0.5) * (Z.x - Zm.x)}
+                                     : cpx<T>{T(0.5) * (Z.x + Zm.x), T(0.5) * (Z.y - Zm.y)};
+            outb[(unsigned)c * s1 + (unsigned)(r * Hb)] = v;
+        }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -522,7 +536,7 @@ __global__ __launch_bounds__(kThreads) void k2_axis(AxisArgs<T> a, int B)
             int si = pos;
             bool ok = j < a.inner;
             if (a.bin) ok = ok && band_index(pos, L, B, &si);
-            s[n2] = ok ? in[(long long)si * a.inner + j] : cpx<T>{T(0), T(0)};
+            s[n2] = ok ? in[(unsigned)(si * a.inner + j)] : cpx<T>{T(0), T(0)};
         }
         reg_dft<T, L2, INV>(s);
         cpx<T>* y = Y + p * L + n1 * L2;
@@ -550,7 +564,7 @@ __global__ __launch_bounds__(kThreads) void k2_axis(AxisArgs<T> a, int B)
                 const int pos = k2 + L2 * k1;
                 int so = pos;
                 if (a.bout && !band_index(pos, L, B, &so)) continue;
-                out[(long long)so * a.inner + j] = s[k1];
+                out[(unsigned)(so * a.inner + j)] = s[k1];
             }
         }
     }
@@ -561,7 +575,7 @@ __global__ __launch_bounds__(kThreads) void k2_axis(AxisArgs<T> a, int B)
 // multiplier and inverse step B in registers -> LDS -> inverse step A.
 // ------------------------------------------------------------------------------------------
 template <typename T, int D, int L1, int L2>
-__global__ __launch_bounds__(kThreads) void k2_middle(MidArgs<T> a, int mult)
+__device__ __forceinline__ void middle_body(const MidArgs<T>& a, int mult)
 {
     if (a.done && *a.done) return;
     constexpr int L = L1 * L2;
@@ -584,7 +598,7 @@ __global__ __launch_bounds__(kThreads) void k2_middle(MidArgs<T> a, int mult)
         cpx<T> s[L2];
 #pragma unroll
         for (int n2 = 0; n2 < L2; n2++)
-            s[n2] = (j < a.cols) ? in[(long long)(n1 + L1 * n2) * a.cols] : cpx<T>{T(0), T(0)};
+            s[n2] = (j < a.cols) ? in[(unsigned)((n1 + L1 * n2) * a.cols)] : cpx<T>{T(0), T(0)};
         reg_dft<T, L2, false>(s);
         cpx<T>* y = Y + c * PL + p * L + n1 * L2;
         int m = 0;
@@ -676,9 +690,15 @@ __global__ __launch_bounds__(kThreads) void k2_middle(MidArgs<T> a, int mult)
         if (j < a.cols) {
             cpx<T>* outp = a.buf + c * a.cs + j;
 #pragma unroll
-            for (int n2 = 0; n2 < L2; n2++) outp[(long long)(n1 + L1 * n2) * a.cols] = s[n2];
+            for (int n2 = 0; n2 < L2; n2++) outp[(unsigned)((n1 + L1 * n2) * a.cols)] = s[n2];
         }
     }
+}
+
+template <typename T, int D, int L1, int L2>
+__global__ __launch_bounds__(kThreads) void k2_middle(MidArgs<T> a, int mult)
+{
+    middle_body<T, D, L1, L2>(a, mult);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -708,25 +728,36 @@ __global__ __launch_bounds__(kThreads) void k2_last(LastArgs<T> a)
         for (int m = threadIdx.x; m < kMaxPhases * 6; m += blockDim.x) tab[m] = T(a.A.tab_inv[m / 6][m % 6]);
     const long long row0 = xcd_tile(blockIdx.x, gridDim.x) * a.rpb;
     const int Hb = a.g.Hb;
-    const int nreal = a.rpb * D;
-    for (int base = 0; base < 2 * npairs * Hb; base += kU * blockDim.x) {
-        cpx<T> v[kU];
+    {
+        // stage L: thread (tq, k) loads frequency k of the real rows q = tq, tq + qstep, ...,
+        // kQ rows per batch with all loads issued before the LDS stores (32-bit offsets)
+        constexpr int kQ = 6;
+        const int qstep = (int)blockDim.x / Hb;
+        const int tq = (int)threadIdx.x / Hb;
+        const int k = (int)threadIdx.x - tq * Hb;
+        const int nrows = (int)(a.g.rows - row0 < a.rpb ? a.g.rows - row0 : a.rpb);
+        const int qend = nrows * D;
+        const unsigned s1 = (unsigned)a.g.s1;
+        const cpx<T>* inb = a.in + row0 * Hb + k;
+        if (tq < qstep)
+            for (int q0 = tq; q0 < 2 * npairs; q0 += kQ * qstep) {
+                cpx<T> v[kQ];
 #pragma unroll
-        for (int u = 0; u < kU; u++) {
-            const int idx = base + u * blockDim.x + threadIdx.x;
-            const int q = idx / Hb;
-            const int k = idx - q * Hb;
-            const int r = q / D;
-            const int c = q - r * D;
-            const long long row = row0 + r;
-            v[u] = {T(0), T(0)};
-            if (q < nreal && row < a.g.rows) v[u] = a.in[c * a.g.s1 + row * Hb + k];
-        }
+                for (int u = 0; u < kQ; u++) {
+                    const int q = q0 + u * qstep;
+                    const int r = q / D;
+                    const int c = q - r * D;
+                    const bool ok = q < qend;
+                    const unsigned off = ok ? (unsigned)c * s1 + (unsigned)(r * Hb) : 0u;
+                    v[u] = inb[off];
+                    if (!ok) v[u] = {T(0), T(0)};
+                }
 #pragma unroll
-        for (int u = 0; u < kU; u++) {
-            const int idx = base + u * blockDim.x + threadIdx.x;
-            if (idx < 2 * npairs * Hb) Sx[idx] = v[u];
-        }
+                for (int u = 0; u < kQ; u++) {
+                    const int q = q0 + u * qstep;
+                    if (q < 2 * npairs) Sx[q * Hb + k] = v[u];
+                }
+            }
     }
     __syncthreads();
     for (int job = threadIdx.x; job < npairs * L2; job += blockDim.x) {
@@ -780,9 +811,12 @@ __global__ __launch_bounds__(kThreads) void k2_last(LastArgs<T> a)
     {
         const int total = a.rpb * L;
         const long long pt0 = row0 * L;
-        const long long ptend = a.g.rows * (long long)L;
-        for (int base = 0; base < total; base += kU * blockDim.x)
-            acc += last_epilogue_chunk<T, D, L, epi>(a, tab, base, total, pt0, ptend, Zr);
+        const long long left = a.g.rows * (long long)L - pt0;
+        const int lim = left < total ? (int)left : total;
+        // the CG and Eyre-Milton epilogues hold three more vectors per point: smaller chunks
+        constexpr int KU = (epi == EPI_CG || epi == EPI_EM) && ku_for(L) > kU ? kU : ku_for(L);
+        for (int base = 0; base < total; base += KU * blockDim.x)
+            acc += last_epilogue_chunk<T, D, L, epi, KU>(a, tab, base, total, lim, pt0, Zr);
     }
     const double tot = block_sum(acc, red);
     if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
