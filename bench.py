@@ -240,7 +240,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=135)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--cpu-iters", type=int, default=16)
     ap.add_argument("--no-c4", action="store_true", help="skip the 243^3 FP32-refinement section")
     ap.add_argument("--no-served", action="store_true", help="skip the served-stream section")
     ap.add_argument("--served-n", type=int, default=64)
