@@ -148,49 +148,66 @@ def served_section(fgh, inputs, np, n_req, max_active=4, pool_gb=24):
     s_mean = float(service.mean())
     log(f"[bench] served: sequential FP64 baseline {n_req} requests, mean service {s_mean * 1e3:.1f} ms")
     rng = np.random.default_rng(np.random.SeedSequence(inputs.ROOT_SEED + 5))
-    arrivals = np.cumsum(rng.exponential(s_mean, size=n_req))
-    arrivals -= arrivals[0]
-    # the baseline's latencies under the same arrivals (single FIFO server, measured service times)
-    t_free = 0.0
-    lat64 = []
-    for a, sv in zip(arrivals, service):
-        start = max(a, t_free)
-        t_free = start + sv
-        lat64.append(t_free - a)
-    lat64 = np.array(lat64)
-    # served
-    srv = fgh.Server(int(pool_gb * (1 << 30)), max_active=max_active)
-    t0 = time.perf_counter()
-    ids = []
-    for a, q in zip(arrivals, reqs):
-        dt = t0 + a - time.perf_counter()
-        if dt > 0:
-            time.sleep(dt)
-        ids.append(submit(srv, q, fgh.FGH_FP32_REFINED))
-    res = [srv.wait(i) for i in ids]
-    st = srv.stats()
-    srv.close()
+    gaps = rng.exponential(1.0, size=n_req)  # unit-mean gaps, scaled per load below
+
+    def fifo_latencies(arrivals):
+        # the baseline under the same arrivals: one FIFO server with the measured service times
+        t_free, out = 0.0, []
+        for a, sv in zip(arrivals, service):
+            start = max(a, t_free)
+            t_free = start + sv
+            out.append(t_free - a)
+        return np.array(out)
+
+    def replay(arrivals):
+        srv = fgh.Server(int(pool_gb * (1 << 30)), max_active=max_active)
+        t0 = time.perf_counter()
+        ids = []
+        for a, q in zip(arrivals, reqs):
+            dt = t0 + a - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            ids.append(submit(srv, q, fgh.FGH_FP32_REFINED))
+        res = [srv.wait(i) for i in ids]
+        st = srv.stats()
+        srv.close()
+        lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+        span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+        return res, st, {"throughput_solves_per_s": round(n_req / span, 3),
+                         "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+                         "p99_latency_s": round(float(np.percentile(lat, 99)), 4)}
+
+    served, seq = {}, {}
+    res = st = None
+    for load in (1.0, 0.5):
+        arrivals = np.cumsum(gaps * (s_mean / load))
+        arrivals -= arrivals[0]
+        r_, st_, rec = replay(arrivals)
+        if load == 1.0:
+            res, st = r_, st_
+        served[f"at_load_{load:g}"] = rec
+        lat64 = fifo_latencies(arrivals)
+        seq[f"at_load_{load:g}"] = {"p50_latency_s": round(float(np.percentile(lat64, 50)), 4),
+                                    "p99_latency_s": round(float(np.percentile(lat64, 99)), 4)}
+        log(f"[bench] served at load {load:g}: {rec}")
     # capacity: the whole stream submitted at once
     srv = fgh.Server(int(pool_gb * (1 << 30)), max_active=max_active)
-    tc = time.perf_counter()
     cids = [submit(srv, q, fgh.FGH_FP32_REFINED) for q in reqs]
     cres = [srv.wait(i) for i in cids]
     cap_span = max(r["t_done"] for r in cres) - min(r["t_submit"] for r in cres)
     srv.close()
-    del tc
-    lat = np.array([r["t_done"] - r["t_submit"] for r in res])
-    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+    cap = n_req / cap_span
     rel = np.array([abs(r["energy"] - b["energy"]) / abs(b["energy"]) for r, b in zip(res, res64)])
     ok = sum(1 for r in res if r["status"] == 0)
     ok64 = sum(1 for r in res64 if r["status"] == 0)
     return {"requests": n_req, "max_active": max_active, "pool_GB": pool_gb,
-            "arrival_rate_per_s": round(1.0 / s_mean, 3),
-            "served_fp32_refined": {"solves_per_s": round(n_req / span, 3),
-                                    "capacity_solves_per_s_all_submitted_at_once": round(n_req / cap_span, 3), "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
-                                    "p99_latency_s": round(float(np.percentile(lat, 99)), 4), "status_ok": ok,
-                                    "peak_active": st["peak_active"], "peak_pool_GB": round(st["peak_pool_bytes"] / 2 ** 30, 2)},
-            "sequential_fp64": {"solves_per_s": round(1.0 / s_mean, 3), "p50_latency_s": round(float(np.percentile(lat64, 50)), 4),
-                                "p99_latency_s": round(float(np.percentile(lat64, 99)), 4), "status_ok": ok64},
+            "arrival_rate_at_load_1_per_s": round(1.0 / s_mean, 3),
+            "served_fp32_refined": {"capacity_solves_per_s": round(cap, 3), **served, "status_ok": ok,
+                                    "peak_active": st["peak_active"],
+                                    "peak_pool_GB": round(st["peak_pool_bytes"] / 2 ** 30, 2)},
+            "sequential_fp64": {"capacity_solves_per_s": round(1.0 / s_mean, 3), **seq, "status_ok": ok64,
+                                "latency_model": "single FIFO server, measured service times"},
+            "capacity_ratio_served_vs_sequential": round(cap * s_mean, 3),
             "energy_rel_diff_served_vs_fp64": {"max": float(rel.max()), "median": float(np.median(rel))},
             "mix": {"d3": sum(q["d"] == 3 for q in reqs), "ga": sum(q["rule"] == 1 for q in reqs),
                     "eyre_milton": sum(q["solver"] == "eyre_milton" for q in reqs)}}

@@ -208,7 +208,10 @@ fgh_status fgh_gani_bound(fgh_plan gani, fgh_plan ga, const double* E, const dou
  * accumulated; solver loops then run without graph replay.  Enabling resets the counters. */
 fgh_status fgh_plan_set_profiling(fgh_plan plan, int enable);
 
-/* Accumulated milliseconds and launch counts per pass kind (arrays of 5).  Synchronises. */
+/* Accumulated milliseconds and launch counts per pass kind (arrays of 5) over the launches that
+ * did work: solver-loop launches issued after the device-side stopping test has fired return at
+ * once, and launches shorter than 30 % of their kind's median are left out.  Times are those of
+ * the dispatches themselves (start and stop events attached to the launch).  Synchronises. */
 fgh_status fgh_plan_read_profile(fgh_plan plan, double* ms, int64_t* launches);
 
 /* ------------------------------------------------------------------------------------------

@@ -94,7 +94,8 @@ Config choose_config(const Geo& g, size_t cs /* bytes per complex */, size_t rs 
     c.v2_axis = small && d == 3 && v2_supported(g.L[1]);
     c.v2_mid = small && v2_supported(g.L[0]);
     c.rpb = 1;
-    const int rpb_cap = env_int("FGH_RPB", c.v2_row ? 8 : 32);
+    int rpb_cap = env_int("FGH_RPB", c.v2_row ? 8 : 32);
+    if (c.v2_row && rpb_cap > 8) rpb_cap = 8;  // the specialised row kernels take tiles of at most 8 rows
     for (int rpb = rpb_cap; rpb >= 1; rpb--) {
         const int npen = (rpb * d + 1) / 2;
         // specialised: twiddles + two complex row buffers of npen rows (+1 element each) + table
@@ -111,8 +112,11 @@ Config choose_config(const Geo& g, size_t cs /* bytes per complex */, size_t rs 
     c.P_axis = 1;
     c.lds_axis = 0;
     const int pax_cap = env_int("FGH_P_AXIS", 16), pmid_cap = env_int("FGH_P_MID", 16);
+    // exact tile widths (tuning): FGH_P_EXACT=1 takes FGH_P_AXIS / FGH_P_MID as given
+    const bool exact = env_int("FGH_P_EXACT", 0) != 0;
     if (d == 3)
         for (int P : Ps) {
+            if (exact) P = pax_cap;
             if (P > pax_cap) continue;
             const size_t lds = c.v2_axis ? (size_t)(g.L[1] + P * g.L[1]) * cs : (size_t)(g.L[1] + 2 * P * g.L[1]) * cs;
             if (lds <= kLdsBudget || P == 1) {
@@ -123,6 +127,7 @@ Config choose_config(const Geo& g, size_t cs /* bytes per complex */, size_t rs 
         }
     c.P_mid = 1;
     for (int P : Ps) {
+        if (exact) P = pmid_cap;
         if (P > pmid_cap) continue;
         const size_t lds = c.v2_mid ? (size_t)(g.L[0] + d * P * g.L[0]) * cs : (size_t)(g.L[0] + (d + 1) * P * g.L[0]) * cs;
         if (lds <= kLdsBudget || P == 1) {
@@ -1208,8 +1213,9 @@ fgh_status fgh_plan_read_profile(fgh_plan p, double* ms, int64_t* launches)
     if (!p->prof) return FGH_OK;
     HIPOK(p->prof->drain());
     for (int k = 0; k < PK_KINDS; k++) {
-        ms[k] = p->prof->ms[k];
-        launches[k] = p->prof->n[k];
+        long long n = 0;
+        p->prof->working(k, &ms[k], &n);
+        launches[k] = n;
     }
     return FGH_OK;
 }

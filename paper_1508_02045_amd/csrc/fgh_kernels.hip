@@ -1,9 +1,12 @@
 // fgh_kernels.hip -- gfx950 kernels of libfgh: the passes of y = G A x (eq:linsys) with the
 // solver epilogues of Algorithms 1-4 fused into the last pass, deterministic FP64 reductions,
 // and the set-up kernels (double-grid coefficients, spectral bounds).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
+#include <cstdlib>
 
 #include "fgh_args.hpp"
 #include "fgh_launch.hpp"
@@ -845,7 +848,14 @@ static hipError_t allow_lds(const void* fn, size_t bytes)
             if (e_ != hipSuccess) return e_;                                                    \
             lds_set_.store((LDS), std::memory_order_relaxed);                                   \
         }                                                                                       \
-        hipLaunchKernelGGL(KERNEL, GRID, dim3(kThreads), (LDS), (STREAM), __VA_ARGS__);          \
+        if (g_pass_events.start) {                                                              \
+            const PassEvents pe_ = g_pass_events;                                               \
+            g_pass_events = PassEvents{};                                                       \
+            hipExtLaunchKernelGGL(KERNEL, GRID, dim3(kThreads), (LDS), (STREAM), pe_.start, pe_.stop, 0, \
+                                  __VA_ARGS__);                                                 \
+        } else {                                                                                \
+            hipLaunchKernelGGL(KERNEL, GRID, dim3(kThreads), (LDS), (STREAM), __VA_ARGS__);      \
+        }                                                                                       \
     } while (0)
 static inline unsigned grid_for(long long n, int per = kThreads, int cap = 4096)
 {
@@ -871,6 +881,7 @@ hipError_t Profiler::init(hipStream_t s)
     for (int k = 0; k < PK_KINDS; k++) {
         ms[k] = 0.0;
         n[k] = 0;
+        dur[k].clear();
     }
     return hipSuccess;
 }
@@ -882,6 +893,8 @@ void Profiler::destroy()
     ready = false;
 }
 
+thread_local PassEvents g_pass_events;
+
 hipError_t Profiler::begin(int k)
 {
     if (used == kPool) {
@@ -889,12 +902,18 @@ hipError_t Profiler::begin(int k)
         if (e != hipSuccess) return e;
     }
     kind[used] = k;
-    return hipEventRecord(ev[2 * used], stream);
+    g_pass_events = PassEvents{ev[2 * used], ev[2 * used + 1]};
+    return hipSuccess;
 }
 
 hipError_t Profiler::end()
 {
-    hipError_t e = hipEventRecord(ev[2 * used + 1], stream);
+    hipError_t e = hipSuccess;
+    if (g_pass_events.start) {  // no launch took the events: record an empty interval
+        g_pass_events = PassEvents{};
+        if ((e = hipEventRecord(ev[2 * used], stream)) != hipSuccess) return e;
+        e = hipEventRecord(ev[2 * used + 1], stream);
+    }
     used++;
     return e;
 }
@@ -910,9 +929,25 @@ hipError_t Profiler::drain()
         if (e != hipSuccess) return e;
         ms[kind[i]] += t;
         n[kind[i]]++;
+        dur[kind[i]].push_back(t);
     }
     used = 0;
     return hipSuccess;
+}
+
+void Profiler::working(int k, double* ms_out, long long* n_out) const
+{
+    std::vector<float> v = dur[k];
+    *ms_out = 0.0;
+    *n_out = 0;
+    if (v.empty()) return;
+    std::nth_element(v.begin(), v.begin() + v.size() / 2, v.end());
+    const float cut = 0.3f * v[v.size() / 2];
+    for (float t : dur[k])
+        if (t >= cut) {
+            *ms_out += t;
+            (*n_out)++;
+        }
 }
 
 template <typename T, int D, int AK>
@@ -993,6 +1028,51 @@ static hipError_t launch_axis(const OpPlan& op, const AxisArgs<T>& xa, bool inv,
 #define V2_ROW_CASES(X) X(45, 5, 9) X(63, 7, 9) X(81, 9, 9) X(125, 5, 25) X(135, 9, 15) X(243, 9, 27)
 #define V2_COL_CASES(X) X(45, 5, 9) X(63, 7, 9) X(81, 9, 9) X(125, 5, 25) X(135, 9, 15) X(243, 9, 27)
 
+// Persistent launches of the last pass: one workgroup per resident slot (occupancy at this LDS
+// size times the CU count), each walking a contiguous range of tiles.  FGH_PERSIST=0 launches
+// one workgroup per tile instead (tuning).
+static bool persist_enabled()
+{
+    static const int v = [] {
+        const char* e = std::getenv("FGH_PERSIST");
+        return e && e[0] == '0' ? 0 : 1;
+    }();
+    return v != 0;
+}
+
+static int cu_count()
+{
+    static std::atomic<int> n{0};
+    int v = n.load(std::memory_order_relaxed);
+    if (v == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1)
+            v = 1;
+        n.store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
+// Resident workgroups of `kernel` per CU at `lds` bytes, cached per call site and LDS size.
+#define PERSIST_GRID(KERNEL, LDS, NTILES, OUT)                                                     \
+    do {                                                                                        \
+        static std::atomic<long long> key_{-1};                                                \
+        static std::atomic<int> per_{1};                                                       \
+        int per = per_.load(std::memory_order_relaxed);                                        \
+        if (key_.load(std::memory_order_relaxed) != (long long)(LDS)) {                         \
+            per = 0;                                                                            \
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (KERNEL), kThreads, (LDS)) != \
+                    hipSuccess ||                                                               \
+                per < 1)                                                                        \
+                per = 1;                                                                        \
+            per_.store(per, std::memory_order_relaxed);                                        \
+            key_.store((long long)(LDS), std::memory_order_relaxed);                            \
+        }                                                                                       \
+        const long long g_ = (long long)per * cu_count();                                      \
+        (OUT) = (unsigned)((NTILES) < g_ ? (NTILES) : g_);                                      \
+    } while (0)
+
 template <typename T, int D>
 static hipError_t v2_first(const OpPlan& op, const FirstArgs<T>& fa, int opc, unsigned nblk)
 {
@@ -1007,13 +1087,25 @@ static hipError_t v2_first(const OpPlan& op, const FirstArgs<T>& fa, int opc, un
     return hipGetLastError();
 }
 
+// nblk: in, the tile count; out, the workgroups launched (one partial sum each).
 template <typename T, int D, int EPI>
-static hipError_t v2_last_epi(const OpPlan& op, const LastArgs<T>& la, unsigned nblk)
+static hipError_t v2_last_epi(const OpPlan& op, const LastArgs<T>& la, unsigned* nblk)
 {
     const size_t lds = op.lds_first;
+    // the Chebyshev epilogue holds three vectors per point next to the prefetched spectra: the
+    // persistent form would run at one wave per SIMD
+    const bool pf = persist_enabled() && EPI != EPI_CHEB;
     switch (la.ax.L) {
-#define C(LL, A1, A2) \
-    case LL: LAUNCH_LDS((k2_last<T, D, A1, A2, EPI>), dim3(nblk), lds, op.stream, la); break;
+#define C(LL, A1, A2)                                                                          \
+    case LL:                                                                                   \
+        if (pf) {                                                                              \
+            const long long nt = *nblk;                                                        \
+            PERSIST_GRID((k2_last_pf<T, D, A1, A2, EPI>), lds, nt, *nblk);                     \
+            LAUNCH_LDS((k2_last_pf<T, D, A1, A2, EPI>), dim3(*nblk), lds, op.stream, la, nt);  \
+        } else {                                                                               \
+            LAUNCH_LDS((k2_last<T, D, A1, A2, EPI>), dim3(*nblk), lds, op.stream, la);         \
+        }                                                                                      \
+        break;
         V2_ROW_CASES(C)
 #undef C
         default: return hipErrorInvalidValue;
@@ -1022,7 +1114,7 @@ static hipError_t v2_last_epi(const OpPlan& op, const LastArgs<T>& la, unsigned 
 }
 
 template <typename T, int D>
-static hipError_t v2_last(const OpPlan& op, const LastArgs<T>& la, int epi, unsigned nblk)
+static hipError_t v2_last(const OpPlan& op, const LastArgs<T>& la, int epi, unsigned* nblk)
 {
     switch (epi) {
         case EPI_STORE: return v2_last_epi<T, D, EPI_STORE>(op, la, nblk);
@@ -1076,7 +1168,7 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     const Geo& g = op.g;
     const int last = D - 1;
     hipError_t e;
-    const unsigned nblk = (unsigned)((g.rows + op.rpb - 1) / op.rpb);
+    unsigned nblk = (unsigned)((g.rows + op.rpb - 1) / op.rpb);
     cpx<T>* SA = static_cast<cpx<T>*>(op.SA);
     cpx<T>* SB = static_cast<cpx<T>*>(op.SB);
 
@@ -1196,7 +1288,7 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     la.sc = a.cheb_dev ? op.sc : nullptr;
     const bool prof_PK_LAST = op.prof && op.prof->wants(PK_LAST);
     if (prof_PK_LAST && (e = op.prof->begin(PK_LAST)) != hipSuccess) return e;
-    if ((e = op.v2_row ? v2_last<T, D>(op, la, a.epi, nblk) : launch_last<T, D>(op, la, a.epi, nblk)) != hipSuccess)
+    if ((e = op.v2_row ? v2_last<T, D>(op, la, a.epi, &nblk) : launch_last<T, D>(op, la, a.epi, nblk)) != hipSuccess)
         return e;
     if (prof_PK_LAST && (e = op.prof->end()) != hipSuccess) return e;
     if (nblocks_last) *nblocks_last = (int)nblk;
@@ -1305,10 +1397,10 @@ hipError_t run_prolong(const OpPlan& opn, const OpPlan& opm, const double* xn, d
     la.A = opm.A;
     la.partials = opm.partials;
     la.twg = static_cast<const cpx<double>*>(opm.tw[d - 1]);
-    const unsigned nblk = (unsigned)((gm.rows + opm.rpb - 1) / opm.rpb);
+    unsigned nblk = (unsigned)((gm.rows + opm.rpb - 1) / opm.rpb);
     if (d == 2)
-        return opm.v2_row ? v2_last<double, 2>(opm, la, EPI_STORE, nblk) : launch_last<double, 2>(opm, la, EPI_STORE, nblk);
-    return opm.v2_row ? v2_last<double, 3>(opm, la, EPI_STORE, nblk) : launch_last<double, 3>(opm, la, EPI_STORE, nblk);
+        return opm.v2_row ? v2_last<double, 2>(opm, la, EPI_STORE, &nblk) : launch_last<double, 2>(opm, la, EPI_STORE, nblk);
+    return opm.v2_row ? v2_last<double, 3>(opm, la, EPI_STORE, &nblk) : launch_last<double, 3>(opm, la, EPI_STORE, nblk);
 }
 
 template <typename T>

@@ -2,12 +2,22 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "fgh_internal.hpp"
 
 namespace fgh {
 
 // Per-pass device timing: launches bracketed by HIP events on the plan's stream.
 enum PassKind : int { PK_FIRST = 0, PK_AXIS_FWD = 1, PK_MIDDLE = 2, PK_AXIS_INV = 3, PK_LAST = 4, PK_KINDS = 5 };
+// Events for the next pass launch while a pass is being timed: the launch takes them as the
+// start and stop events of the dispatch itself (hipExtLaunchKernelGGL), so the measured time is
+// the kernel's own execution time.
+struct PassEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local PassEvents g_pass_events;
+
 struct Profiler {
     static constexpr int kPool = 256;
     hipEvent_t ev[2 * kPool];
@@ -16,6 +26,7 @@ struct Profiler {
     bool ready = false;
     double ms[PK_KINDS] = {0, 0, 0, 0, 0};
     long long n[PK_KINDS] = {0, 0, 0, 0, 0};
+    std::vector<float> dur[PK_KINDS];  // every timed launch (ms), for the working-launch totals
     hipStream_t stream = nullptr;
     unsigned mask = 0u;  // pass kinds timed (bit k: PassKind k)
     bool wants(int k) const { return (mask >> k) & 1u; }
@@ -24,6 +35,9 @@ struct Profiler {
     hipError_t begin(int k);
     hipError_t end();
     hipError_t drain();
+    // Totals over the launches that did work: a launch of a solver body after the loop has
+    // stopped returns at once; launches shorter than 30 % of the kind's median are left out.
+    void working(int k, double* ms_out, long long* n_out) const;
 };
 
 // Everything one operator application needs (one precision).

@@ -14,6 +14,16 @@
 
 namespace fgh {
 
+// Workgroup barrier that orders LDS accesses only.  Threads of one launch exchange data through
+// LDS alone, so global loads issued before the barrier (prefetches of the next tile) stay in
+// flight across it, and global stores are not waited for.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 constexpr int smallest_factor(int n)
 {
     for (int p = 2; p * p <= n; p++)
@@ -419,36 +429,14 @@ __device__ __forceinline__ long long xcd_tile(long long b, long long nb)
 //            B(k) = (X(k) - conj X(L-k)) / 2i, and store k < Hb row by row.
 // LDS: twiddles | Y (npairs rows) | Zr reals (2 npairs rows), reused as X (npairs rows).
 // ------------------------------------------------------------------------------------------
+// Stages A, B and S of the first pass for the tile of rows starting at row0 (the real rows are
+// in Zr; the caller has synchronised after writing them).
 template <typename T, int D, int L1, int L2>
-__global__ __launch_bounds__(kThreads) void k2_first(FirstArgs<T> a, int op)
+__device__ __forceinline__ void first_transform_store(const FirstArgs<T>& a, long long row0, const cpx<T>* tw,
+                                                      cpx<T>* Y, cpx<T>* X, const T* Zr)
 {
-    if (a.done && *a.done) return;
     constexpr int L = L1 * L2;
-    extern __shared__ __align__(16) unsigned char smem[];
     const int npairs = (a.rpb * D + 1) / 2;
-    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
-    cpx<T>* Y = tw + L;
-    cpx<T>* X = Y + npairs * L;
-    T* Zr = reinterpret_cast<T*>(X);
-    T* tab = reinterpret_cast<T*>(X + npairs * L);
-    for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
-    if (a.A.kind == AK_PHASE)
-        for (int m = threadIdx.x; m < kMaxPhases * 6; m += blockDim.x) tab[m] = T(a.A.tab[m / 6][m % 6]);
-    if ((a.rpb * D) & 1)
-        for (int i = threadIdx.x; i < L; i += blockDim.x) Zr[(2 * npairs - 1) * L + i] = T(0);
-    __syncthreads();
-    const long long row0 = xcd_tile(blockIdx.x, gridDim.x) * a.rpb;
-    const T beta = (op == OP_AP_CG) ? T(a.sc->beta) : T(0);
-    {
-        const int total = a.rpb * L;
-        const long long pt0 = row0 * L;
-        const long long left = a.g.rows * (long long)L - pt0;
-        const int lim = left < total ? (int)left : total;
-        constexpr int KU = ku_for(L);
-        for (int base = 0; base < total; base += KU * blockDim.x)
-            first_stage0_chunk<T, D, L, KU>(a, op, tab, beta, base, total, lim, pt0, Zr);
-    }
-    __syncthreads();
     for (int job = threadIdx.x; job < npairs * L1; job += blockDim.x) {
         const int m = job / L1;
         const int n1 = job - m * L1;
@@ -467,7 +455,7 @@ __global__ __launch_bounds__(kThreads) void k2_first(FirstArgs<T> a, int op)
             if (w >= L) w -= L;
         }
     }
-    __syncthreads();
+    lds_barrier();
     for (int job = threadIdx.x; job < npairs * L2; job += blockDim.x) {
         const int m = job / L2;
         const int k2 = job - m * L2;
@@ -480,7 +468,7 @@ __global__ __launch_bounds__(kThreads) void k2_first(FirstArgs<T> a, int op)
 #pragma unroll
         for (int k1 = 0; k1 < L1; k1++) x[L2 * k1] = sv[k1];
     }
-    __syncthreads();
+    lds_barrier();
     // stage S: thread (tq, k) stores frequency k of the real rows q = tq, tq + qstep, ...
     // (32-bit element offsets: the plan keeps d |spectrum| below 2^31 for these kernels)
     const int Hb = a.g.Hb;
@@ -504,6 +492,39 @@ __global__ __launch_bounds__(kThreads) void k2_first(FirstArgs<T> a, int op)
         }
 }
 
+template <typename T, int D, int L1, int L2>
+__global__ __launch_bounds__(kThreads) void k2_first(FirstArgs<T> a, int op)
+{
+    if (a.done && *a.done) return;
+    constexpr int L = L1 * L2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int npairs = (a.rpb * D + 1) / 2;
+    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
+    cpx<T>* Y = tw + L;
+    cpx<T>* X = Y + npairs * L;
+    T* Zr = reinterpret_cast<T*>(X);
+    T* tab = reinterpret_cast<T*>(X + npairs * L);
+    for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
+    if (a.A.kind == AK_PHASE)
+        for (int m = threadIdx.x; m < kMaxPhases * 6; m += blockDim.x) tab[m] = T(a.A.tab[m / 6][m % 6]);
+    if ((a.rpb * D) & 1)
+        for (int i = threadIdx.x; i < L; i += blockDim.x) Zr[(2 * npairs - 1) * L + i] = T(0);
+    lds_barrier();
+    const long long row0 = xcd_tile(blockIdx.x, gridDim.x) * a.rpb;
+    const T beta = (op == OP_AP_CG) ? T(a.sc->beta) : T(0);
+    {
+        const int total = a.rpb * L;
+        const long long pt0 = row0 * L;
+        const long long left = a.g.rows * (long long)L - pt0;
+        const int lim = left < total ? (int)left : total;
+        constexpr int KU = ku_for(L);
+        for (int base = 0; base < total; base += KU * blockDim.x)
+            first_stage0_chunk<T, D, L, KU>(a, op, tab, beta, base, total, lim, pt0, Zr);
+    }
+    lds_barrier();
+    first_transform_store<T, D, L1, L2>(a, row0, tw, Y, X, Zr);
+}
+
 // ------------------------------------------------------------------------------------------
 // Strided axis pass (3D axis 1), one component per workgroup, tile of P columns.
 // ------------------------------------------------------------------------------------------
@@ -522,7 +543,7 @@ __global__ __launch_bounds__(kThreads) void k2_axis(AxisArgs<T> a, int B)
     const int o = (int)((lin / gridDim.x) % gridDim.y);
     const int c = (int)(lin / ((long long)gridDim.x * gridDim.y));
     for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
-    __syncthreads();
+    lds_barrier();
     const cpx<T>* in = a.in + c * a.in_cs + o * a.in_os;
     cpx<T>* out = a.out + c * a.out_cs + o * a.out_os;
     for (int job = threadIdx.x; job < P * L1; job += blockDim.x) {
@@ -548,7 +569,7 @@ __global__ __launch_bounds__(kThreads) void k2_axis(AxisArgs<T> a, int B)
             if (m >= L) m -= L;
         }
     }
-    __syncthreads();
+    lds_barrier();
     for (int job = threadIdx.x; job < P * L2; job += blockDim.x) {
         const int k2 = job / P;
         const int p = job - k2 * P;
@@ -586,7 +607,7 @@ __device__ __forceinline__ void middle_body(const MidArgs<T>& a, int mult)
     const int PL = P * L;
     const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);
     for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
-    __syncthreads();
+    lds_barrier();
     // forward step A: jobs (c, n1, p), p fastest
     for (int job = threadIdx.x; job < D * P * L1; job += blockDim.x) {
         const int cn = job / P;
@@ -609,7 +630,7 @@ __device__ __forceinline__ void middle_body(const MidArgs<T>& a, int mult)
             if (m >= L) m -= L;
         }
     }
-    __syncthreads();
+    lds_barrier();
     // forward step B, multiplier, inverse step B: jobs (k2, p)
     const T scale = T(a.scale);
     for (int job = threadIdx.x; job < P * L2; job += blockDim.x) {
@@ -674,7 +695,7 @@ __device__ __forceinline__ void middle_body(const MidArgs<T>& a, int mult)
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
     // inverse step A: jobs (c, n1, p)
     for (int job = threadIdx.x; job < D * P * L1; job += blockDim.x) {
         const int cn = job / P;
@@ -710,6 +731,80 @@ __global__ __launch_bounds__(kThreads) void k2_middle(MidArgs<T> a, int mult)
 //   stage E   solver epilogue per point, the d components together.
 // LDS: twiddles | Y (npairs rows) | Sx (nreal half rows) sharing space with Zr (2 npairs rows).
 // ------------------------------------------------------------------------------------------
+// Stages B' and A' of the last pass: the half spectra of the tile's rows (Sx) -> real rows Zr
+// (Zr aliases Sx).  The caller has synchronised after filling Sx; returns synchronised.
+template <typename T, int D, int L1, int L2>
+__device__ __forceinline__ void last_transform(const LastArgs<T>& a, const cpx<T>* tw, cpx<T>* Y, const cpx<T>* Sx,
+                                               T* Zr)
+{
+    constexpr int L = L1 * L2;
+    const int npairs = (a.rpb * D + 1) / 2;
+    const int Hb = a.g.Hb;
+    for (int job = threadIdx.x; job < npairs * L2; job += blockDim.x) {
+        const int m = job / L2;
+        const int k2 = job - m * L2;
+        const cpx<T>* s0 = Sx + (2 * m) * Hb;
+        const cpx<T>* s1 = s0 + Hb;
+        cpx<T> sv[L1];
+#pragma unroll
+        for (int k1 = 0; k1 < L1; k1++) {
+            const int k = k2 + L2 * k1;
+            cpx<T> A = {T(0), T(0)}, B = {T(0), T(0)};
+            if (k < Hb) {
+                A = s0[k];
+                B = s1[k];
+            } else if (L - k < Hb) {
+                A = conj(s0[L - k]);
+                B = conj(s1[L - k]);
+            }
+            sv[k1] = {A.x - B.y, A.y + B.x};
+        }
+        reg_dft<T, L1, true>(sv);
+        cpx<T>* y = Y + m * L + k2;
+        int w = 0;
+#pragma unroll
+        for (int n1 = 0; n1 < L1; n1++) {
+            y[n1 * L2] = n1 ? cmul(sv[n1], conj(tw[w])) : sv[n1];
+            w += k2;
+            if (w >= L) w -= L;
+        }
+    }
+    lds_barrier();
+    for (int job = threadIdx.x; job < npairs * L1; job += blockDim.x) {
+        const int m = job / L1;
+        const int n1 = job - m * L1;
+        cpx<T> sv[L2];
+        const cpx<T>* y = Y + m * L + n1 * L2;
+#pragma unroll
+        for (int k2 = 0; k2 < L2; k2++) sv[k2] = y[k2];
+        reg_dft<T, L2, true>(sv);
+        T* z0 = Zr + (2 * m) * L + n1;
+        T* z1 = z0 + L;
+#pragma unroll
+        for (int n2 = 0; n2 < L2; n2++) {
+            z0[L1 * n2] = sv[n2].x;
+            z1[L1 * n2] = sv[n2].y;
+        }
+    }
+    lds_barrier();
+}
+
+// Epilogue of the last pass over the tile of rows starting at row0; returns this thread's sum.
+template <typename T, int D, int L, int epi, int KUH = kU>
+__device__ __forceinline__ double last_epilogue_tile(const LastArgs<T>& a, const T* tab, long long row0, const T* Zr)
+{
+    double acc = 0.0;
+    const int total = a.rpb * L;
+    const long long pt0 = row0 * L;
+    const long long left = a.g.rows * (long long)L - pt0;
+    const int lim = left < total ? (int)left : total;
+    // the CG and Eyre-Milton epilogues hold three more vectors per point: smaller chunks
+    constexpr int KU = (epi == EPI_CG || epi == EPI_EM) && ku_for(L) > KUH ? KUH : ku_for(L);
+    for (int base = 0; base < total; base += KU * blockDim.x)
+        acc += last_epilogue_chunk<T, D, L, epi, KU>(a, tab, base, total, lim, pt0, Zr);
+    return acc;
+}
+
 template <typename T, int D, int L1, int L2, int epi>
 __global__ __launch_bounds__(kThreads) void k2_last(LastArgs<T> a)
 {
@@ -759,64 +854,83 @@ __global__ __launch_bounds__(kThreads) void k2_last(LastArgs<T> a)
                 }
             }
     }
-    __syncthreads();
-    for (int job = threadIdx.x; job < npairs * L2; job += blockDim.x) {
-        const int m = job / L2;
-        const int k2 = job - m * L2;
-        const cpx<T>* s0 = Sx + (2 * m) * Hb;
-        const cpx<T>* s1 = s0 + Hb;
-        cpx<T> sv[L1];
-#pragma unroll
-        for (int k1 = 0; k1 < L1; k1++) {
-            const int k = k2 + L2 * k1;
-            cpx<T> A = {T(0), T(0)}, B = {T(0), T(0)};
-            if (k < Hb) {
-                A = s0[k];
-                B = s1[k];
-            } else if (L - k < Hb) {
-                A = conj(s0[L - k]);
-                B = conj(s1[L - k]);
-            }
-            sv[k1] = {A.x - B.y, A.y + B.x};
-        }
-        reg_dft<T, L1, true>(sv);
-        cpx<T>* y = Y + m * L + k2;
-        int w = 0;
-#pragma unroll
-        for (int n1 = 0; n1 < L1; n1++) {
-            y[n1 * L2] = n1 ? cmul(sv[n1], conj(tw[w])) : sv[n1];
-            w += k2;
-            if (w >= L) w -= L;
-        }
-    }
-    __syncthreads();
-    for (int job = threadIdx.x; job < npairs * L1; job += blockDim.x) {
-        const int m = job / L1;
-        const int n1 = job - m * L1;
-        cpx<T> sv[L2];
-        const cpx<T>* y = Y + m * L + n1 * L2;
-#pragma unroll
-        for (int k2 = 0; k2 < L2; k2++) sv[k2] = y[k2];
-        reg_dft<T, L2, true>(sv);
-        T* z0 = Zr + (2 * m) * L + n1;
-        T* z1 = z0 + L;
-#pragma unroll
-        for (int n2 = 0; n2 < L2; n2++) {
-            z0[L1 * n2] = sv[n2].x;
-            z1[L1 * n2] = sv[n2].y;
-        }
-    }
-    __syncthreads();
+    lds_barrier();
+    last_transform<T, D, L1, L2>(a, tw, Y, Sx, Zr);
+    const double acc = last_epilogue_tile<T, D, L, epi>(a, tab, row0, Zr);
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
+}
+
+// Persistent last pass: each workgroup walks a contiguous range of row tiles; the half spectra
+// of the next tile are loaded into registers before the transforms and the epilogue of the
+// current one.  Thread (tq, k) holds frequency k of the rows q = tq, tq + qstep, ... (at most
+// kQmax of them: qstep >= kThreads / ((L + 1) / 2)).
+template <int L>
+constexpr int last_qmax()
+{
+    return (2 * ((8 * 3 + 1) / 2) + (kThreads / ((L + 1) / 2)) - 1) / (kThreads / ((L + 1) / 2));
+}
+
+template <typename T, int D, int L1, int L2, int epi>
+__global__ __launch_bounds__(kThreads) void k2_last_pf(LastArgs<T> a, long long ntiles)
+{
+    if (a.done && *a.done) return;
+    constexpr int L = L1 * L2;
+    constexpr int QM = last_qmax<L>();
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int npairs = (a.rpb * D + 1) / 2;
+    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
+    cpx<T>* Y = tw + L;
+    cpx<T>* Sx = Y + npairs * L;
+    T* Zr = reinterpret_cast<T*>(Sx);
+    T* tab = reinterpret_cast<T*>(Sx + npairs * (L + 1));
+    __shared__ double red[kThreads / 64];
+    const long long G = gridDim.x;
+    const long long t0 = ntiles * (long long)blockIdx.x / G;
+    const long long t1 = ntiles * ((long long)blockIdx.x + 1) / G;
     double acc = 0.0;
-    {
-        const int total = a.rpb * L;
-        const long long pt0 = row0 * L;
-        const long long left = a.g.rows * (long long)L - pt0;
-        const int lim = left < total ? (int)left : total;
-        // the CG and Eyre-Milton epilogues hold three more vectors per point: smaller chunks
-        constexpr int KU = (epi == EPI_CG || epi == EPI_EM) && ku_for(L) > kU ? kU : ku_for(L);
-        for (int base = 0; base < total; base += KU * blockDim.x)
-            acc += last_epilogue_chunk<T, D, L, epi, KU>(a, tab, base, total, lim, pt0, Zr);
+    if (t0 < t1) {
+        for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
+        if (epi == EPI_EM && a.A.kind == AK_PHASE)
+            for (int m = threadIdx.x; m < kMaxPhases * 6; m += blockDim.x) tab[m] = T(a.A.tab_inv[m / 6][m % 6]);
+        const int Hb = a.g.Hb;
+        const int qstep = (int)blockDim.x / Hb;
+        const int tq = (int)threadIdx.x / Hb;
+        const int k = (int)threadIdx.x - tq * Hb;
+        const bool active = tq < qstep;
+        const unsigned s1 = (unsigned)a.g.s1;
+        cpx<T> v[QM];
+        auto load = [&](long long t) {
+            const long long row0 = t * a.rpb;
+            const int nrows = (int)(a.g.rows - row0 < a.rpb ? a.g.rows - row0 : a.rpb);
+            const int qend = nrows * D;
+            const cpx<T>* inb = a.in + row0 * Hb + k;
+#pragma unroll
+            for (int u = 0; u < QM; u++) {
+                const int q = tq + u * qstep;
+                const int r = q / D;
+                const int c = q - r * D;
+                const bool ok = active && q < qend;
+                const unsigned off = ok ? (unsigned)c * s1 + (unsigned)(r * Hb) : 0u;
+                v[u] = inb[off];
+                if (!ok) v[u] = {T(0), T(0)};
+            }
+        };
+        load(t0);
+        for (long long t = t0; t < t1; t++) {
+            lds_barrier();  // the previous epilogue has read Zr (which aliases Sx)
+            if (active)
+#pragma unroll
+                for (int u = 0; u < QM; u++) {
+                    const int q = tq + u * qstep;
+                    if (q < 2 * npairs) Sx[q * Hb + k] = v[u];
+                }
+            lds_barrier();
+            if (t + 1 < t1) load(t + 1);
+            last_transform<T, D, L1, L2>(a, tw, Y, Sx, Zr);
+            // the prefetched spectra stay live through the epilogue: smaller heavy chunks in FP64
+            acc += last_epilogue_tile<T, D, L, epi, sizeof(T) == 8 ? 2 : kU>(a, tab, t * a.rpb, Zr);
+        }
     }
     const double tot = block_sum(acc, red);
     if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
