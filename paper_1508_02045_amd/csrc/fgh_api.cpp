@@ -9,6 +9,8 @@
 #include <cstring>
 #include <functional>
 #include <initializer_list>
+#include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -370,6 +372,66 @@ void fill_opplan(fgh_plan p, OpPlan* op, bool f32)
     op->partials = reinterpret_cast<double*>(p->ws + p->lay.partials);
     op->sc = reinterpret_cast<Scalars*>(p->ws + p->lay.scalars);
     op->stream = p->stream;
+}
+
+// Tile width of the middle pass, measured at plan creation.  The per-column arithmetic does not
+// depend on the width (results are identical for every choice); the best width depends on how
+// the tile count meets the resident workgroups of the CUs, so a few widths are timed once per
+// process and shape and the fastest is kept.  FGH_TUNE=0 keeps the static choice.
+fgh_status tune_middle(fgh_plan p, OpPlan* op, bool f32)
+{
+    if (!op->v2_mid || env_int("FGH_TUNE", 1) == 0 || env_int("FGH_P_EXACT", 0) != 0) return FGH_OK;
+    static std::mutex mu;
+    static std::map<std::vector<long long>, int> cache;
+    const Geo& g = op->g;
+    const std::vector<long long> key = {f32 ? 1 : 0, g.d, g.L[0], g.B[0], g.B[1], g.Hb, g.cols_mid};
+    const size_t cs = f32 ? 8 : 16;
+    auto lds_of = [&](int P) { return (size_t)(g.L[0] + (size_t)g.d * P * g.L[0]) * cs; };
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            op->P_mid = it->second;
+            op->lds_mid = lds_of(it->second);
+            return FGH_OK;
+        }
+    }
+    const int cand[] = {6, 7, 8, 9, 10, 12, 16};
+    hipEvent_t e0, e1;
+    HIPOK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return FGH_E_DEVICE;
+    }
+    int best = op->P_mid;
+    float best_ms = 1e30f;
+    hipError_t err = hipSuccess;
+    for (int P : cand) {
+        if (lds_of(P) > 128 * 1024 || P > g.cols_mid) continue;
+        OpPlan o = *op;
+        o.P_mid = P;
+        o.lds_mid = lds_of(P);
+        o.prof = nullptr;
+        if ((err = f32 ? run_middle_only<float>(o) : run_middle_only<double>(o)) != hipSuccess) break;
+        if ((err = hipEventRecord(e0, o.stream)) != hipSuccess) break;
+        for (int r = 0; r < 3 && err == hipSuccess; r++) err = f32 ? run_middle_only<float>(o) : run_middle_only<double>(o);
+        if (err != hipSuccess || (err = hipEventRecord(e1, o.stream)) != hipSuccess) break;
+        if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.0f;
+        if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = P;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return FGH_E_DEVICE;
+    op->P_mid = best;
+    op->lds_mid = lds_of(best);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = best;
+    return FGH_OK;
 }
 
 // Read one device double (synchronises the stream).
@@ -1035,6 +1097,8 @@ fgh_status fgh_plan_create(fgh_plan* out, int d, const int32_t* N, fgh_rule rule
     p->p32 = v32 + 2 * nv;
     p->q32 = v32 + 3 * nv;
     if ((s = upload_twiddles(p))) return fail(s);
+    if ((s = tune_middle(p, &p->op64, false))) return fail(s);
+    if (precision == FGH_FP32_REFINED && (s = tune_middle(p, &p->op32, true))) return fail(s);
 
     long long nN = 1;
     for (int a = 0; a < d; a++) nN *= N[a];

@@ -1133,7 +1133,10 @@ static hipError_t v2_middle(const OpPlan& op, const MidArgs<T>& ma, int mult)
     switch (ma.ax.L) {
 #define C(LL, A1, A2)                                                                          \
     case LL:                                                                                   \
-        LAUNCH_LDS((k2_middle<T, D, A1, A2>), dim3(ma.ntiles), lds, op.stream, ma, mult); \
+        if (mult == MULT_G)                                                                    \
+            LAUNCH_LDS((k2_middle<T, D, A1, A2, MULT_G>), dim3(ma.ntiles), lds, op.stream, ma);  \
+        else                                                                                   \
+            LAUNCH_LDS((k2_middle<T, D, A1, A2, MULT_EM>), dim3(ma.ntiles), lds, op.stream, ma); \
         break;
         V2_COL_CASES(C)
 #undef C
@@ -1160,6 +1163,26 @@ static hipError_t v2_axis(const OpPlan& op, const AxisArgs<T>& xa, bool inv, int
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename T>
+static MidArgs<T> mid_args(const OpPlan& op, cpx<T>* buf, const int* done)
+{
+    const Geo& g = op.g;
+    MidArgs<T> ma;
+    ma.ax = op.ax[0];
+    ma.B0 = g.B[0];
+    ma.cols = g.cols_mid;
+    ma.Hb = g.Hb;
+    ma.B1 = g.B[1];
+    ma.P = op.P_mid;
+    ma.ntiles = (g.cols_mid + op.P_mid - 1) / op.P_mid;
+    ma.cs = (long long)g.L[0] * g.cols_mid;
+    ma.scale = 1.0 / (double)g.npts;
+    ma.buf = buf;
+    ma.twg = static_cast<const cpx<T>*>(op.tw[0]);
+    ma.done = done;
+    return ma;
 }
 
 template <typename T, int D>
@@ -1221,19 +1244,7 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
         mid = SB;
     }
 
-    MidArgs<T> ma;
-    ma.ax = op.ax[0];
-    ma.B0 = g.B[0];
-    ma.cols = g.cols_mid;
-    ma.Hb = g.Hb;
-    ma.B1 = g.B[1];
-    ma.P = op.P_mid;
-    ma.ntiles = (g.cols_mid + op.P_mid - 1) / op.P_mid;
-    ma.cs = (long long)g.L[0] * g.cols_mid;
-    ma.scale = 1.0 / (double)g.npts;
-    ma.buf = mid;
-    ma.twg = static_cast<const cpx<T>*>(op.tw[0]);
-    ma.done = done;
+    const MidArgs<T> ma = mid_args<T>(op, mid, done);
     const bool prof_PK_MIDDLE = op.prof && op.prof->wants(PK_MIDDLE);
     if (prof_PK_MIDDLE && (e = op.prof->begin(PK_MIDDLE)) != hipSuccess) return e;
     if ((e = op.v2_mid ? v2_middle<T, D>(op, ma, a.mult) : launch_middle<T, D>(op, ma, a.mult)) != hipSuccess) return e;
@@ -1294,6 +1305,17 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     if (nblocks_last) *nblocks_last = (int)nblk;
     return hipSuccess;
 }
+
+template <typename T>
+hipError_t run_middle_only(const OpPlan& op)
+{
+    cpx<T>* buf = static_cast<cpx<T>*>(op.g.d == 3 ? op.SB : op.SA);
+    const MidArgs<T> ma = mid_args<T>(op, buf, nullptr);
+    if (op.g.d == 2) return op.v2_mid ? v2_middle<T, 2>(op, ma, MULT_G) : launch_middle<T, 2>(op, ma, MULT_G);
+    return op.v2_mid ? v2_middle<T, 3>(op, ma, MULT_G) : launch_middle<T, 3>(op, ma, MULT_G);
+}
+template hipError_t run_middle_only<double>(const OpPlan&);
+template hipError_t run_middle_only<float>(const OpPlan&);
 
 // One strided-axis launch with explicit geometry (generic kernel, any length): transform along
 // an axis of length ax.L for `outer` blocks of `inner` contiguous columns per component.

@@ -84,6 +84,11 @@ hipError_t run_apply(const OpPlan& op, const ApplyArgs& a, int* nblocks_last);
 
 hipError_t run_reduce(const OpPlan& op, int n, int redop, double* host_out);
 
+// The middle pass alone on the plan's spectrum buffer (tile-width tuning at plan creation; the
+// buffer's contents are overwritten).
+template <typename T>
+hipError_t run_middle_only(const OpPlan& op);
+
 // Trigonometric prolongation of a real vector field from the N grid of `opn` to the 2N-1 grid of
 // `opm` (both double precision; opm's spectrum buffers are used as scratch).
 hipError_t run_prolong(const OpPlan& opn, const OpPlan& opm, const double* xn, double* ym);

@@ -14,6 +14,15 @@
 
 namespace fgh {
 
+// 1 / v for an exact positive integer v: the hardware reciprocal, refined by one Newton step in
+// double precision (relative error a few units in the last place).
+__device__ __forceinline__ float recip_int(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double recip_int(double v)
+{
+    const double r = __builtin_amdgcn_rcp(v);
+    return fma(fma(-v, r, 1.0), r, r);
+}
+
 // Workgroup barrier that orders LDS accesses only.  Threads of one launch exchange data through
 // LDS alone, so global loads issued before the barrier (prefetches of the next tile) stay in
 // flight across it, and global stores are not waited for.
@@ -595,8 +604,8 @@ __global__ __launch_bounds__(kThreads) void k2_axis(AxisArgs<T> a, int B)
 // Middle pass along axis 0 (all components, in place): forward step A -> LDS -> forward step B,
 // multiplier and inverse step B in registers -> LDS -> inverse step A.
 // ------------------------------------------------------------------------------------------
-template <typename T, int D, int L1, int L2>
-__device__ __forceinline__ void middle_body(const MidArgs<T>& a, int mult)
+template <typename T, int D, int L1, int L2, int MULT>
+__device__ __forceinline__ void middle_body(const MidArgs<T>& a)
 {
     if (a.done && *a.done) return;
     constexpr int L = L1 * L2;
@@ -654,32 +663,26 @@ __device__ __forceinline__ void middle_body(const MidArgs<T>& a, int mult)
             kv2 = j - kb1 * a.Hb;
         }
         const bool colok = j < a.cols;
+        // |k|^2 is an integer below 2^24 at these lengths, exact in T
+        const T kperp = T(kv1 * kv1 + kv2 * kv2);
 #pragma unroll
         for (int k1 = 0; k1 < L1; k1++) {
             const int pos = k2 + L2 * k1;
             const int k0 = signed_index(pos, L);
             const bool inband = colok && (2 * (k0 < 0 ? -k0 : k0) < a.B0);
-            const double kk = double(k0) * k0 + double(kv1) * kv1 + double(kv2) * kv2;
-            cpx<T> z[D];
+            const T kk = T(k0 * k0) + kperp;
+            // w = scale / |k|^2, and 0 at k = 0 (G^ vanishes, I - 2G^ is the identity) and outside
+            // the band (Ga; Eyre-Milton runs on the GaNi grid only, where every k is in the band)
+            const T w = (inband && kk > T(0)) ? scale * recip_int(kk) : T(0);
+            const T kvec[3] = {T(k0), T(kv1), T(kv2)};
+            cpx<T> kz = {T(0), T(0)};
 #pragma unroll
-            for (int c = 0; c < D; c++) z[c] = s[c][k1];
-            if (!inband) {
+            for (int c = 0; c < D; c++) kz = kz + kvec[c] * s[c][k1];
+            const cpx<T> wkz = w * kz;
 #pragma unroll
-                for (int c = 0; c < D; c++) s[c][k1] = {T(0), T(0)};
-            } else if (kk == 0.0) {
-#pragma unroll
-                for (int c = 0; c < D; c++) s[c][k1] = (mult == MULT_EM) ? scale * z[c] : cpx<T>{T(0), T(0)};
-            } else {
-                const T kvec[3] = {T(k0), T(kv1), T(kv2)};
-                cpx<T> kz = {T(0), T(0)};
-#pragma unroll
-                for (int c = 0; c < D; c++) kz = kz + kvec[c] * z[c];
-                const T inv = T(1.0 / kk);
-#pragma unroll
-                for (int c = 0; c < D; c++) {
-                    const cpx<T> gz = (kvec[c] * inv) * kz;
-                    s[c][k1] = (mult == MULT_G) ? scale * gz : scale * (z[c] - T(2) * gz);
-                }
+            for (int c = 0; c < D; c++) {
+                const cpx<T> gz = kvec[c] * wkz;  // scale G^ z
+                s[c][k1] = (MULT == MULT_G) ? gz : scale * s[c][k1] - T(2) * gz;
             }
         }
 #pragma unroll
@@ -716,10 +719,10 @@ __device__ __forceinline__ void middle_body(const MidArgs<T>& a, int mult)
     }
 }
 
-template <typename T, int D, int L1, int L2>
-__global__ __launch_bounds__(kThreads) void k2_middle(MidArgs<T> a, int mult)
+template <typename T, int D, int L1, int L2, int MULT>
+__global__ __launch_bounds__(kThreads) void k2_middle(MidArgs<T> a)
 {
-    middle_body<T, D, L1, L2>(a, mult);
+    middle_body<T, D, L1, L2, MULT>(a);
 }
 
 // ------------------------------------------------------------------------------------------
