@@ -122,6 +122,32 @@ def c4_section(fgh, inputs, torch, np, n):
     return out
 
 
+def kappa_section(fgh, inputs, np, torch, n=85, kappas=(10.0, 100.0, 1000.0, 10000.0)):
+    """Iterations to 1e-6 versus the inclusion contrast kappa on the paper's square inclusion
+    (Sec. 4.6): GaNi with the four solvers, Ga with Richardson, CG and Chebyshev; the log-log
+    slope of each solver's counts (O(kappa) expected for Richardson, O(sqrt kappa) otherwise)."""
+    N = (n, n)
+    ph = torch.from_numpy(inputs.paper_square(N)).cuda()
+    out = {"N": list(N), "kappas": list(kappas), "tol": 1e-6}
+    for rule, name in ((fgh.FGH_GANI, "gani"), (fgh.FGH_GA, "ga")):
+        sol = ["richardson", "cg", "chebyshev"] + (["eyre_milton"] if rule == fgh.FGH_GANI else [])
+        rec = {}
+        for s in sol:
+            its, secs = [], []
+            for k in kappas:
+                tab = np.stack([inputs.sym_pack(t[None])[:, 0] for t in inputs.iso_tables(2, [1.0, k])])
+                plan = fgh.Plan(N, rule=rule, phase=ph, phase_table=tab, c_A=1.0, C_A=k)
+                _, st, stats = plan.solve(s, [1.0, 0.0], 1e-6, max_iter=500000)
+                its.append(stats[0]["iters"])
+                secs.append(round(stats[0]["seconds"], 4))
+                plan.close()
+            slope = float(np.polyfit(np.log10(kappas), np.log10(its), 1)[0])
+            rec[s] = {"iters": its, "seconds": secs, "loglog_slope": round(slope, 3)}
+        out[name] = rec
+        log(f"[bench] kappa sweep {name}: " + ", ".join(f"{s} {r['iters']}" for s, r in rec.items()))
+    return out
+
+
 def served_section(fgh, inputs, np, n_req, max_active=4, pool_gb=24):
     """Served stream (mixed d, N, rule, contrast, solver, tolerance; see inputs.serving_requests).
     Baseline: the same requests one at a time in plain FP64; its mean service time S sets the
@@ -260,6 +286,7 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=16)
     ap.add_argument("--no-c4", action="store_true", help="skip the 243^3 FP32-refinement section")
     ap.add_argument("--no-served", action="store_true", help="skip the served-stream section")
+    ap.add_argument("--no-kappa", action="store_true", help="skip the iterations-versus-contrast section")
     ap.add_argument("--served-n", type=int, default=64)
     ap.add_argument("--c4-n", type=int, default=243)
     ap.add_argument("--no-profile", action="store_true",
@@ -355,6 +382,7 @@ def main():
                                                 for k, v in prof_all.items()}}
     extra = None if args.no_c4 else c4_section(fgh, inputs, torch, np, args.c4_n)
     served = None if args.no_served else served_section(fgh, inputs, np, args.served_n)
+    kappa = None if args.no_kappa else kappa_section(fgh, inputs, np, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -392,6 +420,7 @@ def main():
         "cpu_baseline": cpu,
         "c4_fp32_refined_243": extra,
         "served": served,
+        "kappa_sweep": kappa,
     }
     print(json.dumps(line), flush=True)
 

@@ -552,3 +552,27 @@ def test_zero_rhs_returns_immediately():
     for s in ("cg", "chebyshev"):
         r = orc.solve(N, orc.GANI, A, np.array([0.0, 1.0]), s, 1.0, 3.0, 1e-8)
         assert r.iters == 0 and np.abs(r.e).max() == 0.0
+
+
+def _slope(kappas, counts):
+    return float(np.polyfit(np.log10(kappas), np.log10(counts), 1)[0])
+
+
+def test_iteration_scaling_with_contrast():
+    """Sec. 4.6: iterations to 1e-6 grow linearly with the contrast for Richardson and with its
+    square root for Chebyshev and Eyre-Milton (CG may do better: the paper reports faster
+    convergence at large contrast).  Square inclusion, inclusion coefficient = kappa, GaNi."""
+    N = (15, 15)
+    kappas = [10.0, 100.0, 1000.0]
+    E = np.array([1.0, 0.0])
+    counts = {s: [] for s in ("richardson", "cg", "chebyshev", "eyre_milton")}
+    for k in kappas:
+        A = _square_problem(N, k)
+        for s in counts:
+            r = orc.solve(N, orc.GANI, A, E, s, 1.0, k, 1e-6, max_iter=100000)
+            assert r.status == orc.OK, (s, k)
+            counts[s].append(r.iters)
+    assert 0.75 <= _slope(kappas, counts["richardson"]) <= 1.25, counts
+    for s in ("chebyshev", "eyre_milton"):
+        assert 0.25 <= _slope(kappas, counts[s]) <= 0.75, (s, counts)
+    assert _slope(kappas, counts["cg"]) <= 0.75, counts
