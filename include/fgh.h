@@ -169,8 +169,9 @@ fgh_status fgh_effective(fgh_plan plan, const double* E, int nrhs, const double*
                          double* bilinear, double* flux);
 
 /* Loop history of later fgh_solve / fgh_solve_fixed calls on an FGH_FP64 plan (Sec. 4.2 residual
- * histories; Sec. 4.3, eq:guar_upper_bound_m, the energy of each iterate).  For load j and loop
- * body m (m = 0: the initial iterate) the entry at j * capacity + (m mod capacity) receives
+ * histories; Sec. 4.3, eq:guar_upper_bound_m, the energy of each iterate; Sec. 4.4 the
+ * non-conformity).  For load j and loop body m (m = 0: the initial iterate) the entry at
+ * j * capacity + (m mod capacity) of each array given receives
  *   res_hist     the stopping-test quantity relative to its scale: ||r_m|| / ||b|| (CG,
  *                Chebyshev; 1 at m = 0, 0 for a load taken as b = 0) or ||x_m - x_{m-1}|| / |E|
  *                (Richardson, Eyre-Milton; 1 at m = 0);
@@ -178,14 +179,22 @@ fgh_status fgh_effective(fgh_plan plan, const double* E, int nrhs, const double*
  *                whole iterate x_m in place of E + e_m); with `ga` set (a Ga plan on the same N,
  *                this plan GaNi) instead the guaranteed bound of the iterate,
  *                (A_{2N-1}(E + R G_N e_m), E + R G_N e_m) on the double grid (eq:ev_bounds_GaNi),
- *                which costs about two more operator applications per body.
- * res_hist, energy_hist: device double[nrhs][capacity], either may be NULL; both NULL (with ga
- * NULL) turns recording off.  The arrays and `ga` must stay alive while recording is on; the Ga
- * plan's spectrum and two FP64 vectors are overwritten.  Entries for m beyond the last body are
- * left untouched; the stats' iters tell how many are valid.  FGH_E_UNSUPPORTED for
- * FGH_FP32_REFINED plans, FGH_E_INVALID for capacity < 1 or mismatched plans. */
-fgh_status fgh_plan_set_history(fgh_plan plan, double* res_hist, double* energy_hist, int capacity,
-                                fgh_plan ga);
+ *                which costs about two more operator applications per body.  For the conforming
+ *                solvers U_E(x_m) - U_E(x*) is the squared energy-norm error of Sec. 4.5;
+ *   nonconf_hist ||G e_m - e_m||_2 with e_m the fluctuation (x_m - E for Eyre-Milton; G removes
+ *                the mean, so this is ||G x_m + E - x_m||), the non-conformity of Sec. 4.4 (G with
+ *                the band of the plan's rule);
+ *   mean_hist    |<e_m>|, the mean-value part of the orthogonal split of the non-conformity; the
+ *                zero-mean part is sqrt(nonconf^2 - mean^2).  These two cost one more operator
+ *                application per body, and `scratch` (device double[d][grid], the integration
+ *                grid) to hold G e_m; FGH_E_INVALID without it.
+ * Arrays: device double[nrhs][capacity], any of them NULL; all NULL (with ga NULL) turns
+ * recording off.  The arrays and `ga` must stay alive while recording is on; the Ga plan's
+ * spectrum and two FP64 vectors are overwritten.  Entries for m beyond the last body are left
+ * untouched; the stats' iters tell how many are valid.  FGH_E_UNSUPPORTED for FGH_FP32_REFINED
+ * plans, FGH_E_INVALID for capacity < 1 or mismatched plans. */
+fgh_status fgh_plan_set_history(fgh_plan plan, double* res_hist, double* energy_hist, double* nonconf_hist,
+                                double* mean_hist, double* scratch, int capacity, fgh_plan ga);
 
 /* Guaranteed upper bound of the GaNi solution (Sec. 2.3, eq:ev_bounds_GaNi; Sec. 4.3): the GaNi
  * fluctuation e_N is read as a trigonometric polynomial, so its prolongation R e_N to the double

@@ -312,6 +312,9 @@ struct fgh_plan_s {
     // loop history (fgh_plan_set_history): device ring buffers [nrhs][hist_cap], nullptr: off
     double* hist_res;
     double* hist_en;
+    double* hist_nc;                     // non-conformity ||G x - x~|| and its mean-value part
+    double* hist_mean;
+    double* hist_scratch;                // caller's vector for G x
     int hist_cap;
     fgh_plan hist_ga;                    // Ga plan of the GaNi bound monitor, or nullptr
     std::function<hipError_t()> hist_fn;  // records the entry of the current body count
@@ -755,8 +758,12 @@ hipError_t hist_record(fgh_plan p, const double* x, bool whole)
 {
     const OpPlan& op = p->op64;
     const int nvals = 1 + p->d;
-    if (!p->hist_en) return run_hist(op.stream, op.partials, 0, nvals, op.sc, p->hist_res, nullptr, p->hist_cap, 0.0);
     hipError_t e;
+    if ((p->hist_nc || p->hist_mean) &&
+        (e = run_hist_nonconf(op, x, op.sc->aux + (whole ? 0 : 3), p->hist_scratch, p->hist_nc, p->hist_mean,
+                              p->hist_cap)) != hipSuccess)
+        return e;
+    if (!p->hist_en) return run_hist(op.stream, op.partials, 0, nvals, op.sc, p->hist_res, nullptr, p->hist_cap, 0.0);
     int nb = 0;
     if (!p->hist_ga) {
         if ((e = run_effective(op, 1, op.sc->aux + (whole ? 3 : 0), x, &nb)) != hipSuccess) return e;
@@ -786,7 +793,7 @@ hipError_t hist_record(fgh_plan p, const double* x, bool whole)
 // Arms the history recorder for load j of a solve (x: the loop's iterate).
 fgh_status hist_arm(fgh_plan p, const double* E, int j, const double* x, bool whole)
 {
-    if (!p->hist_res && !p->hist_en) return FGH_OK;
+    if (!p->hist_res && !p->hist_en && !p->hist_nc && !p->hist_mean) return FGH_OK;
     double v[15] = {0};
     for (int c = 0; c < p->d; c++) v[c] = E[c];
     v[14] = (double)((long long)j * p->hist_cap);
@@ -794,8 +801,8 @@ fgh_status hist_arm(fgh_plan p, const double* E, int j, const double* x, bool wh
     if (p->hist_ga) HIPOK(hipMemcpyAsync(p->hist_ga->op64.sc->aux, v, 3 * sizeof(double), hipMemcpyHostToDevice,
                                          p->stream));
     p->hist_fn = [p, x, whole]() { return hist_record(p, x, whole); };
-    p->hist_key = key_of({7, bits(p->hist_res), bits(p->hist_en), (uint64_t)p->hist_cap, bits(p->hist_ga),
-                          bits(x), (uint64_t)whole});
+    p->hist_key = key_of({7, bits(p->hist_res), bits(p->hist_en), bits(p->hist_nc), bits(p->hist_mean),
+                          bits(p->hist_scratch), (uint64_t)p->hist_cap, bits(p->hist_ga), bits(x), (uint64_t)whole});
     return FGH_OK;
 }
 
@@ -1420,17 +1427,19 @@ fgh_status fgh_effective(fgh_plan p, const double* E, int nrhs, const double* e,
     return FGH_OK;
 }
 
-fgh_status fgh_plan_set_history(fgh_plan p, double* res_hist, double* energy_hist, int capacity, fgh_plan ga)
+fgh_status fgh_plan_set_history(fgh_plan p, double* res_hist, double* energy_hist, double* nonconf_hist,
+                                double* mean_hist, double* scratch, int capacity, fgh_plan ga)
 {
     if (!p) return FGH_E_INVALID;
-    if (!res_hist && !energy_hist) {
+    if (!res_hist && !energy_hist && !nonconf_hist && !mean_hist) {
         if (ga) return FGH_E_INVALID;
-        p->hist_res = p->hist_en = nullptr;
+        p->hist_res = p->hist_en = p->hist_nc = p->hist_mean = p->hist_scratch = nullptr;
         p->hist_cap = 0;
         p->hist_ga = nullptr;
         return FGH_OK;
     }
     if (capacity < 1) return FGH_E_INVALID;
+    if ((nonconf_hist || mean_hist) && !scratch) return FGH_E_INVALID;
     if (p->prec != FGH_FP64) return FGH_E_UNSUPPORTED;
     if (ga) {
         if (!energy_hist || p->rule != FGH_GANI || ga->rule != FGH_GA || ga->d != p->d) return FGH_E_INVALID;
@@ -1439,6 +1448,9 @@ fgh_status fgh_plan_set_history(fgh_plan p, double* res_hist, double* energy_his
     }
     p->hist_res = res_hist;
     p->hist_en = energy_hist;
+    p->hist_nc = nonconf_hist;
+    p->hist_mean = mean_hist;
+    p->hist_scratch = scratch;
     p->hist_cap = capacity;
     p->hist_ga = ga;
     return FGH_OK;

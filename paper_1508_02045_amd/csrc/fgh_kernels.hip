@@ -1578,6 +1578,96 @@ hipError_t run_effective(const OpPlan& op, int nrhs, const double* E, const doub
     return hipGetLastError();
 }
 
+// Non-conformity of an iterate (Sec. 4.4): partials [block][1 + D] of |y - (x - s)|^2 with
+// y = G x, and of the components of x (for its mean); s = E when x is the whole Eyre-Milton field
+// (G removes the mean, so G x = G (x - E)), s = 0 for a fluctuation.
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_nonconf(long long npts, const double* __restrict__ y,
+                                                      const double* __restrict__ x, const double* shift,
+                                                      double* partials)
+{
+    __shared__ double red[kThreads / 64];
+    double sh[D];
+#pragma unroll
+    for (int c = 0; c < D; c++) sh[c] = shift[c];
+    double acc[1 + D];
+#pragma unroll
+    for (int q = 0; q <= D; q++) acc[q] = 0.0;
+    for (long long pt = (long long)blockIdx.x * blockDim.x + threadIdx.x; pt < npts; pt += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int c = 0; c < D; c++) {
+            const double xv = x[c * npts + pt];
+            const double dv = y[c * npts + pt] - (xv - sh[c]);
+            acc[0] += dv * dv;
+            acc[1 + c] += xv;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q <= D; q++) {
+        const double tot = block_sum(acc[q], red);
+        if (threadIdx.x == 0) partials[(long long)blockIdx.x * (1 + D) + q] = tot;
+        __syncthreads();
+    }
+}
+
+// History entries of the non-conformity: nc = ||G x - (x - s)||_2 and mean = |<x> - s| (the
+// mean-value component of the Helmholtz split of the Eyre-Milton error), at slot base + m mod cap.
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_hist_nc(const double* __restrict__ partials, int nb, const Scalars* s,
+                                                      const double* shift, double* nc, double* mean, int cap,
+                                                      double inv_npts)
+{
+    __shared__ double red[kThreads / 64];
+    double tot[1 + D];
+#pragma unroll
+    for (int q = 0; q <= D; q++) {
+        double v = 0.0;
+        for (int i = threadIdx.x; i < nb; i += blockDim.x) v += partials[(long long)i * (1 + D) + q];
+        tot[q] = block_sum(v, red);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const long long slot = (long long)s->aux[14] + s->m % cap;
+        if (nc) nc[slot] = sqrt(tot[0] * inv_npts);
+        if (mean) {
+            double m2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                const double dm = tot[1 + c] * inv_npts - shift[c];
+                m2 += dm * dm;
+            }
+            mean[slot] = sqrt(m2);
+        }
+    }
+}
+
+hipError_t run_hist_nonconf(const OpPlan& op, const double* x, const double* shift, double* y, double* nc,
+                            double* mean, int cap)
+{
+    // y = G x (y: a vector of the integration grid)
+    ApplyArgs a;
+    a.op = OP_ID;
+    a.x = x;
+    a.mult = MULT_G;
+    a.epi = EPI_STORE;
+    a.sgn = 1.0;
+    a.y = y;
+    int nb = 0;
+    hipError_t e = run_apply<double>(op, a, &nb);
+    if (e != hipSuccess) return e;
+    const int nbk = 512;
+    if (op.g.d == 2) {
+        hipLaunchKernelGGL(k_nonconf<2>, dim3(nbk), dim3(kThreads), 0, op.stream, op.g.npts, y, x, shift, op.partials);
+        hipLaunchKernelGGL(k_hist_nc<2>, dim3(1), dim3(kThreads), 0, op.stream, op.partials, nbk, op.sc, shift, nc, mean,
+                           cap, 1.0 / (double)op.g.npts);
+    } else {
+        hipLaunchKernelGGL(k_nonconf<3>, dim3(nbk), dim3(kThreads), 0, op.stream, op.g.npts, y, x, shift, op.partials);
+        hipLaunchKernelGGL(k_hist_nc<3>, dim3(1), dim3(kThreads), 0, op.stream, op.partials, nbk, op.sc, shift, nc, mean,
+                           cap, 1.0 / (double)op.g.npts);
+    }
+    return hipGetLastError();
+}
+
 // One entry of a solver's history at body count m = s->m, slot base + m mod cap: the stopping-test
 // quantity (s->last times aux[12]; aux[13] before the first body) and, when `en` is set, the
 // energy reduced from the first of the nvals interleaved partial sums, times en_scale.

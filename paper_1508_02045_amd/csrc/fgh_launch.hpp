@@ -118,6 +118,10 @@ hipError_t run_dot(const OpPlan& op, long long n, const T* a, const T* b, int* n
 
 // Effective quantities: partials [nblocks][nrhs*nrhs + nrhs*d].
 hipError_t run_effective(const OpPlan& op, int nrhs, const double* E, const double* e, int* nblocks);
+// History entries of the non-conformity of the iterate x (Sec. 4.4): ||G x - (x - shift)|| and
+// |<x> - shift|; y receives G x (a vector of the integration grid); uses the partial sums.
+hipError_t run_hist_nonconf(const OpPlan& op, const double* x, const double* shift, double* y, double* nc,
+                            double* mean, int cap);
 // History entry of a solver loop (stopping-test quantity, energy from k_effective partial sums).
 hipError_t run_hist(hipStream_t stream, const double* partials, int nb, int nvals, const Scalars* sc, double* res,
                     double* en, int cap, double en_scale);

@@ -112,7 +112,7 @@ def lib():
                                       ctypes.POINTER(Stats)]
         L.fgh_effective.argtypes = [_vp, _dp, ctypes.c_int, _vp, _dp, _dp]
         L.fgh_gani_bound.argtypes = [_vp, _vp, _dp, _vp, _dp]
-        L.fgh_plan_set_history.argtypes = [_vp, _vp, _vp, ctypes.c_int, _vp]
+        L.fgh_plan_set_history.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]
         L.fgh_plan_set_profiling.argtypes = [_vp, ctypes.c_int]
         L.fgh_plan_read_profile.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]
         L.fgh_request_footprint.argtypes = [ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_size_t)]
@@ -316,27 +316,31 @@ class Plan:
         same microstructure) and integrated exactly there: an upper bound of (A_H E, E)."""
         return fgh_gani_bound(self.handle, ga_plan.handle, np.asarray(E, dtype=np.float64), e)
 
-    def set_history(self, capacity=0, nrhs=1, residual=True, energy=True, bound_plan=None):
-        """Record per-iteration histories of later solves into device arrays [nrhs][capacity]
-        (residual quantity of the stopping test; energy U_E of the iterate, or with bound_plan, a Ga
-        plan of the same N, the GaNi guaranteed bound of the iterate).  capacity 0 turns it off.
-        Returns (res, energy) tensors (None where not recorded)."""
+    def set_history(self, capacity=0, nrhs=1, residual=True, energy=True, conformity=False, bound_plan=None):
+        """Record per-iteration histories of later solves into device arrays [nrhs][capacity]:
+        the residual quantity of the stopping test, the energy U_E of the iterate (or, with
+        bound_plan, a Ga plan of the same N, the GaNi guaranteed bound of the iterate), and with
+        conformity=True the non-conformity ||G e - e|| and its mean-value part.  capacity 0 turns
+        recording off.  Returns a dict of the tensors recorded ("res", "energy", "nonconf",
+        "mean"; None where not recorded)."""
         if capacity <= 0:
-            st = lib().fgh_plan_set_history(ctypes.c_void_p(self.handle), None, None, 0, None)
+            st = lib().fgh_plan_set_history(ctypes.c_void_p(self.handle), None, None, None, None, None, 0, None)
             self._hist = None
             if st:
                 raise FghError(st, "fgh_plan_set_history")
-            return None, None
+            return {"res": None, "energy": None, "nonconf": None, "mean": None}
         mk = lambda on: (self.torch.full((nrhs, capacity), float("nan"), dtype=self.torch.float64,
                                          device=self.workspace.device) if on else None)
-        res, en = mk(residual), mk(energy)
-        st = lib().fgh_plan_set_history(ctypes.c_void_p(self.handle), _ptr(res) if res is not None else None,
-                                        _ptr(en) if en is not None else None, int(capacity),
+        h = {"res": mk(residual), "energy": mk(energy), "nonconf": mk(conformity), "mean": mk(conformity)}
+        p = lambda t: _ptr(t) if t is not None else None
+        scratch = self.field(1) if conformity else None
+        st = lib().fgh_plan_set_history(ctypes.c_void_p(self.handle), p(h["res"]), p(h["energy"]), p(h["nonconf"]),
+                                        p(h["mean"]), p(scratch), int(capacity),
                                         ctypes.c_void_p(bound_plan.handle) if bound_plan is not None else None)
         if st:
             raise FghError(st, "fgh_plan_set_history")
-        self._hist = (res, en, bound_plan)  # keep alive while recording
-        return res, en
+        self._hist = (h, scratch, bound_plan)  # keep alive while recording
+        return h
 
     def ga_coefficients(self):
         ncoef = (3 if self.d == 2 else 6) if self.a_kind == FGH_A_SYM else 1

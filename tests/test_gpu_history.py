@@ -58,7 +58,8 @@ def test_history_matches_oracle(N, rule, solver):
     Aop = orc.ga_assemble(N, A) if rule == 1 else A
     p = plan(N, A, rule)
     cap = 400
-    res, en = p.set_history(cap)
+    h = p.set_history(cap)
+    res, en = h["res"], h["energy"]
     E = np.zeros(d)
     E[0] = 1.0
     e, st, stats = p.solve(solver, E, 1e-8)
@@ -84,13 +85,15 @@ def test_history_ring_and_loads():
     N = (15, 15)
     A = I.phase_to_full(I.paper_square(N), I.iso_tables(2, [1.0, 20.0]))
     p = plan(N, A)
-    res_full, en_full = p.set_history(500, nrhs=2)
+    h = p.set_history(500, nrhs=2)
+    res_full, en_full = h["res"], h["energy"]
     E = np.eye(2)
     e, st, stats = p.solve("richardson", E, 1e-8)
     full_r = res_full.cpu().numpy()
     full_e = en_full.cpu().numpy()
     cap = 16
-    res, en = p.set_history(cap, nrhs=2)
+    h = p.set_history(cap, nrhs=2)
+    res, en = h["res"], h["energy"]
     e2, st, stats2 = p.solve("richardson", E, 1e-8)
     r = res.cpu().numpy()
     g = en.cpu().numpy()
@@ -113,7 +116,7 @@ def test_gani_bound_monitor(solver):
     A = I.phase_to_full(I.paper_square(N), I.iso_tables(2, [1.0, 100.0]))
     gani = plan(N, A, 0)
     ga = plan(N, A, 1)
-    res, en = gani.set_history(300, bound_plan=ga)
+    en = gani.set_history(300, bound_plan=ga)["energy"]
     E = np.array([1.0, 0.0])
     e, st, stats = gani.solve(solver, E, 1e-6)
     m = stats[0]["iters"]
@@ -147,8 +150,46 @@ def test_history_rejections():
     import ctypes
     h = lambda pl: ctypes.c_void_p(pl.handle)
     ptr = ctypes.c_void_p(buf.data_ptr())
-    assert lib.fgh_plan_set_history(h(p32), ptr, ptr, 8, None) == m.FGH_E_UNSUPPORTED
-    assert lib.fgh_plan_set_history(h(p64), ptr, ptr, 0, None) == m.FGH_E_INVALID
-    assert lib.fgh_plan_set_history(h(ga), ptr, ptr, 8, h(ga)) == m.FGH_E_INVALID      # Ga plan monitored
-    assert lib.fgh_plan_set_history(h(p64), ptr, None, 8, h(ga)) == m.FGH_E_INVALID    # bound needs energy
-    assert lib.fgh_plan_set_history(h(p64), None, None, 0, None) == m.FGH_OK
+    assert lib.fgh_plan_set_history(h(p32), ptr, ptr, None, None, None, 8, None) == m.FGH_E_UNSUPPORTED
+    assert lib.fgh_plan_set_history(h(p64), ptr, ptr, None, None, None, 0, None) == m.FGH_E_INVALID
+    assert lib.fgh_plan_set_history(h(ga), ptr, ptr, None, None, None, 8, h(ga)) == m.FGH_E_INVALID  # Ga monitored
+    assert lib.fgh_plan_set_history(h(p64), ptr, None, None, None, None, 8, h(ga)) == m.FGH_E_INVALID  # bound: energy
+    assert lib.fgh_plan_set_history(h(p64), None, None, ptr, None, None, 8, None) == m.FGH_E_INVALID  # no scratch
+    assert lib.fgh_plan_set_history(h(p64), None, None, None, None, None, 0, None) == m.FGH_OK
+
+
+@pytest.mark.parametrize("rule,solver", [(0, "eyre_milton"), (0, "cg"), (0, "richardson"), (1, "chebyshev")])
+def test_nonconformity_history(rule, solver):
+    """Sec. 4.4: ||G e_m - e_m|| and its mean-value part for every iterate, against the oracle's
+    iterates (projection by the oracle's own G).  Eyre-Milton is non-conforming (large values,
+    relative 1e-6); the conforming solvers stay at round-off (absolute 1e-12 |E|)."""
+    N = (15, 21)
+    A = I.phase_to_full(I.paper_square(N), I.iso_tables(2, [1.0, 20.0]))
+    Aop = orc.ga_assemble(N, A) if rule == 1 else A
+    p = plan(N, A, rule)
+    h = p.set_history(200, conformity=True)
+    E = np.array([1.0, 0.0])
+    e, st, stats = p.solve(solver, E, 1e-6)
+    m = stats[0]["iters"]
+    assert st == 0 and 2 < m < 200
+    nc = h["nonconf"][0, : m + 1].cpu().numpy()
+    mn = h["mean"][0, : m + 1].cpu().numpy()
+    g = orc.op_grid(N, rule)
+    ref_nc, ref_mn = [], []
+    for k in range(m + 1):
+        if k == 0:
+            ek = np.zeros((2,) + g)
+        else:
+            ek = orc.solve(N, rule, Aop, E, solver, 1.0, 20.0, 1e-6, fixed_iters=k).e
+        gk = orc.project(N, rule, ek)
+        ref_nc.append(np.sqrt(np.mean(np.sum((gk - ek) ** 2, axis=0))))
+        ref_mn.append(np.linalg.norm(ek.reshape(2, -1).mean(axis=1)))
+    ref_nc, ref_mn = np.array(ref_nc), np.array(ref_mn)
+    if solver == "eyre_milton":
+        assert np.all(np.abs(nc[1:] - ref_nc[1:]) <= 1e-6 * ref_nc[1:] + 1e-13), (nc, ref_nc)
+        assert np.all(np.abs(mn[1:] - ref_mn[1:]) <= 1e-6 * ref_mn[1:] + 1e-13), (mn, ref_mn)
+        assert np.all(mn <= nc * (1 + 1e-12))  # the mean part is one of two orthogonal parts
+        assert nc[1] > 1e-4  # non-conforming from the first step on
+    else:
+        assert np.all(nc <= 1e-12) and np.all(ref_nc <= 1e-12), (nc, ref_nc)
+        assert np.all(mn <= 1e-12) and np.all(ref_mn <= 1e-12), (mn, ref_mn)
