@@ -67,7 +67,7 @@ bool factorize(int L, Axis* ax)
 
 struct Config {
     int rpb, npen, P_axis, P_mid;
-    size_t lds_first, lds_axis, lds_mid;
+    size_t lds_first, lds_first_v2, lds_last_v2, lds_axis, lds_mid;
     bool v2_row, v2_axis, v2_mid;
 };
 
@@ -106,6 +106,10 @@ Config choose_config(const Geo& g, size_t cs /* bytes per complex */, size_t rs 
         if (lds <= kLdsBudget || rpb == 1) {
             c.rpb = rpb;
             c.lds_first = lds;
+            // the specialised row passes work in place: twiddles + npen rows (+1 slot each in the
+            // last pass) + table
+            c.lds_first_v2 = (size_t)(Ll + npen * Ll) * cs + tabb;
+            c.lds_last_v2 = (size_t)(Ll + npen * (Ll + 1)) * cs + tabb;
             break;
         }
     }
@@ -367,6 +371,8 @@ void fill_opplan(fgh_plan p, OpPlan* op, bool f32)
     op->P_axis = c.P_axis;
     op->P_mid = c.P_mid;
     op->lds_first = c.lds_first;
+    op->lds_first_v2 = c.lds_first_v2;
+    op->lds_last_v2 = c.lds_last_v2;
     op->lds_axis = c.lds_axis;
     op->lds_mid = c.lds_mid;
     op->v2_row = c.v2_row;

@@ -1028,55 +1028,10 @@ static hipError_t launch_axis(const OpPlan& op, const AxisArgs<T>& xa, bool inv,
 #define V2_ROW_CASES(X) X(45, 5, 9) X(63, 7, 9) X(81, 9, 9) X(125, 5, 25) X(135, 9, 15) X(243, 9, 27)
 #define V2_COL_CASES(X) X(45, 5, 9) X(63, 7, 9) X(81, 9, 9) X(125, 5, 25) X(135, 9, 15) X(243, 9, 27)
 
-// Persistent launches of the last pass: one workgroup per resident slot (occupancy at this LDS
-// size times the CU count), each walking a contiguous range of tiles.  FGH_PERSIST=0 launches
-// one workgroup per tile instead (tuning).
-static bool persist_enabled()
-{
-    static const int v = [] {
-        const char* e = std::getenv("FGH_PERSIST");
-        return e && e[0] == '0' ? 0 : 1;
-    }();
-    return v != 0;
-}
-
-static int cu_count()
-{
-    static std::atomic<int> n{0};
-    int v = n.load(std::memory_order_relaxed);
-    if (v == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1)
-            v = 1;
-        n.store(v, std::memory_order_relaxed);
-    }
-    return v;
-}
-
-// Resident workgroups of `kernel` per CU at `lds` bytes, cached per call site and LDS size.
-#define PERSIST_GRID(KERNEL, LDS, NTILES, OUT)                                                     \
-    do {                                                                                        \
-        static std::atomic<long long> key_{-1};                                                \
-        static std::atomic<int> per_{1};                                                       \
-        int per = per_.load(std::memory_order_relaxed);                                        \
-        if (key_.load(std::memory_order_relaxed) != (long long)(LDS)) {                         \
-            per = 0;                                                                            \
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (KERNEL), kThreads, (LDS)) != \
-                    hipSuccess ||                                                               \
-                per < 1)                                                                        \
-                per = 1;                                                                        \
-            per_.store(per, std::memory_order_relaxed);                                        \
-            key_.store((long long)(LDS), std::memory_order_relaxed);                            \
-        }                                                                                       \
-        const long long g_ = (long long)per * cu_count();                                      \
-        (OUT) = (unsigned)((NTILES) < g_ ? (NTILES) : g_);                                      \
-    } while (0)
-
 template <typename T, int D>
 static hipError_t v2_first(const OpPlan& op, const FirstArgs<T>& fa, int opc, unsigned nblk)
 {
-    const size_t lds = op.lds_first;
+    const size_t lds = op.lds_first_v2;
     switch (fa.ax.L) {
 #define C(LL, A1, A2) \
     case LL: LAUNCH_LDS((k2_first<T, D, A1, A2>), dim3(nblk), lds, op.stream, fa, opc); break;
@@ -1087,25 +1042,14 @@ static hipError_t v2_first(const OpPlan& op, const FirstArgs<T>& fa, int opc, un
     return hipGetLastError();
 }
 
-// nblk: in, the tile count; out, the workgroups launched (one partial sum each).
+// nblk: the tile count, one workgroup (and one partial sum) per tile.
 template <typename T, int D, int EPI>
 static hipError_t v2_last_epi(const OpPlan& op, const LastArgs<T>& la, unsigned* nblk)
 {
-    const size_t lds = op.lds_first;
-    // the Chebyshev epilogue holds three vectors per point next to the prefetched spectra: the
-    // persistent form would run at one wave per SIMD
-    const bool pf = persist_enabled() && EPI != EPI_CHEB;
+    const size_t lds = op.lds_last_v2;
     switch (la.ax.L) {
-#define C(LL, A1, A2)                                                                          \
-    case LL:                                                                                   \
-        if (pf) {                                                                              \
-            const long long nt = *nblk;                                                        \
-            PERSIST_GRID((k2_last_pf<T, D, A1, A2, EPI>), lds, nt, *nblk);                     \
-            LAUNCH_LDS((k2_last_pf<T, D, A1, A2, EPI>), dim3(*nblk), lds, op.stream, la, nt);  \
-        } else {                                                                               \
-            LAUNCH_LDS((k2_last<T, D, A1, A2, EPI>), dim3(*nblk), lds, op.stream, la);         \
-        }                                                                                      \
-        break;
+#define C(LL, A1, A2) \
+    case LL: LAUNCH_LDS((k2_last<T, D, A1, A2, EPI>), dim3(*nblk), lds, op.stream, la); break;
         V2_ROW_CASES(C)
 #undef C
         default: return hipErrorInvalidValue;

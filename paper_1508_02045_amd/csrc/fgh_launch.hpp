@@ -51,6 +51,8 @@ struct OpPlan {
     int rpb, npen;           // first/last passes: rows per block, complex pencils per block
     int P_axis, P_mid;       // axis / middle passes: tile width
     size_t lds_first, lds_axis, lds_mid;
+    size_t lds_first_v2;     // the specialised first pass (one row buffer)
+    size_t lds_last_v2;      // the specialised last pass (one row buffer)
     bool v2_row, v2_axis, v2_mid;  // size-specialised kernels for the row / axis-1 / axis-0 passes
     double* partials;        // one double per block of the last pass (and of vector kernels)
     Scalars* sc;

@@ -159,7 +159,7 @@ constexpr int ku_for(int L)
 
 // Stage 0 of the first pass for kU points starting at this thread's index base + threadIdx.x:
 // z = A(pt) u with u per FirstOp; writes the real rows Zr[(r D + c) L + i].
-template <typename T, int D, int L, int KU>
+template <typename T, int D, int L, int KU, bool IL = false>
 __device__ __forceinline__ void first_stage0_chunk(const FirstArgs<T>& a, int op, const T* tab, T beta, int base,
                                                    int total, int lim, long long pt0, T* Zr)
 {
@@ -250,7 +250,12 @@ __device__ __forceinline__ void first_stage0_chunk(const FirstArgs<T>& a, int op
             const int r = idx / L;
             const int i = idx - r * L;
 #pragma unroll
-            for (int c = 0; c < D; c++) Zr[(r * D + c) * L + i] = ok[u] ? z[u][c] : T(0);
+            for (int c = 0; c < D; c++) {
+                const int q = r * D + c;
+                // IL: real rows 2m, 2m+1 interleaved as the real and imaginary parts of complex row m
+                const int at = IL ? ((q >> 1) * L + i) * 2 + (q & 1) : q * L + i;
+                Zr[at] = ok[u] ? z[u][c] : T(0);
+            }
         }
     }
 }
@@ -273,7 +278,11 @@ __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, cons
         const int r = ii / L;
         const int i = ii - r * L;
 #pragma unroll
-        for (int c = 0; c < D; c++) y[u][c] = Zr[(r * D + c) * L + i];
+        for (int c = 0; c < D; c++) {
+            // real rows 2m, 2m+1 are the real and imaginary parts of packed row m (stride L + 1)
+            const int q = r * D + c;
+            y[u][c] = Zr[((q >> 1) * (L + 1) + i) * 2 + (q & 1)];
+        }
     }
     double acc = 0.0;
     if constexpr (epi == EPI_STORE) {
@@ -438,30 +447,41 @@ __device__ __forceinline__ long long xcd_tile(long long b, long long nb)
 //            B(k) = (X(k) - conj X(L-k)) / 2i, and store k < Hb row by row.
 // LDS: twiddles | Y (npairs rows) | Zr reals (2 npairs rows), reused as X (npairs rows).
 // ------------------------------------------------------------------------------------------
-// Stages A, B and S of the first pass for the tile of rows starting at row0 (the real rows are
-// in Zr; the caller has synchronised after writing them).
+// Stages A, B and S of the first pass in place on the packed complex rows Zc (row m holds real
+// rows 2m and 2m+1 as its real and imaginary parts).  Stage A maps all L1 jobs of one row to lanes
+// of one wavefront: the wavefront's lanes read all their inputs before any lane writes (one
+// instruction stream), so a row can be transformed in its own storage; rows of different waves
+// are disjoint.  Stage B is in place per job (it reads and writes the slots k2 + L2 j).
 template <typename T, int D, int L1, int L2>
-__device__ __forceinline__ void first_transform_store(const FirstArgs<T>& a, long long row0, const cpx<T>* tw,
-                                                      cpx<T>* Y, cpx<T>* X, const T* Zr)
+__device__ __forceinline__ void first_transform_store_ip(const FirstArgs<T>& a, long long row0, const cpx<T>* tw,
+                                                         cpx<T>* Zc)
 {
     constexpr int L = L1 * L2;
+    constexpr int PPW = 64 / L1;  // rows per wavefront in stage A
+    static_assert(PPW >= 1, "a row's stage-A jobs must fit one wavefront");
     const int npairs = (a.rpb * D + 1) / 2;
-    for (int job = threadIdx.x; job < npairs * L1; job += blockDim.x) {
-        const int m = job / L1;
-        const int n1 = job - m * L1;
-        const T* z0 = Zr + (2 * m) * L + n1;
-        const T* z1 = z0 + L;
-        cpx<T> sv[L2];
+    const int wid = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    const int nw = (npairs + PPW - 1) / PPW;
+    for (int w = wid; w < nw; w += (int)(blockDim.x >> 6)) {
+        const int m = w * PPW + lane / L1;
+        const int n1 = lane - (lane / L1) * L1;
+        const bool act = lane < PPW * L1 && m < npairs;
+        if (act) {
+            // every store below depends on every load of this lane, and the lanes share one
+            // instruction stream: all reads of the wavefront precede its writes
+            cpx<T> sv[L2];
+            const cpx<T>* z = Zc + m * L + n1;
 #pragma unroll
-        for (int n2 = 0; n2 < L2; n2++) sv[n2] = {z0[L1 * n2], z1[L1 * n2]};
-        reg_dft<T, L2, false>(sv);
-        cpx<T>* y = Y + m * L + n1 * L2;
-        int w = 0;
+            for (int n2 = 0; n2 < L2; n2++) sv[n2] = z[L1 * n2];
+            reg_dft<T, L2, false>(sv);
+            cpx<T>* y = Zc + m * L + n1 * L2;
+            int t = 0;
 #pragma unroll
-        for (int k2 = 0; k2 < L2; k2++) {
-            y[k2] = k2 ? cmul(sv[k2], tw[w]) : sv[k2];
-            w += n1;
-            if (w >= L) w -= L;
+            for (int k2 = 0; k2 < L2; k2++) {
+                y[k2] = k2 ? cmul(sv[k2], tw[t]) : sv[k2];
+                t += n1;
+                if (t >= L) t -= L;
+            }
         }
     }
     lds_barrier();
@@ -469,13 +489,12 @@ __device__ __forceinline__ void first_transform_store(const FirstArgs<T>& a, lon
         const int m = job / L2;
         const int k2 = job - m * L2;
         cpx<T> sv[L1];
-        const cpx<T>* y = Y + m * L + k2;
+        cpx<T>* y = Zc + m * L + k2;
 #pragma unroll
         for (int n1 = 0; n1 < L1; n1++) sv[n1] = y[n1 * L2];
         reg_dft<T, L1, false>(sv);
-        cpx<T>* x = X + m * L + k2;
 #pragma unroll
-        for (int k1 = 0; k1 < L1; k1++) x[L2 * k1] = sv[k1];
+        for (int k1 = 0; k1 < L1; k1++) y[L2 * k1] = sv[k1];
     }
     lds_barrier();
     // stage S: thread (tq, k) stores frequency k of the real rows q = tq, tq + qstep, ...
@@ -492,7 +511,7 @@ __device__ __forceinline__ void first_transform_store(const FirstArgs<T>& a, lon
         for (int q = tq; q < qend; q += qstep) {
             const int r = q / D;
             const int c = q - r * D;
-            const cpx<T>* x = X + (q >> 1) * L;
+            const cpx<T>* x = Zc + (q >> 1) * L;
             const cpx<T> Z = x[k];
             const cpx<T> Zm = x[k ? L - k : 0];
             const cpx<T> v = (q & 1) ? cpx<T>{T(0.5) * (Z.y + Zm.y), T(-0.5) * (Z.x - Zm.x)}
@@ -501,23 +520,23 @@ __device__ __forceinline__ void first_transform_store(const FirstArgs<T>& a, lon
         }
 }
 
+// First pass with one LDS buffer of npairs packed rows (the stages run in place).
+// LDS: twiddles | Zc (npairs complex rows) | phase table.
 template <typename T, int D, int L1, int L2>
-__global__ __launch_bounds__(kThreads) void k2_first(FirstArgs<T> a, int op)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void k2_first(FirstArgs<T> a, int op)
 {
     if (a.done && *a.done) return;
     constexpr int L = L1 * L2;
     extern __shared__ __align__(16) unsigned char smem[];
     const int npairs = (a.rpb * D + 1) / 2;
     cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
-    cpx<T>* Y = tw + L;
-    cpx<T>* X = Y + npairs * L;
-    T* Zr = reinterpret_cast<T*>(X);
-    T* tab = reinterpret_cast<T*>(X + npairs * L);
+    cpx<T>* Zc = tw + L;
+    T* tab = reinterpret_cast<T*>(Zc + npairs * L);
     for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
     if (a.A.kind == AK_PHASE)
         for (int m = threadIdx.x; m < kMaxPhases * 6; m += blockDim.x) tab[m] = T(a.A.tab[m / 6][m % 6]);
-    if ((a.rpb * D) & 1)
-        for (int i = threadIdx.x; i < L; i += blockDim.x) Zr[(2 * npairs - 1) * L + i] = T(0);
+    if ((a.rpb * D) & 1)  // the imaginary half of the last packed row is a zero row
+        for (int i = threadIdx.x; i < L; i += blockDim.x) Zc[(npairs - 1) * L + i].y = T(0);
     lds_barrier();
     const long long row0 = xcd_tile(blockIdx.x, gridDim.x) * a.rpb;
     const T beta = (op == OP_AP_CG) ? T(a.sc->beta) : T(0);
@@ -528,10 +547,11 @@ __global__ __launch_bounds__(kThreads) void k2_first(FirstArgs<T> a, int op)
         const int lim = left < total ? (int)left : total;
         constexpr int KU = ku_for(L);
         for (int base = 0; base < total; base += KU * blockDim.x)
-            first_stage0_chunk<T, D, L, KU>(a, op, tab, beta, base, total, lim, pt0, Zr);
+            first_stage0_chunk<T, D, L, KU, true>(a, op, tab, beta, base, total, lim, pt0,
+                                                  reinterpret_cast<T*>(Zc));
     }
     lds_barrier();
-    first_transform_store<T, D, L1, L2>(a, row0, tw, Y, X, Zr);
+    first_transform_store_ip<T, D, L1, L2>(a, row0, tw, Zc);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -732,61 +752,67 @@ __global__ __launch_bounds__(kThreads) void k2_middle(MidArgs<T> a)
 //             (A(L-k) = conj A(k)), inverse L1-point DFTs -> Y
 //   stage A'  inverse L2-point DFTs; real and imaginary parts are the two real rows (Zr)
 //   stage E   solver epilogue per point, the d components together.
-// LDS: twiddles | Y (npairs rows) | Sx (nreal half rows) sharing space with Zr (2 npairs rows).
+// LDS: twiddles | npairs packed rows of L + 1 slots (half spectra in, real rows out) | table.
 // ------------------------------------------------------------------------------------------
-// Stages B' and A' of the last pass: the half spectra of the tile's rows (Sx) -> real rows Zr
-// (Zr aliases Sx).  The caller has synchronised after filling Sx; returns synchronised.
+// Stages B' and A' of the last pass in place.  Packed row m has its own region of L + 1 complex
+// slots: it enters holding the half spectra of real rows 2m and 2m+1 (slots [0, Hb) and
+// [Hb, 2Hb)) and leaves holding the two real rows interleaved as one complex row.  Both stages
+// map the jobs of one row to lanes of one wavefront, whose lanes read all their inputs before any
+// lane writes (one instruction stream); rows of different waves are disjoint.  The caller has
+// synchronised after filling S; returns synchronised.
 template <typename T, int D, int L1, int L2>
-__device__ __forceinline__ void last_transform(const LastArgs<T>& a, const cpx<T>* tw, cpx<T>* Y, const cpx<T>* Sx,
-                                               T* Zr)
+__device__ __forceinline__ void last_transform(const LastArgs<T>& a, const cpx<T>* tw, cpx<T>* S)
 {
     constexpr int L = L1 * L2;
+    constexpr int LP = L + 1;
+    constexpr int PB = 64 / L2, PA = 64 / L1;  // rows per wavefront in stages B' and A'
+    static_assert(PB >= 1 && PA >= 1, "a row's jobs must fit one wavefront");
     const int npairs = (a.rpb * D + 1) / 2;
     const int Hb = a.g.Hb;
-    for (int job = threadIdx.x; job < npairs * L2; job += blockDim.x) {
-        const int m = job / L2;
-        const int k2 = job - m * L2;
-        const cpx<T>* s0 = Sx + (2 * m) * Hb;
-        const cpx<T>* s1 = s0 + Hb;
-        cpx<T> sv[L1];
+    const int wid = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63, nwaves = (int)(blockDim.x >> 6);
+    for (int w = wid; w < (npairs + PB - 1) / PB; w += nwaves) {
+        const int m = w * PB + lane / L2;
+        const int k2 = lane - (lane / L2) * L2;
+        if (lane < PB * L2 && m < npairs) {
+            const cpx<T>* s0 = S + m * LP;
+            const cpx<T>* s1 = s0 + Hb;
+            cpx<T> sv[L1];
 #pragma unroll
-        for (int k1 = 0; k1 < L1; k1++) {
-            const int k = k2 + L2 * k1;
-            cpx<T> A = {T(0), T(0)}, B = {T(0), T(0)};
-            if (k < Hb) {
-                A = s0[k];
-                B = s1[k];
-            } else if (L - k < Hb) {
-                A = conj(s0[L - k]);
-                B = conj(s1[L - k]);
+            for (int k1 = 0; k1 < L1; k1++) {
+                const int k = k2 + L2 * k1;
+                cpx<T> A = {T(0), T(0)}, B = {T(0), T(0)};
+                if (k < Hb) {
+                    A = s0[k];
+                    B = s1[k];
+                } else if (L - k < Hb) {
+                    A = conj(s0[L - k]);
+                    B = conj(s1[L - k]);
+                }
+                sv[k1] = {A.x - B.y, A.y + B.x};
             }
-            sv[k1] = {A.x - B.y, A.y + B.x};
-        }
-        reg_dft<T, L1, true>(sv);
-        cpx<T>* y = Y + m * L + k2;
-        int w = 0;
+            reg_dft<T, L1, true>(sv);
+            cpx<T>* y = S + m * LP + k2;
+            int t = 0;
 #pragma unroll
-        for (int n1 = 0; n1 < L1; n1++) {
-            y[n1 * L2] = n1 ? cmul(sv[n1], conj(tw[w])) : sv[n1];
-            w += k2;
-            if (w >= L) w -= L;
+            for (int n1 = 0; n1 < L1; n1++) {
+                y[n1 * L2] = n1 ? cmul(sv[n1], conj(tw[t])) : sv[n1];
+                t += k2;
+                if (t >= L) t -= L;
+            }
         }
     }
     lds_barrier();
-    for (int job = threadIdx.x; job < npairs * L1; job += blockDim.x) {
-        const int m = job / L1;
-        const int n1 = job - m * L1;
-        cpx<T> sv[L2];
-        const cpx<T>* y = Y + m * L + n1 * L2;
+    for (int w = wid; w < (npairs + PA - 1) / PA; w += nwaves) {
+        const int m = w * PA + lane / L1;
+        const int n1 = lane - (lane / L1) * L1;
+        if (lane < PA * L1 && m < npairs) {
+            cpx<T> sv[L2];
+            cpx<T>* y = S + m * LP;
 #pragma unroll
-        for (int k2 = 0; k2 < L2; k2++) sv[k2] = y[k2];
-        reg_dft<T, L2, true>(sv);
-        T* z0 = Zr + (2 * m) * L + n1;
-        T* z1 = z0 + L;
+            for (int k2 = 0; k2 < L2; k2++) sv[k2] = y[n1 * L2 + k2];
+            reg_dft<T, L2, true>(sv);
 #pragma unroll
-        for (int n2 = 0; n2 < L2; n2++) {
-            z0[L1 * n2] = sv[n2].x;
-            z1[L1 * n2] = sv[n2].y;
+            for (int n2 = 0; n2 < L2; n2++) y[n1 + L1 * n2] = sv[n2];
         }
     }
     lds_barrier();
@@ -816,9 +842,8 @@ __global__ __launch_bounds__(kThreads) void k2_last(LastArgs<T> a)
     extern __shared__ __align__(16) unsigned char smem[];
     const int npairs = (a.rpb * D + 1) / 2;
     cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
-    cpx<T>* Y = tw + L;
-    cpx<T>* Sx = Y + npairs * L;
-    T* Zr = reinterpret_cast<T*>(Sx);
+    cpx<T>* Sx = tw + L;  // npairs packed rows of L + 1 slots
+    const T* Zr = reinterpret_cast<const T*>(Sx);
     T* tab = reinterpret_cast<T*>(Sx + npairs * (L + 1));
     __shared__ double red[kThreads / 64];
     for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
@@ -853,88 +878,13 @@ __global__ __launch_bounds__(kThreads) void k2_last(LastArgs<T> a)
 #pragma unroll
                 for (int u = 0; u < kQ; u++) {
                     const int q = q0 + u * qstep;
-                    if (q < 2 * npairs) Sx[q * Hb + k] = v[u];
+                    if (q < 2 * npairs) Sx[(q >> 1) * (L + 1) + (q & 1) * Hb + k] = v[u];
                 }
             }
     }
     lds_barrier();
-    last_transform<T, D, L1, L2>(a, tw, Y, Sx, Zr);
+    last_transform<T, D, L1, L2>(a, tw, Sx);
     const double acc = last_epilogue_tile<T, D, L, epi>(a, tab, row0, Zr);
-    const double tot = block_sum(acc, red);
-    if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
-}
-
-// Persistent last pass: each workgroup walks a contiguous range of row tiles; the half spectra
-// of the next tile are loaded into registers before the transforms and the epilogue of the
-// current one.  Thread (tq, k) holds frequency k of the rows q = tq, tq + qstep, ... (at most
-// kQmax of them: qstep >= kThreads / ((L + 1) / 2)).
-template <int L>
-constexpr int last_qmax()
-{
-    return (2 * ((8 * 3 + 1) / 2) + (kThreads / ((L + 1) / 2)) - 1) / (kThreads / ((L + 1) / 2));
-}
-
-template <typename T, int D, int L1, int L2, int epi>
-__global__ __launch_bounds__(kThreads) void k2_last_pf(LastArgs<T> a, long long ntiles)
-{
-    if (a.done && *a.done) return;
-    constexpr int L = L1 * L2;
-    constexpr int QM = last_qmax<L>();
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int npairs = (a.rpb * D + 1) / 2;
-    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
-    cpx<T>* Y = tw + L;
-    cpx<T>* Sx = Y + npairs * L;
-    T* Zr = reinterpret_cast<T*>(Sx);
-    T* tab = reinterpret_cast<T*>(Sx + npairs * (L + 1));
-    __shared__ double red[kThreads / 64];
-    const long long G = gridDim.x;
-    const long long t0 = ntiles * (long long)blockIdx.x / G;
-    const long long t1 = ntiles * ((long long)blockIdx.x + 1) / G;
-    double acc = 0.0;
-    if (t0 < t1) {
-        for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
-        if (epi == EPI_EM && a.A.kind == AK_PHASE)
-            for (int m = threadIdx.x; m < kMaxPhases * 6; m += blockDim.x) tab[m] = T(a.A.tab_inv[m / 6][m % 6]);
-        const int Hb = a.g.Hb;
-        const int qstep = (int)blockDim.x / Hb;
-        const int tq = (int)threadIdx.x / Hb;
-        const int k = (int)threadIdx.x - tq * Hb;
-        const bool active = tq < qstep;
-        const unsigned s1 = (unsigned)a.g.s1;
-        cpx<T> v[QM];
-        auto load = [&](long long t) {
-            const long long row0 = t * a.rpb;
-            const int nrows = (int)(a.g.rows - row0 < a.rpb ? a.g.rows - row0 : a.rpb);
-            const int qend = nrows * D;
-            const cpx<T>* inb = a.in + row0 * Hb + k;
-#pragma unroll
-            for (int u = 0; u < QM; u++) {
-                const int q = tq + u * qstep;
-                const int r = q / D;
-                const int c = q - r * D;
-                const bool ok = active && q < qend;
-                const unsigned off = ok ? (unsigned)c * s1 + (unsigned)(r * Hb) : 0u;
-                v[u] = inb[off];
-                if (!ok) v[u] = {T(0), T(0)};
-            }
-        };
-        load(t0);
-        for (long long t = t0; t < t1; t++) {
-            lds_barrier();  // the previous epilogue has read Zr (which aliases Sx)
-            if (active)
-#pragma unroll
-                for (int u = 0; u < QM; u++) {
-                    const int q = tq + u * qstep;
-                    if (q < 2 * npairs) Sx[q * Hb + k] = v[u];
-                }
-            lds_barrier();
-            if (t + 1 < t1) load(t + 1);
-            last_transform<T, D, L1, L2>(a, tw, Y, Sx, Zr);
-            // the prefetched spectra stay live through the epilogue: smaller heavy chunks in FP64
-            acc += last_epilogue_tile<T, D, L, epi, sizeof(T) == 8 ? 2 : kU>(a, tab, t * a.rpb, Zr);
-        }
-    }
     const double tot = block_sum(acc, red);
     if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
 }
