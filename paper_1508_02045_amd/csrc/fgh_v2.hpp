@@ -545,7 +545,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
         const long long pt0 = row0 * L;
         const long long left = a.g.rows * (long long)L - pt0;
         const int lim = left < total ? (int)left : total;
-        constexpr int KU = ku_for(L);
+        // FP32: chunks of at most 4 points keep the pass at four waves per SIMD at the longest rows
+        constexpr int KU = (sizeof(T) == 4 && ku_for(L) > 4) ? 4 : ku_for(L);
         for (int base = 0; base < total; base += KU * blockDim.x)
             first_stage0_chunk<T, D, L, KU, true>(a, op, tab, beta, base, total, lim, pt0,
                                                   reinterpret_cast<T*>(Zc));
@@ -819,7 +820,7 @@ __device__ __forceinline__ void last_transform(const LastArgs<T>& a, const cpx<T
 }
 
 // Epilogue of the last pass over the tile of rows starting at row0; returns this thread's sum.
-template <typename T, int D, int L, int epi, int KUH = kU>
+template <typename T, int D, int L, int epi, int KUH = 2>
 __device__ __forceinline__ double last_epilogue_tile(const LastArgs<T>& a, const T* tab, long long row0, const T* Zr)
 {
     double acc = 0.0;
@@ -827,8 +828,8 @@ __device__ __forceinline__ double last_epilogue_tile(const LastArgs<T>& a, const
     const long long pt0 = row0 * L;
     const long long left = a.g.rows * (long long)L - pt0;
     const int lim = left < total ? (int)left : total;
-    // the CG and Eyre-Milton epilogues hold three more vectors per point: smaller chunks
-    constexpr int KU = (epi == EPI_CG || epi == EPI_EM) && ku_for(L) > KUH ? KUH : ku_for(L);
+    // the Chebyshev and Eyre-Milton epilogues hold three more vectors per point: smaller chunks
+    constexpr int KU = (epi == EPI_CHEB || epi == EPI_EM) && ku_for(L) > KUH ? KUH : ku_for(L);
     for (int base = 0; base < total; base += KU * blockDim.x)
         acc += last_epilogue_chunk<T, D, L, epi, KU>(a, tab, base, total, lim, pt0, Zr);
     return acc;
