@@ -143,6 +143,14 @@ __device__ __forceinline__ void coef_shift_solve_rt(const CoefArgs& A, const T* 
     }
 }
 
+// Component c of a [d][n] vector: a uniform base address, so that a point's access is that base
+// plus a 32-bit per-lane offset (no 64-bit address arithmetic per access).
+template <typename P>
+__device__ __forceinline__ P* comp(P* base, int c, unsigned n)
+{
+    return base + (size_t)c * n;
+}
+
 // Batched point processing: the loads of kU points per thread are all issued before any of them
 // is used, so one memory latency covers kU points (a loop with a runtime trip count would wait
 // once per point).  The operation and coefficient kind are uniform across the launch, so their
@@ -184,21 +192,21 @@ __device__ __forceinline__ void first_stage0_chunk(const FirstArgs<T>& a, int op
         for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) {
-                rr[u][c] = a.r[c * npts + pt[u]];
-                pp[u][c] = a.p[c * npts + pt[u]];
+                rr[u][c] = comp(a.r, c, npts)[pt[u]];
+                pp[u][c] = comp(a.p, c, npts)[pt[u]];
             }
 #pragma unroll
         for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) {
                 uu[u][c] = rr[u][c] + beta * pp[u][c];
-                if (ok[u]) a.p[c * npts + pt[u]] = uu[u][c];
+                if (ok[u]) comp(a.p, c, npts)[pt[u]] = uu[u][c];
             }
     } else {
 #pragma unroll
         for (int u = 0; u < KU; u++)
 #pragma unroll
-            for (int c = 0; c < D; c++) uu[u][c] = a.x[c * npts + pt[u]];
+            for (int c = 0; c < D; c++) uu[u][c] = comp(a.x, c, npts)[pt[u]];
         if (op == OP_AX) {
 #pragma unroll
             for (int u = 0; u < KU; u++)
@@ -233,7 +241,7 @@ __device__ __forceinline__ void first_stage0_chunk(const FirstArgs<T>& a, int op
 #pragma unroll
         for (int u = 0; u < KU; u++)
 #pragma unroll
-            for (int q = 0; q < ncoef_of<D>(); q++) co[u][q] = cc[q * npts + pt[u]];
+            for (int q = 0; q < ncoef_of<D>(); q++) co[u][q] = comp(cc, q, npts)[pt[u]];
 #pragma unroll
         for (int u = 0; u < KU; u++) sym_mul<T, D>(co[u], uu[u], z[u]);
     }
@@ -293,7 +301,7 @@ __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, cons
             for (int c = 0; c < D; c++) {
                 const T v = sg * y[u][c];
                 if (ok[u]) {
-                    a.y[c * npts + pt[u]] = v;
+                    comp(a.y, c, npts)[pt[u]] = v;
                     acc += double(v) * double(v);
                 }
             }
@@ -302,7 +310,7 @@ __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, cons
 #pragma unroll
         for (int u = 0; u < KU; u++)
 #pragma unroll
-            for (int c = 0; c < D; c++) xv[u][c] = a.x[c * npts + pt[u]];
+            for (int c = 0; c < D; c++) xv[u][c] = comp(a.x, c, npts)[pt[u]];
         const T w = T(-a.omega);
 #pragma unroll
         for (int u = 0; u < KU; u++)
@@ -310,7 +318,7 @@ __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, cons
             for (int c = 0; c < D; c++) {
                 const T st = w * y[u][c];
                 if (ok[u]) {
-                    a.x[c * npts + pt[u]] = xv[u][c] + st;
+                    comp(a.x, c, npts)[pt[u]] = xv[u][c] + st;
                     acc += double(st) * double(st);
                 }
             }
@@ -319,13 +327,13 @@ __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, cons
 #pragma unroll
         for (int u = 0; u < KU; u++)
 #pragma unroll
-            for (int c = 0; c < D; c++) pv[u][c] = a.p[c * npts + pt[u]];
+            for (int c = 0; c < D; c++) pv[u][c] = comp(a.p, c, npts)[pt[u]];
 #pragma unroll
         for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++)
                 if (ok[u]) {
-                    a.q[c * npts + pt[u]] = y[u][c];
+                    comp(a.q, c, npts)[pt[u]] = y[u][c];
                     acc += double(y[u][c]) * double(pv[u][c]);
                 }
     } else if constexpr (epi == EPI_CHEB) {
@@ -334,10 +342,10 @@ __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, cons
         for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) {
-                const unsigned o = c * npts + pt[u];
-                xv[u][c] = a.x[o];
-                rv[u][c] = a.r[o];
-                pv[u][c] = a.p[o];
+                const unsigned o = pt[u];
+                xv[u][c] = comp(a.x, c, npts)[o];
+                rv[u][c] = comp(a.r, c, npts)[o];
+                pv[u][c] = comp(a.p, c, npts)[o];
             }
         const T al = T(a.sc ? a.sc->alpha : a.alpha), be = T(a.sc ? a.sc->beta : a.beta);
 #pragma unroll
@@ -346,10 +354,10 @@ __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, cons
             for (int c = 0; c < D; c++) {
                 const T rn = rv[u][c] - al * y[u][c];
                 if (ok[u]) {
-                    const unsigned o = c * npts + pt[u];
-                    a.r[o] = rn;
-                    a.x[o] = xv[u][c] + al * pv[u][c];
-                    a.p[o] = rn - be * pv[u][c];
+                    const unsigned o = pt[u];
+                    comp(a.r, c, npts)[o] = rn;
+                    comp(a.x, c, npts)[o] = xv[u][c] + al * pv[u][c];
+                    comp(a.p, c, npts)[o] = rn - be * pv[u][c];
                     acc += double(rn) * double(rn);
                 }
             }
@@ -359,9 +367,9 @@ __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, cons
         for (int u = 0; u < KU; u++)
 #pragma unroll
             for (int c = 0; c < D; c++) {
-                const unsigned o = c * npts + pt[u];
-                xv[u][c] = a.x[o];
-                sv[u][c] = a.src ? a.src[o] : T(2.0 * a.omega * a.E[c]);
+                const unsigned o = pt[u];
+                xv[u][c] = comp(a.x, c, npts)[o];
+                sv[u][c] = a.src ? comp(a.src, c, npts)[o] : T(2.0 * a.omega * a.E[c]);
             }
         const T w = T(a.omega);
         T xn[KU][D];
@@ -391,7 +399,7 @@ __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, cons
 #pragma unroll
             for (int u = 0; u < KU; u++)
 #pragma unroll
-                for (int q = 0; q < ncoef_of<D>(); q++) co[u][q] = cc[q * npts + pt[u]];
+                for (int q = 0; q < ncoef_of<D>(); q++) co[u][q] = comp(cc, q, npts)[pt[u]];
 #pragma unroll
             for (int u = 0; u < KU; u++) {
                 T v[D];
@@ -408,7 +416,7 @@ __device__ __forceinline__ double last_epilogue_chunk(const LastArgs<T>& a, cons
                 if (a.src) xnew += sv[u][c];
                 const T st = xnew - xv[u][c];
                 if (ok[u]) {
-                    a.x[c * npts + pt[u]] = xnew;
+                    comp(a.x, c, npts)[pt[u]] = xnew;
                     acc += double(st) * double(st);
                 }
             }
@@ -506,7 +514,7 @@ __device__ __forceinline__ void first_transform_store_ip(const FirstArgs<T>& a, 
     const int nrows = (int)(a.g.rows - row0 < a.rpb ? a.g.rows - row0 : a.rpb);
     const int qend = nrows * D;
     const unsigned s1 = (unsigned)a.g.s1;
-    cpx<T>* outb = a.out + row0 * Hb + k;
+    cpx<T>* outb = a.out + row0 * Hb;  // uniform base, 32-bit per-lane offsets
     if (tq < qstep)
         for (int q = tq; q < qend; q += qstep) {
             const int r = q / D;
@@ -516,7 +524,7 @@ __device__ __forceinline__ void first_transform_store_ip(const FirstArgs<T>& a, 
             const cpx<T> Zm = x[k ? L - k : 0];
             const cpx<T> v = (q & 1) ? cpx<T>{T(0.5) * (Z.y + Zm.y), T(-0.5) * (Z.x - Zm.x)}
                                      : cpx<T>{T(0.5) * (Z.x + Zm.x), T(0.5) * (Z.y - Zm.y)};
-            outb[(unsigned)c * s1 + (unsigned)(r * Hb)] = v;
+            outb[(unsigned)c * s1 + (unsigned)(r * Hb + k)] = v;
         }
 }
 
@@ -862,7 +870,7 @@ __global__ __launch_bounds__(kThreads) void k2_last(LastArgs<T> a)
         const int nrows = (int)(a.g.rows - row0 < a.rpb ? a.g.rows - row0 : a.rpb);
         const int qend = nrows * D;
         const unsigned s1 = (unsigned)a.g.s1;
-        const cpx<T>* inb = a.in + row0 * Hb + k;
+        const cpx<T>* inb = a.in + row0 * Hb;  // uniform base, 32-bit per-lane offsets
         if (tq < qstep)
             for (int q0 = tq; q0 < 2 * npairs; q0 += kQ * qstep) {
                 cpx<T> v[kQ];
@@ -872,7 +880,7 @@ __global__ __launch_bounds__(kThreads) void k2_last(LastArgs<T> a)
                     const int r = q / D;
                     const int c = q - r * D;
                     const bool ok = q < qend;
-                    const unsigned off = ok ? (unsigned)c * s1 + (unsigned)(r * Hb) : 0u;
+                    const unsigned off = ok ? (unsigned)c * s1 + (unsigned)(r * Hb + k) : (unsigned)k;
                     v[u] = inb[off];
                     if (!ok) v[u] = {T(0), T(0)};
                 }
