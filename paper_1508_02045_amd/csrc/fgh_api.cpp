@@ -97,11 +97,12 @@ Config choose_config(const Geo& g, size_t cs /* bytes per complex */, size_t rs 
     c.v2_mid = small && v2_supported(g.L[0]);
     c.rpb = 1;
     int rpb_cap = env_int("FGH_RPB", c.v2_row ? 8 : 32);
-    if (c.v2_row && rpb_cap > 8) rpb_cap = 8;  // the specialised row kernels take tiles of at most 8 rows
+    if (rpb_cap > 32) rpb_cap = 32;
     for (int rpb = rpb_cap; rpb >= 1; rpb--) {
         const int npen = (rpb * d + 1) / 2;
-        // specialised: twiddles + two complex row buffers of npen rows (+1 element each) + table
-        const size_t lds = c.v2_row ? (size_t)(Ll + npen * Ll + npen * (Ll + 1)) * cs + tabb
+        // specialised (in place): twiddles + npen rows of L + 1 slots + table; generic: two row
+        // buffers
+        const size_t lds = c.v2_row ? (size_t)(Ll + npen * (Ll + 1)) * cs + tabb
                                     : (size_t)(Ll + 2 * npen * Ll) * cs + tabb;
         if (lds <= kLdsBudget || rpb == 1) {
             c.rpb = rpb;
@@ -367,6 +368,7 @@ void fill_opplan(fgh_plan p, OpPlan* op, bool f32)
     op->SA = p->ws + p->lay.SA;
     op->SB = p->ws + p->lay.SB;
     op->rpb = c.rpb;
+    op->rpb_first = c.rpb;
     op->npen = c.npen;
     op->P_axis = c.P_axis;
     op->P_mid = c.P_mid;
@@ -438,6 +440,72 @@ fgh_status tune_middle(fgh_plan p, OpPlan* op, bool f32)
     if (err != hipSuccess) return FGH_E_DEVICE;
     op->P_mid = best;
     op->lds_mid = lds_of(best);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = best;
+    return FGH_OK;
+}
+
+// Rows per block of the specialised first pass, measured at plan creation like the middle pass's
+// tile width.  Only even counts are tried: a tile then starts on an even real row, so rows are
+// paired into complex transforms the same way whatever the choice, and results do not depend on
+// it.
+fgh_status tune_first(fgh_plan p, OpPlan* op, bool f32, const void* x)
+{
+    if (!op->v2_row || env_int("FGH_TUNE", 1) == 0 || std::getenv("FGH_RPB")) return FGH_OK;
+    static std::mutex mu;
+    static std::map<std::vector<long long>, int> cache;
+    const Geo& g = op->g;
+    const std::vector<long long> key = {f32 ? 1 : 0, g.d, g.L[g.d - 1], g.Hb, g.rows, (long long)op->A.kind};
+    const size_t cs = f32 ? 8 : 16;
+    const size_t tabb = kMaxPhases * 6 * (f32 ? 4 : 8);
+    const int L = g.L[g.d - 1];
+    auto lds_of = [&](int r) { return (size_t)(L + (size_t)((r * g.d + 1) / 2) * L) * cs + tabb; };
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            op->rpb_first = it->second;
+            op->lds_first_v2 = lds_of(it->second);
+            return FGH_OK;
+        }
+    }
+    const int cand[] = {6, 8, 10, 12, 16};
+    hipEvent_t e0, e1;
+    HIPOK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return FGH_E_DEVICE;
+    }
+    int best = op->rpb_first;
+    float best_ms = 1e30f;
+    hipError_t err = hipSuccess;
+    for (int r : cand) {
+        if (lds_of(r) > 128 * 1024 || r > g.rows) continue;
+        OpPlan o = *op;
+        o.rpb_first = r;
+        o.lds_first_v2 = lds_of(r);
+        o.prof = nullptr;
+        auto run = [&]() {
+            return f32 ? run_first_only<float>(o, static_cast<const float*>(x))
+                       : run_first_only<double>(o, static_cast<const double*>(x));
+        };
+        if ((err = run()) != hipSuccess) break;
+        if ((err = hipEventRecord(e0, o.stream)) != hipSuccess) break;
+        for (int k = 0; k < 3 && err == hipSuccess; k++) err = run();
+        if (err != hipSuccess || (err = hipEventRecord(e1, o.stream)) != hipSuccess) break;
+        if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.0f;
+        if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = r;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return FGH_E_DEVICE;
+    op->rpb_first = best;
+    op->lds_first_v2 = lds_of(best);
     std::lock_guard<std::mutex> lk(mu);
     cache[key] = best;
     return FGH_OK;
@@ -1112,6 +1180,8 @@ fgh_status fgh_plan_create(fgh_plan* out, int d, const int32_t* N, fgh_rule rule
     if ((s = upload_twiddles(p))) return fail(s);
     if ((s = tune_middle(p, &p->op64, false))) return fail(s);
     if (precision == FGH_FP32_REFINED && (s = tune_middle(p, &p->op32, true))) return fail(s);
+    if ((s = tune_first(p, &p->op64, false, p->r64))) return fail(s);
+    if (precision == FGH_FP32_REFINED && (s = tune_first(p, &p->op32, true, p->r32))) return fail(s);
 
     long long nN = 1;
     for (int a = 0; a < d; a++) nN *= N[a];

@@ -1142,8 +1142,10 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     FirstArgs<T> fa;
     fa.g = g;
     fa.ax = op.ax[last];
-    fa.rpb = op.rpb;
-    fa.npen = op.npen;
+    const int rpb1 = op.v2_row ? op.rpb_first : op.rpb;
+    const unsigned nblk1 = (unsigned)((g.rows + rpb1 - 1) / rpb1);
+    fa.rpb = rpb1;
+    fa.npen = (rpb1 * D + 1) / 2;
     fa.x = static_cast<const T*>(a.x);
     fa.p = static_cast<T*>(a.p_cg);
     fa.r = static_cast<const T*>(a.r_cg);
@@ -1157,7 +1159,7 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     fa.twg = static_cast<const cpx<T>*>(op.tw[last]);
     const bool prof_PK_FIRST = op.prof && op.prof->wants(PK_FIRST);
     if (prof_PK_FIRST && (e = op.prof->begin(PK_FIRST)) != hipSuccess) return e;
-    if ((e = op.v2_row ? v2_first<T, D>(op, fa, a.op, nblk) : launch_first<T, D>(op, fa, a.op, nblk)) != hipSuccess)
+    if ((e = op.v2_row ? v2_first<T, D>(op, fa, a.op, nblk1) : launch_first<T, D>(op, fa, a.op, nblk1)) != hipSuccess)
         return e;
     if (prof_PK_FIRST && (e = op.prof->end()) != hipSuccess) return e;
 
@@ -1261,6 +1263,27 @@ hipError_t run_middle_only(const OpPlan& op)
 template hipError_t run_middle_only<double>(const OpPlan&);
 template hipError_t run_middle_only<float>(const OpPlan&);
 
+template <typename T>
+hipError_t run_first_only(const OpPlan& op, const T* x)
+{
+    const Geo& g = op.g;
+    const int d = g.d;
+    FirstArgs<T> fa{};
+    fa.done = nullptr;
+    fa.g = g;
+    fa.ax = op.ax[d - 1];
+    fa.rpb = op.rpb_first;
+    fa.npen = (op.rpb_first * d + 1) / 2;
+    fa.x = x;
+    fa.A = op.A;
+    fa.out = static_cast<cpx<T>*>(op.SA);
+    fa.twg = static_cast<const cpx<T>*>(op.tw[d - 1]);
+    const unsigned nblk = (unsigned)((g.rows + op.rpb_first - 1) / op.rpb_first);
+    return d == 2 ? v2_first<T, 2>(op, fa, OP_ID, nblk) : v2_first<T, 3>(op, fa, OP_ID, nblk);
+}
+template hipError_t run_first_only<double>(const OpPlan&, const double*);
+template hipError_t run_first_only<float>(const OpPlan&, const float*);
+
 // One strided-axis launch with explicit geometry (generic kernel, any length): transform along
 // an axis of length ax.L for `outer` blocks of `inner` contiguous columns per component.
 static hipError_t axis_custom(const OpPlan& op, const Axis& ax, const void* tw, bool inv, int nin, int bin, int nout,
@@ -1305,13 +1328,14 @@ hipError_t run_prolong(const OpPlan& opn, const OpPlan& opm, const double* xn, d
         fa.done = nullptr;
         fa.g = gn;
         fa.ax = opn.ax[d - 1];
-        fa.rpb = opn.rpb;
-        fa.npen = opn.npen;
+        const int rpb1 = opn.v2_row ? opn.rpb_first : opn.rpb;
+        fa.rpb = rpb1;
+        fa.npen = (rpb1 * d + 1) / 2;
         fa.x = xn;
         fa.A = opn.A;
         fa.out = reinterpret_cast<cpx<double>*>(A);
         fa.twg = static_cast<const cpx<double>*>(opn.tw[d - 1]);
-        const unsigned nblk = (unsigned)((gn.rows + opn.rpb - 1) / opn.rpb);
+        const unsigned nblk = (unsigned)((gn.rows + rpb1 - 1) / rpb1);
         if (d == 2)
             e = opn.v2_row ? v2_first<double, 2>(opn, fa, OP_ID, nblk) : launch_first<double, 2>(opn, fa, OP_ID, nblk);
         else

@@ -49,6 +49,7 @@ struct OpPlan {
     void* SB;
     CoefArgs A;              // coefficients as seen by the passes
     int rpb, npen;           // first/last passes: rows per block, complex pencils per block
+    int rpb_first;           // the specialised first pass: rows per block (even; tuned)
     int P_axis, P_mid;       // axis / middle passes: tile width
     size_t lds_first, lds_axis, lds_mid;
     size_t lds_first_v2;     // the specialised first pass (one row buffer)
@@ -90,6 +91,11 @@ hipError_t run_reduce(const OpPlan& op, int n, int redop, double* host_out);
 // buffer's contents are overwritten).
 template <typename T>
 hipError_t run_middle_only(const OpPlan& op);
+
+// The first pass alone (identity operator) from the vector x into the plan's first spectrum
+// buffer (tile tuning at plan creation).
+template <typename T>
+hipError_t run_first_only(const OpPlan& op, const T* x);
 
 // Trigonometric prolongation of a real vector field from the N grid of `opn` to the 2N-1 grid of
 // `opm` (both double precision; opm's spectrum buffers are used as scratch).
