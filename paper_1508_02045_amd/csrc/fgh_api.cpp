@@ -369,6 +369,7 @@ void fill_opplan(fgh_plan p, OpPlan* op, bool f32)
     op->SB = p->ws + p->lay.SB;
     op->rpb = c.rpb;
     op->rpb_first = c.rpb;
+    op->mid_pad = 0;
     op->npen = c.npen;
     op->P_axis = c.P_axis;
     op->P_mid = c.P_mid;
@@ -393,17 +394,18 @@ fgh_status tune_middle(fgh_plan p, OpPlan* op, bool f32)
 {
     if (!op->v2_mid || env_int("FGH_TUNE", 1) == 0 || env_int("FGH_P_EXACT", 0) != 0) return FGH_OK;
     static std::mutex mu;
-    static std::map<std::vector<long long>, int> cache;
+    static std::map<std::vector<long long>, std::pair<int, int>> cache;
     const Geo& g = op->g;
     const std::vector<long long> key = {f32 ? 1 : 0, g.d, g.L[0], g.B[0], g.B[1], g.Hb, g.cols_mid};
     const size_t cs = f32 ? 8 : 16;
-    auto lds_of = [&](int P) { return (size_t)(g.L[0] + (size_t)g.d * P * g.L[0]) * cs; };
+    auto lds_of = [&](int P, int pad) { return (size_t)(g.L[0] + (size_t)g.d * P * (g.L[0] + pad)) * cs; };
     {
         std::lock_guard<std::mutex> lk(mu);
         auto it = cache.find(key);
         if (it != cache.end()) {
-            op->P_mid = it->second;
-            op->lds_mid = lds_of(it->second);
+            op->P_mid = it->second.first;
+            op->mid_pad = it->second.second;
+            op->lds_mid = lds_of(op->P_mid, op->mid_pad);
             return FGH_OK;
         }
     }
@@ -414,34 +416,39 @@ fgh_status tune_middle(fgh_plan p, OpPlan* op, bool f32)
         (void)hipEventDestroy(e0);
         return FGH_E_DEVICE;
     }
-    int best = op->P_mid;
+    int best = op->P_mid, best_pad = 0;
     float best_ms = 1e30f;
     hipError_t err = hipSuccess;
-    for (int P : cand) {
-        if (lds_of(P) > 128 * 1024 || P > g.cols_mid) continue;
-        OpPlan o = *op;
-        o.P_mid = P;
-        o.lds_mid = lds_of(P);
-        o.prof = nullptr;
-        if ((err = f32 ? run_middle_only<float>(o) : run_middle_only<double>(o)) != hipSuccess) break;
-        if ((err = hipEventRecord(e0, o.stream)) != hipSuccess) break;
-        for (int r = 0; r < 3 && err == hipSuccess; r++) err = f32 ? run_middle_only<float>(o) : run_middle_only<double>(o);
-        if (err != hipSuccess || (err = hipEventRecord(e1, o.stream)) != hipSuccess) break;
-        if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
-        float ms = 0.0f;
-        if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = P;
+    for (int pad = 0; pad < 2 && err == hipSuccess; pad++)
+        for (int P : cand) {
+            if (lds_of(P, pad) > 128 * 1024 || P > g.cols_mid) continue;
+            OpPlan o = *op;
+            o.P_mid = P;
+            o.mid_pad = pad;
+            o.lds_mid = lds_of(P, pad);
+            o.prof = nullptr;
+            if ((err = f32 ? run_middle_only<float>(o) : run_middle_only<double>(o)) != hipSuccess) break;
+            if ((err = hipEventRecord(e0, o.stream)) != hipSuccess) break;
+            for (int r = 0; r < 3 && err == hipSuccess; r++)
+                err = f32 ? run_middle_only<float>(o) : run_middle_only<double>(o);
+            if (err != hipSuccess || (err = hipEventRecord(e1, o.stream)) != hipSuccess) break;
+            if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
+            float ms = 0.0f;
+            if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = P;
+                best_pad = pad;
+            }
         }
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err != hipSuccess) return FGH_E_DEVICE;
     op->P_mid = best;
-    op->lds_mid = lds_of(best);
+    op->mid_pad = best_pad;
+    op->lds_mid = lds_of(best, best_pad);
     std::lock_guard<std::mutex> lk(mu);
-    cache[key] = best;
+    cache[key] = {best, best_pad};
     return FGH_OK;
 }
 

@@ -114,6 +114,7 @@ struct MidArgs {
     const int* done;  // the loop's stop flag (nullptr: always run)
     Axis ax;
     int B0, cols, Hb, B1, P, ntiles;
+    int ys;        // specialised kernel: LDS stride of a column (complex elements, >= L)
     long long cs;
     double scale;  // 1 / |grid| (the forward DFT factor of eq:DFT)
     cpx<T>* buf;

@@ -1120,6 +1120,7 @@ static MidArgs<T> mid_args(const OpPlan& op, cpx<T>* buf, const int* done)
     ma.Hb = g.Hb;
     ma.B1 = g.B[1];
     ma.P = op.P_mid;
+    ma.ys = g.L[0] + op.mid_pad;
     ma.ntiles = (g.cols_mid + op.P_mid - 1) / op.P_mid;
     ma.cs = (long long)g.L[0] * g.cols_mid;
     ma.scale = 1.0 / (double)g.npts;

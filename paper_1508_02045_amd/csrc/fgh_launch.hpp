@@ -51,6 +51,7 @@ struct OpPlan {
     int rpb, npen;           // first/last passes: rows per block, complex pencils per block
     int rpb_first;           // the specialised first pass: rows per block (even; tuned)
     int P_axis, P_mid;       // axis / middle passes: tile width
+    int mid_pad;             // specialised middle pass: LDS column stride L + mid_pad (tuned)
     size_t lds_first, lds_axis, lds_mid;
     size_t lds_first_v2;     // the specialised first pass (one row buffer)
     size_t lds_last_v2;      // the specialised last pass (one row buffer)

@@ -642,7 +642,8 @@ __device__ __forceinline__ void middle_body(const MidArgs<T>& a)
     cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
     cpx<T>* Y = tw + L;
     const int P = a.P;
-    const int PL = P * L;
+    const int YS = a.ys;      // LDS stride of a column (L, or L + 1 to spread the banks)
+    const int PL = P * YS;
     const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);
     for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
     lds_barrier();
@@ -659,7 +660,7 @@ __device__ __forceinline__ void middle_body(const MidArgs<T>& a)
         for (int n2 = 0; n2 < L2; n2++)
             s[n2] = (j < a.cols) ? in[(unsigned)((n1 + L1 * n2) * a.cols)] : cpx<T>{T(0), T(0)};
         reg_dft<T, L2, false>(s);
-        cpx<T>* y = Y + c * PL + p * L + n1 * L2;
+        cpx<T>* y = Y + c * PL + p * YS + n1 * L2;
         int m = 0;
 #pragma unroll
         for (int k2 = 0; k2 < L2; k2++) {
@@ -678,7 +679,7 @@ __device__ __forceinline__ void middle_body(const MidArgs<T>& a)
         cpx<T> s[D][L1];
 #pragma unroll
         for (int c = 0; c < D; c++) {
-            const cpx<T>* y = Y + c * PL + p * L + k2;
+            const cpx<T>* y = Y + c * PL + p * YS + k2;
 #pragma unroll
             for (int n1 = 0; n1 < L1; n1++) s[c][n1] = y[n1 * L2];
             reg_dft<T, L1, false>(s[c]);
@@ -717,7 +718,7 @@ __device__ __forceinline__ void middle_body(const MidArgs<T>& a)
 #pragma unroll
         for (int c = 0; c < D; c++) {
             reg_dft<T, L1, true>(s[c]);
-            cpx<T>* y = Y + c * PL + p * L + k2;
+            cpx<T>* y = Y + c * PL + p * YS + k2;
             int m = 0;
 #pragma unroll
             for (int n1 = 0; n1 < L1; n1++) {
@@ -736,7 +737,7 @@ __device__ __forceinline__ void middle_body(const MidArgs<T>& a)
         const int n1 = cn - c * L1;
         const int j = tile * P + p;
         cpx<T> s[L2];
-        const cpx<T>* y = Y + c * PL + p * L + n1 * L2;
+        const cpx<T>* y = Y + c * PL + p * YS + n1 * L2;
 #pragma unroll
         for (int k2 = 0; k2 < L2; k2++) s[k2] = y[k2];
         reg_dft<T, L2, true>(s);
