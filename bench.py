@@ -26,8 +26,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 SOLVERS = ["richardson", "cg", "chebyshev", "eyre_milton"]
-PASS_KERNELS = {"first": "k_first", "axis_fwd": "k_axis<fwd>", "middle": "k_middle", "axis_inv": "k_axis<inv>",
-                "last": "k_last"}
+PASS_KERNELS = {"first": "k2_first", "axis_fwd": "k2_axis<forward>", "middle": "k2_middle<G>",
+                "axis_inv": "k2_axis<inverse>", "last": "k2_last"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "middle_pass_135_fp64_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1508_02045_amd", "csrc", f) for f in
                   ("fgh_kernels.hip", "fgh_fft.hpp", "fgh_internal.hpp", "fgh_v2.hpp", "fgh_args.hpp")]

@@ -1024,7 +1024,7 @@ static hipError_t launch_axis(const OpPlan& op, const AxisArgs<T>& xa, bool inv,
     return hipGetLastError();
 }
 
-// Size-specialised launches (lengths listed in kSplits).
+// Size-specialised launches: length, L1, L2 (the lengths of kV2Lengths).
 #define V2_ROW_CASES(X) X(45, 5, 9) X(63, 7, 9) X(81, 9, 9) X(125, 5, 25) X(135, 9, 15) X(243, 9, 27)
 #define V2_COL_CASES(X) X(45, 5, 9) X(63, 7, 9) X(81, 9, 9) X(125, 5, 25) X(135, 9, 15) X(243, 9, 27)
 

@@ -829,7 +829,7 @@ __device__ __forceinline__ void last_transform(const LastArgs<T>& a, const cpx<T
 }
 
 // Epilogue of the last pass over the tile of rows starting at row0; returns this thread's sum.
-template <typename T, int D, int L, int epi, int KUH = 2>
+template <typename T, int D, int L, int epi, int KUH = 2>  // KUH: points per chunk of the heavy epilogues
 __device__ __forceinline__ double last_epilogue_tile(const LastArgs<T>& a, const T* tab, long long row0, const T* Zr)
 {
     double acc = 0.0;
@@ -899,20 +899,14 @@ __global__ __launch_bounds__(kThreads) void k2_last(LastArgs<T> a)
     if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
 }
 
-// Lengths with a specialised kernel and their split L = L1 * L2 (L1 small: the middle pass holds
-// d x L1 values per job in registers, the row passes 2 x L1).
-struct Split {
-    int L, row_L1, row_L2, col_L1, col_L2;
-};
-constexpr Split kSplits[] = {
-    {45, 9, 5, 5, 9},    {63, 7, 9, 7, 9},     {81, 9, 9, 9, 9},   {125, 25, 5, 5, 25},
-    {135, 15, 9, 9, 15}, {243, 27, 9, 9, 27},
-};
+// Lengths with specialised kernels; their splits L = L1 * L2 (L1 = 5, 7 or 9: the middle pass holds
+// d x L1 values per job in registers) are listed with the launches.
+constexpr int kV2Lengths[] = {45, 63, 81, 125, 135, 243};
 
 inline bool v2_supported(int L)
 {
-    for (const Split& s : kSplits)
-        if (s.L == L) return true;
+    for (int v : kV2Lengths)
+        if (v == L) return true;
     return false;
 }
 
