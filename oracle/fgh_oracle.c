@@ -147,6 +147,72 @@ int orc_dft(int d, const int* n, double* re, double* im, int inverse)
     return ORC_OK;
 }
 
+/* Selected Fourier coefficients of the GaNi operator, by direct sums (eq:DFT, eq:linsys):
+ * for each listed frequency k (signed integers, |k_a| <= (N_a - 1)/2),
+ *   w(k) = G(k) zhat(k),  zhat(k) = (1/|N|) sum_m (A x)(m) exp(-2 pi i k.m / N),
+ * with G(k) = k k^T / (k.k) and G(0) = 0.  A: [grid][d][d]; x: [d][grid]; ks: [nk][d];
+ * out: [nk][d][2] (real, imaginary).  Full-size applies are checked at sampled frequencies
+ * with it: one coefficient costs one pass over the grid and no transform. */
+int orc_apply_at(int d, const int* N, const double* A, const double* x, int nk, const int* ks, double* out)
+{
+    grid_t g;
+    if (mk_grid(d, N, &g) || nk < 1) return ORC_E_INVALID;
+    const long S = g.size;
+    for (int q = 0; q < nk; q++)
+        for (int a = 0; a < d; a++)
+            if (2 * abs(ks[q * d + a]) >= N[a]) return ORC_E_INVALID;
+    /* per axis and frequency: exp(-2 pi i k m / n) for m in [0, n) */
+    cplx* w = (cplx*)malloc(sizeof(cplx) * (size_t)nk * 3 * 8192);
+    for (int q = 0; q < nk; q++)
+        for (int a = 0; a < d; a++)
+            for (int m = 0; m < N[a]; m++) {
+                /* the root from the exact residue (k m mod n), in long double, then rounded */
+                long km = ((long)ks[q * d + a] * m) % N[a];
+                if (km < 0) km += N[a];
+                const long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)km / (long double)N[a];
+                w[((size_t)q * 3 + a) * 8192 + m] = (double)cosl(ang) - (double)sinl(ang) * I;
+            }
+    cplx* acc = (cplx*)calloc((size_t)nk * d, sizeof(cplx));
+#pragma omp parallel
+    {
+        cplx* loc = (cplx*)calloc((size_t)nk * d, sizeof(cplx));
+#pragma omp for schedule(static)
+        for (long p = 0; p < S; p++) {
+            int idx[3] = {0, 0, 0};
+            unflatten(&g, p, idx);
+            double z[3];
+            for (int a = 0; a < d; a++) {
+                double v = 0.0;
+                for (int b = 0; b < d; b++) v += A[(p * d + a) * d + b] * x[b * S + p];
+                z[a] = v;
+            }
+            for (int q = 0; q < nk; q++) {
+                cplx e = 1.0;
+                for (int a = 0; a < d; a++) e *= w[((size_t)q * 3 + a) * 8192 + idx[a]];
+                for (int a = 0; a < d; a++) loc[q * d + a] += z[a] * e;
+            }
+        }
+#pragma omp critical
+        for (int q = 0; q < nk * d; q++) acc[q] += loc[q];
+        free(loc);
+    }
+    for (int q = 0; q < nk; q++) {
+        const int* k = ks + q * d;
+        double kk = 0.0;
+        for (int a = 0; a < d; a++) kk += (double)k[a] * k[a];
+        cplx kz = 0.0;
+        for (int a = 0; a < d; a++) kz += (double)k[a] * acc[q * d + a] / (double)S;
+        for (int a = 0; a < d; a++) {
+            const cplx v = kk > 0.0 ? (double)k[a] * kz / kk : 0.0;
+            out[(q * d + a) * 2] = creal(v);
+            out[(q * d + a) * 2 + 1] = cimag(v);
+        }
+    }
+    free(acc);
+    free(w);
+    return ORC_OK;
+}
+
 /* ---------------------------------------------------------------------------------------- */
 /* Projection (eq:proj, eq:discrete_proj).                                                    */
 /* ---------------------------------------------------------------------------------------- */

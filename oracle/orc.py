@@ -26,6 +26,7 @@ def lib():
         path = _build.ensure_built()
         L = ctypes.CDLL(path)
         L.orc_dft.argtypes = [ctypes.c_int, _ip, _dp, _dp, ctypes.c_int]
+        L.orc_apply_at.argtypes = [ctypes.c_int, _ip, _dp, _dp, ctypes.c_int, _ip, _dp]
         L.orc_apply.argtypes = [ctypes.c_int, _ip, ctypes.c_int, _dp, _dp, _dp]
         L.orc_project.argtypes = [ctypes.c_int, _ip, ctypes.c_int, _dp, _dp]
         L.orc_ga_assemble.argtypes = [ctypes.c_int, _ip, _dp, _dp]
@@ -37,7 +38,7 @@ def lib():
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                 ctypes.c_int, _dp, _ip, _dp, _dp, _dp]
         L.orc_num_threads.argtypes = []
-        for f in (L.orc_dft, L.orc_apply, L.orc_project, L.orc_ga_assemble, L.orc_prolong,
+        for f in (L.orc_dft, L.orc_apply_at, L.orc_apply, L.orc_project, L.orc_ga_assemble, L.orc_prolong,
                   L.orc_spectral_bounds, L.orc_bilinear, L.orc_flux, L.orc_solve, L.orc_num_threads):
             f.restype = ctypes.c_int
         _lib = L
@@ -77,6 +78,20 @@ def dft(c, inverse=False):
     st = lib().orc_dft(c.ndim, _ints(c.shape), _d(re), _d(im), 1 if inverse else 0)
     assert st == OK, st
     return re + 1j * im
+
+
+def apply_at(N, A, x, ks):
+    """Fourier coefficients G(k) (A x)^(k) of the GaNi operator at the listed signed frequencies
+    ks [nk][d], by direct sums over the grid (no transform); [nk][d] complex."""
+    d = len(N)
+    A = _f64(A)
+    x = _f64(x)
+    ks = np.ascontiguousarray(np.asarray(ks, dtype=np.int32).reshape(-1, d))
+    out = np.empty((ks.shape[0], d, 2), dtype=np.float64)
+    st = lib().orc_apply_at(d, _ints(N), _d(A), _d(x), ks.shape[0], ks.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                            _d(out))
+    assert st == OK, st
+    return out[..., 0] + 1j * out[..., 1]
 
 
 def apply(N, rule, A, x):

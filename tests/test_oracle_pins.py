@@ -576,3 +576,31 @@ def test_iteration_scaling_with_contrast():
     for s in ("chebyshev", "eyre_milton"):
         assert 0.25 <= _slope(kappas, counts[s]) <= 0.75, (s, counts)
     assert _slope(kappas, counts["cg"]) <= 0.75, counts
+
+
+def test_apply_at_matches_transform_of_apply():
+    """orc.apply_at (direct sums at chosen frequencies, used for the full-size GPU checks) equals
+    the library FFT of the oracle's whole-grid operator at those frequencies, and the projection
+    of the library FFT of A x (plain definition of G(k))."""
+    rng = np.random.default_rng(11)
+    for N in [(9, 11), (7, 9, 5)]:
+        d = len(N)
+        A = _random_spd_field(N, rng)
+        x = rng.standard_normal((d,) + N)
+        y = orc.apply(N, orc.GANI, A, x)
+        ks = []
+        for _ in range(6):
+            ks.append([int(rng.integers(-(n - 1) // 2, (n - 1) // 2 + 1)) for n in N])
+        ks.append([0] * d)
+        got = orc.apply_at(N, A, x, ks)
+        yh = np.stack([np.fft.fftn(y[c]) for c in range(d)]) / np.prod(N)
+        z = np.einsum("...ab,b...->a...", A, x)
+        zh = np.stack([np.fft.fftn(z[c]) for c in range(d)]) / np.prod(N)
+        for q, k in enumerate(ks):
+            idx = tuple(kk % n for kk, n in zip(k, N))
+            ref1 = yh[(slice(None),) + idx]
+            kv = np.array(k, dtype=float)
+            zk = zh[(slice(None),) + idx]
+            ref2 = kv * (kv @ zk) / (kv @ kv) if kv @ kv > 0 else np.zeros(d)
+            assert np.allclose(got[q], ref1, atol=1e-12 * np.abs(yh).max())
+            assert np.allclose(got[q], ref2, atol=1e-12 * np.abs(zh).max())
