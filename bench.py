@@ -148,6 +148,51 @@ def kappa_section(fgh, inputs, np, torch, n=85, kappas=(10.0, 100.0, 1000.0, 100
     return out
 
 
+def monitor_section(fgh, inputs, np, torch, w, plan_main):
+    """Cost of the per-iteration monitors on the bench workload (CG to 1e-8): no recording,
+    residual + energy history, plus the non-conformity; and the GaNi guaranteed-bound monitor on
+    the paper's 85^2 square (a Ga plan on 169^2 supplies A_{2N-1})."""
+    out = {}
+    e = plan_main.field()
+
+    def timed(tag):
+        plan_main.solve("cg", w.E, 1e-8, max_iter=5000, e=e)  # warm (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st, stats = plan_main.solve("cg", w.E, 1e-8, max_iter=5000, e=e)
+        torch.cuda.synchronize()
+        out[tag] = {"seconds": round(time.perf_counter() - t0, 4), "iters": stats[0]["iters"]}
+
+    timed("none")
+    plan_main.set_history(512)
+    timed("residual_energy")
+    plan_main.set_history(512, conformity=True)
+    timed("residual_energy_conformity")
+    plan_main.set_history(0)
+    N = (85, 85)
+    tab = np.stack([inputs.sym_pack(t[None])[:, 0] for t in inputs.iso_tables(2, [1.0, 100.0])])
+    ph = torch.from_numpy(inputs.paper_square(N)).cuda()
+    gani = fgh.Plan(N, rule=fgh.FGH_GANI, phase=ph, phase_table=tab, c_A=1.0, C_A=100.0)
+    ga = fgh.Plan(N, rule=fgh.FGH_GA, phase=ph, phase_table=tab, c_A=1.0, C_A=100.0)
+    rec = {}
+    for tag, bound in (("none", False), ("gani_bound_monitor", True)):
+        if bound:
+            h = gani.set_history(256, bound_plan=ga)
+        gani.solve("cg", [1.0, 0.0], 1e-6)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e2, st, stats = gani.solve("cg", [1.0, 0.0], 1e-6)
+        torch.cuda.synchronize()
+        rec[tag] = {"seconds": round(time.perf_counter() - t0, 4), "iters": stats[0]["iters"]}
+        if bound:
+            en = h["energy"][0, : stats[0]["iters"] + 1].cpu().numpy()
+            rec[tag]["bound_first_last"] = [float(en[0]), float(en[-1])]
+            gani.set_history(0)
+    out["square85_cg_1e-6"] = rec
+    log(f"[bench] monitors: {out}")
+    return out
+
+
 def served_section(fgh, inputs, np, n_req, max_active=4, pool_gb=24):
     """Served stream (mixed d, N, rule, contrast, solver, tolerance; see inputs.serving_requests).
     Baseline: the same requests one at a time in plain FP64; its mean service time S sets the
@@ -287,6 +332,7 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the 243^3 FP32-refinement section")
     ap.add_argument("--no-served", action="store_true", help="skip the served-stream section")
     ap.add_argument("--no-kappa", action="store_true", help="skip the iterations-versus-contrast section")
+    ap.add_argument("--no-monitors", action="store_true", help="skip the monitor-cost section")
     ap.add_argument("--served-n", type=int, default=64)
     ap.add_argument("--c4-n", type=int, default=243)
     ap.add_argument("--no-profile", action="store_true",
@@ -383,6 +429,7 @@ def main():
     extra = None if args.no_c4 else c4_section(fgh, inputs, torch, np, args.c4_n)
     served = None if args.no_served else served_section(fgh, inputs, np, args.served_n)
     kappa = None if args.no_kappa else kappa_section(fgh, inputs, np, torch)
+    monitors = None if args.no_monitors else monitor_section(fgh, inputs, np, torch, w, plan)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -421,6 +468,7 @@ def main():
         "c4_fp32_refined_243": extra,
         "served": served,
         "kappa_sweep": kappa,
+        "monitors": monitors,
     }
     print(json.dumps(line), flush=True)
 
