@@ -214,3 +214,55 @@ def effective_tensor(N, rule, A, fields):
 
 def energy(N, rule, A, E, e):
     return bilinear(N, rule, A, E, e, E, e)
+
+
+def krylov_rhs(N, rule, A, E):
+    """b = -C E, the right-hand side of the fluctuation system C e = b (eq:linsys), with E the
+    constant field on the integration grid."""
+    d = len(N)
+    g = op_grid(N, rule)
+    Ef = np.empty((d,) + g, dtype=np.float64)
+    for a in range(d):
+        Ef[a] = E[a]
+    return -apply(N, rule, A, Ef)
+
+
+def ritz_values(N, rule, A, E, m, breakdown=1e-10):
+    """Ritz values of C = G A on the Krylov space K_m(C, b), b = -C E.
+
+    This is the plain Rayleigh-Ritz definition behind the adaptive bounds of the paper's
+    closing outlook (Sec. 5): an orthonormal basis Q of span{b, C b, ..., C^(m-1) b} is built by
+    Gram-Schmidt, applied twice to each new vector, and the eigenvalues of the m x m matrix
+    Q^T C Q are returned in ascending order.  The inner product is the plain sum over the grid
+    and the components.  When C^j b already lies in the span of the earlier vectors (relative
+    norm below `breakdown`) the space is invariant and fewer than m values are returned; a zero
+    b (round-off compared with A E) gives none.  Near the dimension of the invariant space the
+    basis is only as good as round-off lets it be, so use m well below it.
+    Test infrastructure: the GPU path builds the same values from its CG coefficients instead."""
+    b = krylov_rhs(N, rule, A, E).reshape(-1)
+    nb = np.linalg.norm(b)
+    # b that is round-off next to A E (e.g. a laminate loaded along its layers) spans nothing
+    AE = np.einsum("...ab,b->...a", _f64(A), _f64(E))
+    if not nb > 1e-12 * np.sqrt(np.sum(AE * AE)):
+        return np.zeros(0)
+    shape = b.shape
+    Q = [b / nb]
+    CQ = []
+    field_shape = (len(N),) + op_grid(N, rule)
+    for j in range(m):
+        w = apply(N, rule, A, Q[j].reshape(field_shape)).reshape(shape)
+        CQ.append(w)
+        if j == m - 1:
+            break
+        v = w.copy()
+        for _ in range(2):
+            for q in Q:
+                v = v - (q @ v) * q
+        nv = np.linalg.norm(v)
+        if nv <= breakdown * np.linalg.norm(w):
+            break
+        Q.append(v / nv)
+    Qm = np.stack(Q[: len(CQ)], axis=1)
+    T = Qm.T @ np.stack(CQ, axis=1)
+    T = 0.5 * (T + T.T)
+    return np.linalg.eigvalsh(T)

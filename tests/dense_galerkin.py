@@ -104,3 +104,39 @@ def ga_solve(N, A_full, E):
     P = grid_points(M)
     e = (_modes_at(K, P) @ c).real.reshape((d,) + M)
     return e, en
+
+
+def gani_matrices(N, A_full, E):
+    """GaNi Galerkin matrices in the gradient-mode basis: stiffness K (from A), mass M (the
+    grid inner product of the modes) and load f = -(A E, psi_l).  The eigenvalues of K c = lam M c
+    are those of C = G A on compatible fields."""
+    N = tuple(N)
+    d = len(N)
+    K = freqs(N)
+    P = grid_points(N)
+    npts = P.shape[0]
+    Phi = _modes_at(K, P)
+    A = A_full.reshape(npts, d, d)
+    Phi_c = Phi.reshape(d, npts, -1)
+    WPhi = np.einsum("pab,bpk->apk", A, Phi_c).reshape(d * npts, -1)
+    Kmat = Phi.conj().T @ WPhi / npts
+    Mmat = Phi.conj().T @ Phi / npts
+    AE = np.einsum("pab,b->ap", A, E).reshape(-1)
+    f = -(Phi.conj().T @ AE) / npts
+    return Kmat, Mmat, f
+
+
+def ga_matrices(N, A_full, E):
+    """Ga Galerkin matrices (exact integrals): K from the exact Fourier coefficients of the
+    pixel-wise constant A, M = diag(|k|^2) (the modes are orthogonal in L2), f = -(A E, psi_l)."""
+    N = tuple(N)
+    d = len(N)
+    K = freqs(N)
+    nk = K.shape[0]
+    diffs = (K[:, None, :] - K[None, :, :]).reshape(-1, d)
+    Ahat_diff = pixel_fourier_coeffs(N, A_full, diffs).reshape(nk, nk, d, d)
+    Kmat = np.einsum("la,lkab,kb->lk", K, Ahat_diff, K)
+    Mmat = np.diag(np.sum(K * K, axis=1).astype(np.float64)).astype(np.complex128)
+    Ahat_l = pixel_fourier_coeffs(N, A_full, K)
+    f = -np.einsum("la,lab,b->l", K, Ahat_l, E)
+    return Kmat, Mmat, f

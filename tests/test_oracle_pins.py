@@ -604,3 +604,106 @@ def test_apply_at_matches_transform_of_apply():
             ref2 = kv * (kv @ zk) / (kv @ kv) if kv @ kv > 0 else np.zeros(d)
             assert np.allclose(got[q], ref1, atol=1e-12 * np.abs(yh).max())
             assert np.allclose(got[q], ref2, atol=1e-12 * np.abs(zh).max())
+
+
+# ---- Ritz values of C on the Krylov space of the load (adaptive bounds, outlook of Sec. 5) ----
+
+def _dense_spectrum(N, rule, A, E):
+    """Eigenvalues lam_i of K c = lam M c (dense Galerkin, no DFT) and the weights |v_i^H f| of
+    the load in the M-orthonormal eigenvectors."""
+    import scipy.linalg as sl
+    K, M, f = (dg.gani_matrices if rule == orc.GANI else dg.ga_matrices)(N, A, E)
+    lam, V = sl.eigh(K, M)
+    return lam, np.abs(V.conj().T @ f)
+
+
+def _gauss_nodes(lam, w, m):
+    """Ritz values of diag(lam) on the Krylov space of the vector w (full reorthogonalisation,
+    in the eigenbasis): the nodes of the m-point Gauss rule of the measure sum w_i^2 delta(lam_i)."""
+    q = w / np.linalg.norm(w)
+    Q = [q]
+    for _ in range(m - 1):
+        v = lam * Q[-1]
+        for _ in range(2):
+            for u in Q:
+                v = v - (u @ v) * u
+        Q.append(v / np.linalg.norm(v))
+    Qm = np.stack(Q, axis=1)
+    return np.linalg.eigvalsh(Qm.T @ (lam[:, None] * Qm))
+
+
+@pytest.mark.parametrize("N,rule", [((5, 5), orc.GANI), ((5, 7), orc.GA), ((3, 5, 3), orc.GANI)])
+def test_ritz_values_match_dense_gauss_nodes(N, rule):
+    """Ritz values on K_m(C, b) computed through the DFT operator equal those of the dense
+    Galerkin spectrum weighted by the load (an FFT-free route), for m well below the dimension."""
+    rng = _rng(11)
+    d = len(N)
+    ph = (rng.uniform(size=N) < 0.4).astype(np.uint8)
+    A = I.phase_to_full(ph, I.iso_tables(d, [1.0, 20.0]))
+    E = np.zeros(d)
+    E[0] = 1.0
+    lam, w = _dense_spectrum(N, rule, A, E)
+    AA = A if rule == orc.GANI else orc.ga_assemble(N, A)
+    for m in (1, 3, 6, 10):
+        rv = orc.ritz_values(N, rule, AA, E, m)
+        ref = _gauss_nodes(lam, w.astype(np.float64), m)
+        assert rv.shape == (m,)
+        np.testing.assert_allclose(rv, ref, rtol=0, atol=1e-9 * lam.max())
+
+
+@pytest.mark.parametrize("N,rule", [((5, 5), orc.GANI), ((5, 7), orc.GANI), ((5, 5), orc.GA)])
+def test_ritz_extremes_at_invariant_dimension(N, rule):
+    """Once m reaches the number of eigenvalues the load excites, the extreme Ritz values are the
+    extreme excited eigenvalues of the dense Galerkin problem (to 1e-7 of the largest: at full
+    dimension the Krylov basis keeps only that much of the weakly excited directions)."""
+    rng = _rng(1)
+    d = len(N)
+    ph = (rng.uniform(size=N) < 0.4).astype(np.uint8)
+    A = I.phase_to_full(ph, I.iso_tables(d, [1.0, 20.0]))
+    E = np.zeros(d)
+    E[0] = 1.0
+    lam, w = _dense_spectrum(N, rule, A, E)
+    sel = lam[w > 1e-9 * w.max()]
+    AA = A if rule == orc.GANI else orc.ga_assemble(N, A)
+    rv = orc.ritz_values(N, rule, AA, E, len(sel))
+    assert abs(rv[0] - sel.min()) <= 1e-7 * sel.max()
+    assert abs(rv[-1] - sel.max()) <= 1e-7 * sel.max()
+
+
+@pytest.mark.parametrize("N,layers", [((9, 7), [1, 1, 0, 0, 0, 1, 0, 0, 0]), ((7, 5, 9), [0, 1, 1, 0, 1, 0, 0])])
+def test_ritz_laminate_closed_form(N, layers):
+    """Pixel-aligned laminate loaded across its layers: b = -G(a E) is the zero-mean part of the
+    layer profile times e_0, and G(a v) = (a v - mean(a v)) e_0 for such fields, so b is an
+    eigenvector with eigenvalue (a_1 n_0 + a_0 n_1) / n (n_j layers of phase j): one Ritz value,
+    an invariant space after one step.  Loaded along the layers, b = 0 and there is none."""
+    d = len(N)
+    a0, a1 = 1.0, 10.0
+    ph = I.laminate(N, 0, layers)
+    A = I.phase_to_full(ph, I.iso_tables(d, [a0, a1]))
+    n1 = sum(layers)
+    n = len(layers)
+    E = np.zeros(d)
+    E[0] = 1.0
+    rv = orc.ritz_values(N, orc.GANI, A, E, 5)
+    assert rv.shape == (1,)
+    assert abs(rv[0] - (a1 * (n - n1) + a0 * n1) / n) <= 1e-13 * a1
+    E = np.zeros(d)
+    E[1] = 1.0
+    assert orc.ritz_values(N, orc.GANI, A, E, 5).shape == (0,)
+
+
+def test_ritz_interlacing_inside_phase_bounds():
+    """Ritz values of nested Krylov spaces interlace (Cauchy), so the smallest never rises and the
+    largest never falls with m; all lie inside [c_A, C_A] = [1, 100] (eq:A)."""
+    N = (15, 15, 15)
+    ph, _, _ = I.boolean_spheres(N, 2.5, 0.3, _rng(3))
+    A = I.phase_to_full(ph, I.iso_tables(3, [1.0, 100.0]))
+    E = np.array([1.0, 0.0, 0.0])
+    prev = None
+    for m in (2, 5, 10, 20):
+        rv = orc.ritz_values(N, orc.GANI, A, E, m)
+        assert rv.shape == (m,)
+        assert rv[0] >= 1.0 - 1e-12 and rv[-1] <= 100.0 + 1e-10
+        if prev is not None:
+            assert rv[0] <= prev[0] + 1e-12 and rv[-1] >= prev[-1] - 1e-10
+        prev = rv
