@@ -209,6 +209,33 @@ fgh_status fgh_plan_set_history(fgh_plan plan, double* res_hist, double* energy_
 fgh_status fgh_gani_bound(fgh_plan gani, fgh_plan ga, const double* E, const double* e,
                           double* bound);
 
+/* Adaptive spectral bounds (the outlook of Sec. 5: spectral estimates from the CG coefficients to
+ * set the Chebyshev and Eyre-Milton parameters).  Runs up to `iters` bodies of Algorithm 2 in
+ * double precision on C e = b, b = -G A E (eq:linsys), from e = 0.  The CG coefficients alpha_k,
+ * beta_k = ||r_{k+1}||^2 / ||r_k||^2 define the Lanczos matrix T_m of C on the Krylov space
+ * K_m(C, b):
+ *   T[0][0] = 1/alpha_0,  T[k][k] = 1/alpha_k + beta_{k-1}/alpha_{k-1},  T[k][k+1] = sqrt(beta_k)/alpha_k,
+ * whose eigenvalues (Ritz values) lie inside the spectrum of C on compatible fields, itself
+ * inside [c_A, C_A] (eq:A).  lo and hi receive the smallest and largest Ritz value (Sturm
+ * bisection on the host); they approach the extreme eigenvalues from inside as m grows.
+ *   E      host double[d] load (b must be nonzero: FGH_E_INVALID for a homogeneous medium).
+ *   iters  1 .. 4096 CG bodies; fewer are taken when ||r_m|| <= 1e-14 ||b|| (K_m invariant).
+ *   e      device double[d][grid]: receives the CG iterate after the last body taken.
+ *   tri    host double[2 * iters] or NULL: T's diagonal in [0, m), its off-diagonal in
+ *          [iters, iters + m - 1); the rest zero.
+ *   steps  host int or NULL: m, the bodies taken.
+ * Synchronises once per body.  Overwrites the plan's CG vectors.  The plan's own bounds are not
+ * changed: see fgh_plan_set_bounds.  FGH_E_NOT_SPD if (C b, b) <= 0. */
+fgh_status fgh_estimate_bounds(fgh_plan plan, const double* E, int iters, double* e, double* tri,
+                               int* steps, double* lo, double* hi);
+
+/* Replace the spectral bounds a plan's Richardson, Chebyshev and Eyre-Milton use (Algorithms 1,
+ * 3 and 4: omega = 2/(c_A + C_A), the interval [c_A, C_A], omega = sqrt(c_A C_A)); e.g. estimates
+ * from fgh_estimate_bounds, widened by a margin since Ritz values lie inside the spectrum.
+ * Chebyshev still converges for eigenvalues outside [c_A, C_A] as long as all lie in
+ * (0, c_A + C_A).  Waits for the plan's stream.  FGH_E_INVALID unless 0 < c_A <= C_A < inf. */
+fgh_status fgh_plan_set_bounds(fgh_plan plan, double c_A, double C_A);
+
 /* Per-pass device timing (profiling aid, off by default).  `enable` is a bit mask of pass kinds
  * -- bit 0 first (A multiply + forward transform of the last axis), bit 1 forward strided axis,
  * bit 2 middle (transform of axis 0 with the Fourier multiplier), bit 3 inverse strided axis,

@@ -37,6 +37,8 @@ size_t lds_budget()
     return kLdsBudgetDefault;
 }
 constexpr double kZeroRhs = 1e-12;      // b is taken as zero when ||b|| <= kZeroRhs ||A E||
+constexpr int kMaxLanczos = 4096;       // cap on the CG steps of fgh_estimate_bounds
+constexpr double kLanczosInvariant = 1e-14;  // ||r_m|| / ||b|| below which K_m is taken as invariant
 constexpr double kInnerTolMin = 1e-4;   // FP32 inner solves stop at this relative residual
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -670,6 +672,28 @@ fgh_status run_loop(fgh_plan p, const OpPlan& op, Body body, uint64_t key, bool 
     return FGH_OK;
 }
 
+// One body of Algorithm 2: p <- r + beta p (beta = 0 before the first body, p = r), q = C p,
+// alpha = (r, r) / (q, p), x += alpha p, r -= alpha q, beta = (r_new, r_new) / (r, r).  The
+// coefficients are left in the loop's scalar block.
+template <typename T>
+hipError_t cg_body(const OpPlan& op, long long n, T* x, T* r, T* pv, T* q)
+{
+    ApplyArgs a;
+    a.op = OP_AP_CG;
+    a.p_cg = pv;
+    a.r_cg = r;
+    a.epi = EPI_CG;
+    a.eq = q;
+    a.ep = pv;
+    a.loop = true;
+    int nb = 0;
+    hipError_t e = run_apply<T>(op, a, &nb);
+    if (e != hipSuccess) return e;
+    if ((e = run_reduce_async(op, nb, RED_CG_ALPHA)) != hipSuccess) return e;
+    if ((e = run_cg_update<T>(op, n, x, r, pv, q)) != hipSuccess) return e;
+    return run_reduce_async(op, vec_blocks(), RED_CG_END);
+}
+
 // Conjugate gradients (Algorithm 2) for C x = b with b already in r, x = 0 on entry.  Stops when
 // ||r_m|| <= tol_rel ||b|| (recursive residual) or after `fixed` bodies.
 template <typename T>
@@ -689,22 +713,7 @@ fgh_status cg_core(fgh_plan p, T* x, T* r, T* pv, T* q, double tol_rel, int max_
     const double normb = std::sqrt(bb / S);
     const int limit = fixed > 0 ? fixed : max_iter;
     HIPOK(run_init_loop(op, bb, 0.0, 0.0, fixed > 0 ? -1.0 : tol_rel * normb, S, 0.0, 0.0, 0.0, limit));
-    auto body = [&]() -> hipError_t {
-        ApplyArgs a;
-        a.op = OP_AP_CG;  // p <- r + beta p (beta = 0 before the first body, p = r)
-        a.p_cg = pv;
-        a.r_cg = r;
-        a.epi = EPI_CG;
-        a.eq = q;
-        a.ep = pv;
-        a.loop = true;
-        int nb = 0;
-        hipError_t e = run_apply<T>(op, a, &nb);
-        if (e != hipSuccess) return e;
-        if ((e = run_reduce_async(op, nb, RED_CG_ALPHA)) != hipSuccess) return e;
-        if ((e = run_cg_update<T>(op, n, x, r, pv, q)) != hipSuccess) return e;
-        return run_reduce_async(op, vec_blocks(), RED_CG_END);
-    };
+    auto body = [&]() { return cg_body<T>(op, n, x, r, pv, q); };
     const uint64_t key = key_of({1, sizeof(T), bits(x), bits(r), bits(pv), bits(q)});
     return run_loop(p, op, body, key, fixed > 0, normb, out);
 }
@@ -1088,6 +1097,47 @@ fgh_status solve_one_refined(fgh_plan p, int solver, const double* E, double tol
         st->rel_res_recursive = res;
     }
     return FGH_OK;
+}
+
+
+// Symmetric tridiagonal matrix with diagonal a and off-diagonal b: the number of its eigenvalues
+// below x, from the signs of the pivots of the LDL^T factorisation of T - x I (Sturm sequence;
+// a zero pivot is replaced by a tiny negative one, as in the bisection method of Barth, Martin
+// and Wilkinson, 1967).
+int tridiag_count_below(const std::vector<double>& a, const std::vector<double>& b, double x, double pivmin)
+{
+    int cnt = 0;
+    double q = 1.0;
+    for (size_t i = 0; i < a.size(); i++) {
+        q = a[i] - x - (i ? b[i - 1] * b[i - 1] / q : 0.0);
+        if (std::fabs(q) < pivmin) q = -pivmin;
+        if (q < 0.0) cnt++;
+    }
+    return cnt;
+}
+
+// The k-th smallest eigenvalue (k from 0) of that matrix by bisection inside its Gershgorin
+// interval, to the resolution of double precision.
+double tridiag_eigenvalue(const std::vector<double>& a, const std::vector<double>& b, int k)
+{
+    const size_t m = a.size();
+    double lo = a[0], hi = a[0], scale = 0.0;
+    for (size_t i = 0; i < m; i++) {
+        const double r = (i ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+        scale = std::max(scale, std::fabs(a[i]) + r);
+    }
+    const double pivmin = std::max(scale, 1e-300) * 1e-300;
+    for (int it = 0; it < 2000; it++) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        if (tridiag_count_below(a, b, mid, pivmin) > k)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return 0.5 * (lo + hi);
 }
 
 }  // namespace
@@ -1557,6 +1607,71 @@ fgh_status fgh_gani_bound(fgh_plan gani, fgh_plan ga, const double* E, const dou
     double* y = ga->q64;  // R e on the double grid
     HIPOK(run_prolong(opn, opm, e, y));
     return fgh_effective(ga, E, 1, y, bound, nullptr);
+}
+
+/* Adaptive spectral bounds (outlook of Sec. 5): Ritz values of C on the Krylov space of the load
+ * from the coefficients of plain CG (Algorithm 2), which are those of the Lanczos process. */
+fgh_status fgh_estimate_bounds(fgh_plan p, const double* E, int iters, double* e, double* tri, int* steps,
+                               double* lo, double* hi)
+{
+    if (!p || !E || !e || !lo || !hi || iters < 1 || iters > kMaxLanczos) return FGH_E_INVALID;
+    for (int c = 0; c < p->d; c++)
+        if (!std::isfinite(E[c])) return FGH_E_INVALID;
+    const OpPlan& op = p->op64;
+    const long long n = (long long)p->d * p->g.npts;
+    const double S = (double)p->g.npts;
+    double bb = 0.0, ae2 = 0.0;
+    fgh_status s;
+    if ((s = rhs<double>(p, E, p->r64, &bb, &ae2))) return s;
+    if (!(std::sqrt(bb / S) > kZeroRhs * std::sqrt(ae2 / S))) return FGH_E_INVALID;  // b = 0: no Krylov space
+    HIPOK(run_fill<double>(p->stream, n, e, 0.0));
+    HIPOK(run_copy<double>(p->stream, n, p->p64, p->r64));
+    HIPOK(run_init_loop(op, bb, 0.0, 0.0, -1.0, S, 0.0, 0.0, 0.0, iters));
+    const Scalars* h = reinterpret_cast<const Scalars*>(p->host_buf);
+    std::vector<double> al, be;
+    for (int k = 0; k < iters; k++) {
+        HIPOK(cg_body<double>(op, n, e, p->r64, p->p64, p->q64));
+        HIPOK(hipMemcpyAsync(p->host_buf, op.sc, sizeof(Scalars), hipMemcpyDeviceToHost, op.stream));
+        HIPOK(hipStreamSynchronize(op.stream));
+        if (!(h->alpha > 0.0) || !std::isfinite(h->alpha)) {
+            if (k == 0) return FGH_E_NOT_SPD;  // (C b, b) <= 0
+            break;                             // breakdown in round-off: keep T_k
+        }
+        al.push_back(h->alpha);
+        // the residual has vanished to round-off: the Krylov space is invariant, T is complete
+        if (k == iters - 1 || !std::isfinite(h->beta) || h->rr <= kLanczosInvariant * kLanczosInvariant * bb) break;
+        be.push_back(h->beta);
+    }
+    // T_m of the Lanczos process: T[0][0] = 1/alpha_0, T[k][k] = 1/alpha_k + beta_{k-1}/alpha_{k-1},
+    // T[k][k+1] = sqrt(beta_k)/alpha_k
+    const int m = (int)al.size();
+    std::vector<double> diag(m), off(m > 0 ? m - 1 : 0);
+    for (int k = 0; k < m; k++) diag[k] = 1.0 / al[k] + (k ? be[k - 1] / al[k - 1] : 0.0);
+    for (int k = 0; k + 1 < m; k++) off[k] = std::sqrt(be[k]) / al[k];
+    *lo = tridiag_eigenvalue(diag, off, 0);
+    *hi = tridiag_eigenvalue(diag, off, m - 1);
+    if (steps) *steps = m;
+    if (tri) {
+        for (int k = 0; k < iters; k++) tri[k] = k < m ? diag[k] : 0.0;
+        for (int k = 0; k < iters; k++) tri[iters + k] = k + 1 < m ? off[k] : 0.0;
+    }
+    return FGH_OK;
+}
+
+fgh_status fgh_plan_set_bounds(fgh_plan p, double c_A, double C_A)
+{
+    if (!p || !(c_A > 0.0) || !(C_A >= c_A) || !std::isfinite(C_A)) return FGH_E_INVALID;
+    HIPOK(hipStreamSynchronize(p->stream));
+    p->cA = c_A;
+    p->CA = C_A;
+    // the per-phase (A + w I)^{-1} of Eyre-Milton depends on w = sqrt(c_A C_A)
+    const double omega = std::sqrt(c_A * C_A);
+    for (int i = 0; i < p->nphase; i++) {
+        host_shift_inverse(p->d, p->tab[i], omega, p->op64.A.tab_inv[i]);
+        host_shift_inverse(p->d, p->tab[i], omega, p->op32.A.tab_inv[i]);
+    }
+    drop_graph(p);
+    return FGH_OK;
 }
 
 }  // extern "C"

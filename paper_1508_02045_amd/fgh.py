@@ -37,8 +37,8 @@ SOLVERS = {"richardson": FGH_RICHARDSON, "cg": FGH_CG, "chebyshev": FGH_CHEBYSHE
 
 EXPORTS = ["fgh_plan_workspace", "fgh_plan_create", "fgh_plan_destroy", "fgh_plan_grid_points",
            "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32", "fgh_ga_coefficients", "fgh_solve",
-           "fgh_solve_fixed", "fgh_effective", "fgh_gani_bound", "fgh_plan_set_history", "fgh_plan_set_profiling",
-           "fgh_plan_read_profile", "fgh_request_footprint", "fgh_server_create", "fgh_server_submit", "fgh_server_poll",
+           "fgh_solve_fixed", "fgh_effective", "fgh_gani_bound", "fgh_plan_set_history", "fgh_estimate_bounds",
+           "fgh_plan_set_bounds", "fgh_plan_set_profiling", "fgh_plan_read_profile", "fgh_request_footprint", "fgh_server_create", "fgh_server_submit", "fgh_server_poll",
            "fgh_server_wait", "fgh_server_drain", "fgh_server_stats", "fgh_server_destroy",
            "fgh_status_string"]
 PASS_NAMES = ["first", "axis_fwd", "middle", "axis_inv", "last"]
@@ -113,6 +113,8 @@ def lib():
         L.fgh_effective.argtypes = [_vp, _dp, ctypes.c_int, _vp, _dp, _dp]
         L.fgh_gani_bound.argtypes = [_vp, _vp, _dp, _vp, _dp]
         L.fgh_plan_set_history.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]
+        L.fgh_estimate_bounds.argtypes = [_vp, _dp, ctypes.c_int, _vp, _dp, ctypes.POINTER(ctypes.c_int), _dp, _dp]
+        L.fgh_plan_set_bounds.argtypes = [_vp, ctypes.c_double, ctypes.c_double]
         L.fgh_plan_set_profiling.argtypes = [_vp, ctypes.c_int]
         L.fgh_plan_read_profile.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]
         L.fgh_request_footprint.argtypes = [ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_size_t)]
@@ -131,7 +133,8 @@ def lib():
         L.fgh_status_string.restype = ctypes.c_char_p
         for name in ("fgh_plan_workspace", "fgh_plan_create", "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32",
                      "fgh_ga_coefficients", "fgh_solve", "fgh_solve_fixed", "fgh_effective",
-                     "fgh_gani_bound", "fgh_plan_set_history", "fgh_plan_set_profiling", "fgh_plan_read_profile"):
+                     "fgh_gani_bound", "fgh_plan_set_history", "fgh_estimate_bounds", "fgh_plan_set_bounds",
+                     "fgh_plan_set_profiling", "fgh_plan_read_profile"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -315,6 +318,32 @@ class Plan:
         """This GaNi plan's solution e prolonged to the double grid of `ga_plan` (a Ga plan of the
         same microstructure) and integrated exactly there: an upper bound of (A_H E, E)."""
         return fgh_gani_bound(self.handle, ga_plan.handle, np.asarray(E, dtype=np.float64), e)
+
+    def estimate_bounds(self, E, iters, e=None):
+        """Lanczos estimates of the spectrum of C on the Krylov space of load E from `iters` CG
+        bodies (fewer if the space becomes invariant).  Returns a dict: "lo", "hi" (extreme Ritz
+        values), "steps" (m), "diag" and "off" (the tridiagonal T_m, numpy), "e" (the CG iterate)."""
+        E = np.asarray(E, dtype=np.float64)
+        if e is None:
+            e = self.field(1)
+        tri = np.zeros(2 * int(iters), dtype=np.float64)
+        steps = ctypes.c_int()
+        lo = ctypes.c_double()
+        hi = ctypes.c_double()
+        st = lib().fgh_estimate_bounds(ctypes.c_void_p(self.handle), E.ctypes.data_as(_dp), int(iters), _ptr(e),
+                                       tri.ctypes.data_as(_dp), ctypes.byref(steps), ctypes.byref(lo),
+                                       ctypes.byref(hi))
+        if st:
+            raise FghError(st, "fgh_estimate_bounds")
+        m = steps.value
+        return {"lo": lo.value, "hi": hi.value, "steps": m, "diag": tri[:m].copy(),
+                "off": tri[iters: iters + max(m - 1, 0)].copy(), "e": e}
+
+    def set_bounds(self, c_A, C_A):
+        """Spectral bounds for Richardson, Chebyshev and Eyre-Milton from now on."""
+        st = lib().fgh_plan_set_bounds(ctypes.c_void_p(self.handle), float(c_A), float(C_A))
+        if st:
+            raise FghError(st, "fgh_plan_set_bounds")
 
     def set_history(self, capacity=0, nrhs=1, residual=True, energy=True, conformity=False, bound_plan=None):
         """Record per-iteration histories of later solves into device arrays [nrhs][capacity]:
