@@ -193,6 +193,47 @@ def monitor_section(fgh, inputs, np, torch, w, plan_main):
     return out
 
 
+def adaptive_section(fgh, inputs, np, torch, w_main, plan_main, m=40, margins=(0.9, 1.02)):
+    """Adaptive spectral bounds: Lanczos estimates from m CG steps (fgh_estimate_bounds), set with
+    margins (lo * 0.9, hi * 1.02), against the pointwise bounds c_A, C_A of the material, for
+    Richardson, Chebyshev and Eyre-Milton to 1e-8 (CG for reference).  Workloads: the 63^3
+    anisotropic field (pointwise eigenvalues in [1, 1e3]) and the 135^3 spheres of the main line."""
+    w3 = inputs.config3()
+    plan3 = fgh.Plan(w3.N, A=torch.from_numpy(inputs.sym_pack(w3.A_full)).cuda(), a_kind=fgh.FGH_A_SYM)
+    out = {}
+    for tag, w, plan in (("aniso63", w3, plan3), ("spheres135", w_main, plan_main)):
+        e = plan.field()
+        c0, C0 = plan.bounds()
+
+        def run(s):
+            plan.solve(s, w.E, 1e-8, max_iter=200000, e=e)  # warm (graph capture)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st, stats = plan.solve(s, w.E, 1e-8, max_iter=200000, e=e)
+            torch.cuda.synchronize()
+            return {"iters": stats[0]["iters"], "seconds": round(time.perf_counter() - t0, 4), "status": st}
+
+        rec = {"pointwise_bounds": [c0, C0], "cg": run("cg")}
+        for s in ("richardson", "chebyshev", "eyre_milton"):
+            rec[s] = {"pointwise": run(s)}
+        plan.estimate_bounds(w.E, m, e=e)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        est = plan.estimate_bounds(w.E, m, e=e)
+        rec["estimate"] = {"steps": est["steps"], "seconds": round(time.perf_counter() - t0, 4),
+                           "ritz_lo": est["lo"], "ritz_hi": est["hi"]}
+        plan.set_bounds(margins[0] * est["lo"], margins[1] * est["hi"])
+        for s in ("richardson", "chebyshev", "eyre_milton"):
+            rec[s]["estimated"] = run(s)
+        plan.set_bounds(c0, C0)
+        out[tag] = rec
+        log(f"[bench] adaptive {tag}: ritz [{est['lo']:.4g}, {est['hi']:.4g}] vs [{c0:.4g}, {C0:.4g}]; " +
+            ", ".join(f"{s} {rec[s]['pointwise']['iters']} -> {rec[s]['estimated']['iters']}"
+                      for s in ("richardson", "chebyshev", "eyre_milton")) + f"; cg {rec['cg']['iters']}")
+    plan3.close()
+    return out
+
+
 def served_section(fgh, inputs, np, n_req, max_active=4, pool_gb=24):
     """Served stream (mixed d, N, rule, contrast, solver, tolerance; see inputs.serving_requests).
     Baseline: the same requests one at a time in plain FP64; its mean service time S sets the
@@ -333,6 +374,7 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the served-stream section")
     ap.add_argument("--no-kappa", action="store_true", help="skip the iterations-versus-contrast section")
     ap.add_argument("--no-monitors", action="store_true", help="skip the monitor-cost section")
+    ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive-bounds section")
     ap.add_argument("--served-n", type=int, default=64)
     ap.add_argument("--c4-n", type=int, default=243)
     ap.add_argument("--no-profile", action="store_true",
@@ -430,6 +472,7 @@ def main():
     served = None if args.no_served else served_section(fgh, inputs, np, args.served_n)
     kappa = None if args.no_kappa else kappa_section(fgh, inputs, np, torch)
     monitors = None if args.no_monitors else monitor_section(fgh, inputs, np, torch, w, plan)
+    adaptive = None if args.no_adaptive else adaptive_section(fgh, inputs, np, torch, w, plan)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -469,6 +512,7 @@ def main():
         "served": served,
         "kappa_sweep": kappa,
         "monitors": monitors,
+        "adaptive_bounds": adaptive,
     }
     print(json.dumps(line), flush=True)
 

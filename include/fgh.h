@@ -233,7 +233,9 @@ fgh_status fgh_estimate_bounds(fgh_plan plan, const double* E, int iters, double
  * 3 and 4: omega = 2/(c_A + C_A), the interval [c_A, C_A], omega = sqrt(c_A C_A)); e.g. estimates
  * from fgh_estimate_bounds, widened by a margin since Ritz values lie inside the spectrum.
  * Chebyshev still converges for eigenvalues outside [c_A, C_A] as long as all lie in
- * (0, c_A + C_A).  Waits for the plan's stream.  FGH_E_INVALID unless 0 < c_A <= C_A < inf. */
+ * (0, c_A + C_A).  Eyre-Milton contracts with (A - w I)(A + w I)^{-1} pointwise, so its rate is
+ * set by the pointwise eigenvalues of A, and bounds narrower than those can slow it down.
+ * Waits for the plan's stream.  FGH_E_INVALID unless 0 < c_A <= C_A < inf. */
 fgh_status fgh_plan_set_bounds(fgh_plan plan, double c_A, double C_A);
 
 /* Per-pass device timing (profiling aid, off by default).  `enable` is a bit mask of pass kinds
