@@ -718,6 +718,26 @@ fgh_status cg_core(fgh_plan p, T* x, T* r, T* pv, T* q, double tol_rel, int max_
     return run_loop(p, op, body, key, fixed > 0, normb, out);
 }
 
+// Fused loop bodies (the last pass also runs the next body's first pass; the loop's first body
+// gets its first pass from a prologue): with the specialised row kernels, and not while a history
+// recorder is armed (its monitors may apply operators on the plan's spectrum buffers between
+// bodies).  FGH_FUSE=0 turns fusion off.
+bool fuse_loop(fgh_plan p, const OpPlan& op)
+{
+    const char* v = std::getenv("FGH_FUSE");
+    return fusable(op) && !p->hist_fn && !(v && v[0] == '0');
+}
+
+// The loop's prologue of a fused loop: the first body's first pass alone.
+template <typename T>
+hipError_t fused_prologue(const OpPlan& op, ApplyArgs a)
+{
+    a.first_only = true;
+    a.loop = false;
+    int nb = 0;
+    return run_apply<T>(op, a, &nb);
+}
+
 // Chebyshev semi-iteration (Algorithm 3), b in r, x = 0.
 template <typename T>
 fgh_status cheb_core(fgh_plan p, T* x, T* r, T* pv, double tol_rel, int max_iter, int fixed, SolveOut* out)
@@ -738,22 +758,28 @@ fgh_status cheb_core(fgh_plan p, T* x, T* r, T* pv, double tol_rel, int max_iter
     const int limit = fixed > 0 ? fixed : max_iter;
     HIPOK(run_init_loop(op, bb, 1.0 / delta, -0.5 * (c / delta) * (c / delta), fixed > 0 ? -1.0 : tol_rel * normb, S,
                         0.0, c, delta, limit));
+    const bool fuse = fuse_loop(p, op);
+    ApplyArgs a;
+    a.op = OP_AX;
+    a.x = pv;
+    a.epi = EPI_CHEB;
+    a.ex = x;
+    a.er = r;
+    a.ep = pv;
+    a.loop = true;
+    a.cheb_dev = true;
+    if (fuse) {
+        HIPOK(fused_prologue<T>(op, a));
+        a.skip_first = true;
+        a.next_op = OP_AX;
+    }
     auto body = [&]() -> hipError_t {
-        ApplyArgs a;
-        a.op = OP_AX;
-        a.x = pv;
-        a.epi = EPI_CHEB;
-        a.ex = x;
-        a.er = r;
-        a.ep = pv;
-        a.loop = true;
-        a.cheb_dev = true;
         int nb = 0;
         hipError_t e = run_apply<T>(op, a, &nb);
         if (e != hipSuccess) return e;
         return run_reduce_async(op, nb, RED_CHEB_END);
     };
-    const uint64_t key = key_of({2, sizeof(T), bits(x), bits(r), bits(pv)});
+    const uint64_t key = key_of({2, sizeof(T), bits(x), bits(r), bits(pv), (uint64_t)fuse});
     return run_loop(p, op, body, key, fixed > 0, normb, out);
 }
 
@@ -767,22 +793,28 @@ fgh_status rich_core(fgh_plan p, T* x, const double* E0, double thr, int max_ite
     const double omega = 2.0 / (p->cA + p->CA);
     const int limit = fixed > 0 ? fixed : max_iter;
     HIPOK(run_init_loop(op, 0.0, 0.0, 0.0, fixed > 0 ? -1.0 : thr, S, 0.0, 0.0, 0.0, limit));
+    const bool fuse = fuse_loop(p, op);
+    ApplyArgs a;
+    a.op = OP_AX;
+    a.x = x;
+    for (int c = 0; c < p->d; c++) a.E[c] = E0[c];
+    a.epi = EPI_RICH;
+    a.ex = x;
+    a.omega = omega;
+    a.loop = true;
+    if (fuse) {
+        HIPOK(fused_prologue<T>(op, a));
+        a.skip_first = true;
+        a.next_op = OP_AX;
+    }
     auto body = [&]() -> hipError_t {
-        ApplyArgs a;
-        a.op = OP_AX;
-        a.x = x;
-        for (int c = 0; c < p->d; c++) a.E[c] = E0[c];
-        a.epi = EPI_RICH;
-        a.ex = x;
-        a.omega = omega;
-        a.loop = true;
         int nb = 0;
         hipError_t e = run_apply<T>(op, a, &nb);
         if (e != hipSuccess) return e;
         return run_reduce_async(op, nb, RED_STEP_END);
     };
     const uint64_t key = key_of({3, sizeof(T), bits(x), bits(E0[0]), bits(E0[1]), bits(p->d == 3 ? E0[2] : 0.0),
-                                 bits(omega)});
+                                 bits(omega), (uint64_t)fuse});
     return run_loop(p, op, body, key, fixed > 0, scale, out);
 }
 
@@ -798,24 +830,30 @@ fgh_status em_core(fgh_plan p, T* x, const double* E, const T* src, double thr, 
     const int limit = fixed > 0 ? fixed : max_iter;
     HIPOK(run_init_loop(op, 0.0, 0.0, 0.0, fixed > 0 ? -1.0 : thr, S, 1e12 * (scale > 0 ? scale : 1.0), 0.0, 0.0,
                         limit));
+    const bool fuse = fuse_loop(p, op);
+    ApplyArgs a;
+    a.op = OP_EM;
+    a.x = x;
+    a.omega = omega;
+    a.mult = MULT_EM;
+    a.epi = EPI_EM;
+    a.ex = x;
+    a.src = src;
+    for (int c = 0; c < p->d; c++) a.E[c] = E[c];
+    a.loop = true;
+    if (fuse) {
+        HIPOK(fused_prologue<T>(op, a));
+        a.skip_first = true;
+        a.next_op = OP_EM;
+    }
     auto body = [&]() -> hipError_t {
-        ApplyArgs a;
-        a.op = OP_EM;
-        a.x = x;
-        a.omega = omega;
-        a.mult = MULT_EM;
-        a.epi = EPI_EM;
-        a.ex = x;
-        a.src = src;
-        for (int c = 0; c < p->d; c++) a.E[c] = E[c];
-        a.loop = true;
         int nb = 0;
         hipError_t e = run_apply<T>(op, a, &nb);
         if (e != hipSuccess) return e;
         return run_reduce_async(op, nb, RED_STEP_END);
     };
     const uint64_t key = key_of({4, sizeof(T), bits(x), bits(src), bits(E[0]), bits(E[1]),
-                                 bits(p->d == 3 ? E[2] : 0.0), bits(omega)});
+                                 bits(p->d == 3 ? E[2] : 0.0), bits(omega), (uint64_t)fuse});
     return run_loop(p, op, body, key, fixed > 0, scale, out);
 }
 

@@ -140,6 +140,7 @@ struct LastArgs {
     CoefArgs A;
     double* partials;
     const cpx<T>* twg;
+    cpx<T>* out;    // fused last + first pass: the next body's first spectrum (rows of this tile)
 };
 
 }  // namespace fgh

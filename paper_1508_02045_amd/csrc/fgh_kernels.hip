@@ -1070,6 +1070,32 @@ static hipError_t v2_last(const OpPlan& op, const LastArgs<T>& la, int epi, unsi
     return hipErrorInvalidValue;
 }
 
+// Fused last + first pass: the last pass's LDS plus a second coefficient table.
+template <typename T, int D, int EPI>
+static hipError_t v2_lastfirst_epi(const OpPlan& op, const LastArgs<T>& la, unsigned* nblk)
+{
+    const size_t lds = op.lds_last_v2 + kMaxPhases * 6 * sizeof(T);
+    switch (la.ax.L) {
+#define C(LL, A1, A2) \
+    case LL: LAUNCH_LDS((k2_lastfirst<T, D, A1, A2, EPI>), dim3(*nblk), lds, op.stream, la); break;
+        V2_ROW_CASES(C)
+#undef C
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int D>
+static hipError_t v2_lastfirst(const OpPlan& op, const LastArgs<T>& la, int epi, unsigned* nblk)
+{
+    switch (epi) {
+        case EPI_RICH: return v2_lastfirst_epi<T, D, EPI_RICH>(op, la, nblk);
+        case EPI_CHEB: return v2_lastfirst_epi<T, D, EPI_CHEB>(op, la, nblk);
+        case EPI_EM: return v2_lastfirst_epi<T, D, EPI_EM>(op, la, nblk);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <typename T, int D>
 static hipError_t v2_middle(const OpPlan& op, const MidArgs<T>& ma, int mult)
 {
@@ -1158,11 +1184,15 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     fa.A = op.A;
     fa.out = SA;
     fa.twg = static_cast<const cpx<T>*>(op.tw[last]);
-    const bool prof_PK_FIRST = op.prof && op.prof->wants(PK_FIRST);
-    if (prof_PK_FIRST && (e = op.prof->begin(PK_FIRST)) != hipSuccess) return e;
-    if ((e = op.v2_row ? v2_first<T, D>(op, fa, a.op, nblk1) : launch_first<T, D>(op, fa, a.op, nblk1)) != hipSuccess)
-        return e;
-    if (prof_PK_FIRST && (e = op.prof->end()) != hipSuccess) return e;
+    if (!a.skip_first) {
+        const bool prof_PK_FIRST = op.prof && op.prof->wants(PK_FIRST);
+        if (prof_PK_FIRST && (e = op.prof->begin(PK_FIRST)) != hipSuccess) return e;
+        if ((e = op.v2_row ? v2_first<T, D>(op, fa, a.op, nblk1) : launch_first<T, D>(op, fa, a.op, nblk1)) !=
+            hipSuccess)
+            return e;
+        if (prof_PK_FIRST && (e = op.prof->end()) != hipSuccess) return e;
+    }
+    if (a.first_only) return hipSuccess;
 
     cpx<T>* mid = SA;
     if (D == 3) {
@@ -1244,9 +1274,16 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     la.twg = static_cast<const cpx<T>*>(op.tw[last]);
     la.done = done;
     la.sc = a.cheb_dev ? op.sc : nullptr;
+    la.out = SA;
+    const bool fused = a.next_op >= 0;
+    if (fused && (!fusable(op) || a.next_op != (a.epi == EPI_EM ? OP_EM : OP_AX) ||
+                  (a.epi != EPI_RICH && a.epi != EPI_CHEB && a.epi != EPI_EM)))
+        return hipErrorInvalidValue;
     const bool prof_PK_LAST = op.prof && op.prof->wants(PK_LAST);
     if (prof_PK_LAST && (e = op.prof->begin(PK_LAST)) != hipSuccess) return e;
-    if ((e = op.v2_row ? v2_last<T, D>(op, la, a.epi, &nblk) : launch_last<T, D>(op, la, a.epi, nblk)) != hipSuccess)
+    if ((e = fused        ? v2_lastfirst<T, D>(op, la, a.epi, &nblk)
+             : op.v2_row ? v2_last<T, D>(op, la, a.epi, &nblk)
+                         : launch_last<T, D>(op, la, a.epi, nblk)) != hipSuccess)
         return e;
     if (prof_PK_LAST && (e = op.prof->end()) != hipSuccess) return e;
     if (nblocks_last) *nblocks_last = (int)nblk;

@@ -81,7 +81,16 @@ struct ApplyArgs {
     const void* src = nullptr; // EPI_EM: additive source field (refinement); nullptr: 2 w E
     bool loop = false;       // part of a solver loop: kernels skip work once the stop flag is set
     bool cheb_dev = false;   // Chebyshev alpha, beta from the device scalars
+    // Fused loops (specialised row kernels, epilogues RICH / CHEB / EM): the last pass also runs
+    // the next body's first pass with operator next_op on the updated vector; the next body then
+    // skips its first pass.  first_only runs the first pass alone (the loop's prologue).
+    int next_op = -1;
+    bool skip_first = false;
+    bool first_only = false;
 };
+
+// Whether the plan's last pass can run the next body's first pass (see ApplyArgs::next_op).
+inline bool fusable(const OpPlan& op) { return op.v2_row; }
 
 template <typename T>
 hipError_t run_apply(const OpPlan& op, const ApplyArgs& a, int* nblocks_last);

@@ -460,9 +460,8 @@ __device__ __forceinline__ long long xcd_tile(long long b, long long nb)
 // of one wavefront: the wavefront's lanes read all their inputs before any lane writes (one
 // instruction stream), so a row can be transformed in its own storage; rows of different waves
 // are disjoint.  Stage B is in place per job (it reads and writes the slots k2 + L2 j).
-template <typename T, int D, int L1, int L2>
-__device__ __forceinline__ void first_transform_store_ip(const FirstArgs<T>& a, long long row0, const cpx<T>* tw,
-                                                         cpx<T>* Zc)
+template <typename T, int D, int L1, int L2, int RS = L1 * L2, typename Args>
+__device__ __forceinline__ void first_transform_store_ip(const Args& a, long long row0, const cpx<T>* tw, cpx<T>* Zc)
 {
     constexpr int L = L1 * L2;
     constexpr int PPW = 64 / L1;  // rows per wavefront in stage A
@@ -478,11 +477,11 @@ __device__ __forceinline__ void first_transform_store_ip(const FirstArgs<T>& a, 
             // every store below depends on every load of this lane, and the lanes share one
             // instruction stream: all reads of the wavefront precede its writes
             cpx<T> sv[L2];
-            const cpx<T>* z = Zc + m * L + n1;
+            const cpx<T>* z = Zc + m * RS + n1;
 #pragma unroll
             for (int n2 = 0; n2 < L2; n2++) sv[n2] = z[L1 * n2];
             reg_dft<T, L2, false>(sv);
-            cpx<T>* y = Zc + m * L + n1 * L2;
+            cpx<T>* y = Zc + m * RS + n1 * L2;
             int t = 0;
 #pragma unroll
             for (int k2 = 0; k2 < L2; k2++) {
@@ -497,7 +496,7 @@ __device__ __forceinline__ void first_transform_store_ip(const FirstArgs<T>& a, 
         const int m = job / L2;
         const int k2 = job - m * L2;
         cpx<T> sv[L1];
-        cpx<T>* y = Zc + m * L + k2;
+        cpx<T>* y = Zc + m * RS + k2;
 #pragma unroll
         for (int n1 = 0; n1 < L1; n1++) sv[n1] = y[n1 * L2];
         reg_dft<T, L1, false>(sv);
@@ -519,7 +518,7 @@ __device__ __forceinline__ void first_transform_store_ip(const FirstArgs<T>& a, 
         for (int q = tq; q < qend; q += qstep) {
             const int r = q / D;
             const int c = q - r * D;
-            const cpx<T>* x = Zc + (q >> 1) * L;
+            const cpx<T>* x = Zc + (q >> 1) * RS;
             const cpx<T> Z = x[k];
             const cpx<T> Zm = x[k ? L - k : 0];
             const cpx<T> v = (q & 1) ? cpx<T>{T(0.5) * (Z.y + Zm.y), T(-0.5) * (Z.x - Zm.x)}
@@ -895,6 +894,216 @@ __global__ __launch_bounds__(kThreads) void k2_last(LastArgs<T> a)
     lds_barrier();
     last_transform<T, D, L1, L2>(a, tw, Sx);
     const double acc = last_epilogue_tile<T, D, L, epi>(a, tab, row0, Zr);
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
+}
+
+// ------------------------------------------------------------------------------------------
+// Last pass of one loop body fused with the first pass of the next (Richardson, Chebyshev,
+// Eyre-Milton).  Their updates are pointwise with scalars known before the pass, so once a
+// point's iterate is updated the next operator application's operand is known there too:
+//   Richardson   x' = x - w y,                   next z = A (x' + E)
+//   Chebyshev    r' = r - a y, x' = x + a p,      next z = A p',  p' = r' - b p
+//   Eyre-Milton  x' = (A + wI)^{-1} (y + src),    next z = (A - wI) x'
+// The tile of rows is inverse-transformed as in the last pass; each point's update and its next
+// z are computed by one thread, which writes z into the very LDS slot its y came from; the rows
+// are then forward-transformed in place (row stride L + 1) and stored as the next body's first
+// spectrum.  This saves the next first pass's read of the iterate and one launch per body.
+// ------------------------------------------------------------------------------------------
+template <typename T, int D, int L, int epi, int KU>
+__device__ __forceinline__ double lastfirst_chunk(const LastArgs<T>& a, const T* tab, const T* tabinv, int base,
+                                                  int total, int lim, long long pt0, T* Zr)
+{
+    const unsigned npts = (unsigned)a.g.npts;  // 32-bit offsets: d |grid| < 2^31 here
+    unsigned pt[KU];
+    bool ok[KU];
+    int at[KU];  // the point's position within its row
+    T y[KU][D];
+#pragma unroll
+    for (int u = 0; u < KU; u++) {
+        const int idx = base + u * (int)blockDim.x + (int)threadIdx.x;
+        ok[u] = idx < lim;
+        pt[u] = ok[u] ? (unsigned)(pt0 + idx) : 0u;
+        const int r = idx / L;
+        const int i = idx - r * L;
+        at[u] = i;
+#pragma unroll
+        for (int c = 0; c < D; c++) {
+            const int q = r * D + c;
+            y[u][c] = ok[u] ? Zr[((q >> 1) * (L + 1) + i) * 2 + (q & 1)] : T(0);
+        }
+    }
+    T un[KU][D];
+    double acc = 0.0;
+    if constexpr (epi == EPI_RICH) {
+        T xv[KU][D];
+#pragma unroll
+        for (int u = 0; u < KU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) xv[u][c] = comp(a.x, c, npts)[pt[u]];
+        const T w = T(-a.omega);
+#pragma unroll
+        for (int u = 0; u < KU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                const T st = w * y[u][c];
+                const T xn = xv[u][c] + st;
+                un[u][c] = xn + T(a.E[c]);
+                if (ok[u]) {
+                    comp(a.x, c, npts)[pt[u]] = xn;
+                    acc += double(st) * double(st);
+                }
+            }
+    } else if constexpr (epi == EPI_CHEB) {
+        T xv[KU][D], rv[KU][D], pv[KU][D];
+#pragma unroll
+        for (int u = 0; u < KU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                const unsigned o = pt[u];
+                xv[u][c] = comp(a.x, c, npts)[o];
+                rv[u][c] = comp(a.r, c, npts)[o];
+                pv[u][c] = comp(a.p, c, npts)[o];
+            }
+        const T al = T(a.sc ? a.sc->alpha : a.alpha), be = T(a.sc ? a.sc->beta : a.beta);
+#pragma unroll
+        for (int u = 0; u < KU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                const T rn = rv[u][c] - al * y[u][c];
+                const T pn = rn - be * pv[u][c];
+                un[u][c] = pn + T(a.E[c]);
+                if (ok[u]) {
+                    const unsigned o = pt[u];
+                    comp(a.r, c, npts)[o] = rn;
+                    comp(a.x, c, npts)[o] = xv[u][c] + al * pv[u][c];
+                    comp(a.p, c, npts)[o] = pn;
+                    acc += double(rn) * double(rn);
+                }
+            }
+    } else {  // EPI_EM
+        T xv[KU][D], sv[KU][D];
+#pragma unroll
+        for (int u = 0; u < KU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                const unsigned o = pt[u];
+                xv[u][c] = comp(a.x, c, npts)[o];
+                sv[u][c] = a.src ? comp(a.src, c, npts)[o] : T(2.0 * a.omega * a.E[c]);
+            }
+        const T w = T(a.omega);
+#pragma unroll
+        for (int u = 0; u < KU; u++) {
+            T v[D];
+#pragma unroll
+            for (int c = 0; c < D; c++) v[c] = a.src ? y[u][c] : y[u][c] + sv[u][c];
+            coef_shift_solve_rt<T, D>(a.A, tabinv, w, pt[u], npts, v, un[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < KU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                if (a.src) un[u][c] += sv[u][c];
+                const T st = un[u][c] - xv[u][c];
+                if (ok[u]) {
+                    comp(a.x, c, npts)[pt[u]] = un[u][c];
+                    acc += double(st) * double(st);
+                }
+            }
+    }
+    // the next body's first pass: z = A u (Richardson, Chebyshev) or (A - w I) u (Eyre-Milton)
+    T z[KU][D];
+#pragma unroll
+    for (int u = 0; u < KU; u++) coef_mul_rt<T, D>(a.A, tab, pt[u], npts, un[u], z[u]);
+    if constexpr (epi == EPI_EM) {
+#pragma unroll
+        for (int u = 0; u < KU; u++)
+#pragma unroll
+            for (int c = 0; c < D; c++) z[u][c] -= T(a.omega) * un[u][c];
+    }
+#pragma unroll
+    for (int u = 0; u < KU; u++) {
+        const int idx = base + u * (int)blockDim.x + (int)threadIdx.x;
+        if (idx < total) {
+            const int r = idx / L;
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                const int q = r * D + c;
+                Zr[((q >> 1) * (L + 1) + at[u]) * 2 + (q & 1)] = ok[u] ? z[u][c] : T(0);
+            }
+        }
+    }
+    return acc;
+}
+
+template <typename T, int D, int L1, int L2, int epi>
+__global__ __launch_bounds__(kThreads) void k2_lastfirst(LastArgs<T> a)
+{
+    static_assert(epi == EPI_RICH || epi == EPI_CHEB || epi == EPI_EM, "pointwise updates only");
+    if (a.done && *a.done) return;
+    constexpr int L = L1 * L2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int npairs = (a.rpb * D + 1) / 2;
+    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
+    cpx<T>* Sx = tw + L;  // npairs packed rows of L + 1 slots
+    T* Zr = reinterpret_cast<T*>(Sx);
+    T* tab = reinterpret_cast<T*>(Sx + npairs * (L + 1));
+    T* tabinv = tab + kMaxPhases * 6;
+    __shared__ double red[kThreads / 64];
+    for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
+    if (a.A.kind == AK_PHASE)
+        for (int m = threadIdx.x; m < kMaxPhases * 6; m += blockDim.x) {
+            tab[m] = T(a.A.tab[m / 6][m % 6]);
+            tabinv[m] = T(a.A.tab_inv[m / 6][m % 6]);
+        }
+    const long long row0 = xcd_tile(blockIdx.x, gridDim.x) * a.rpb;
+    const int Hb = a.g.Hb;
+    const int nrows = (int)(a.g.rows - row0 < a.rpb ? a.g.rows - row0 : a.rpb);
+    {
+        // stage L as in the last pass
+        constexpr int kQ = 6;
+        const int qstep = (int)blockDim.x / Hb;
+        const int tq = (int)threadIdx.x / Hb;
+        const int k = (int)threadIdx.x - tq * Hb;
+        const int qend = nrows * D;
+        const unsigned s1 = (unsigned)a.g.s1;
+        const cpx<T>* inb = a.in + row0 * Hb;
+        if (tq < qstep)
+            for (int q0 = tq; q0 < 2 * npairs; q0 += kQ * qstep) {
+                cpx<T> v[kQ];
+#pragma unroll
+                for (int u = 0; u < kQ; u++) {
+                    const int q = q0 + u * qstep;
+                    const int r = q / D;
+                    const int c = q - r * D;
+                    const bool ok = q < qend;
+                    const unsigned off = ok ? (unsigned)c * s1 + (unsigned)(r * Hb + k) : (unsigned)k;
+                    v[u] = inb[off];
+                    if (!ok) v[u] = {T(0), T(0)};
+                }
+#pragma unroll
+                for (int u = 0; u < kQ; u++) {
+                    const int q = q0 + u * qstep;
+                    if (q < 2 * npairs) Sx[(q >> 1) * (L + 1) + (q & 1) * Hb + k] = v[u];
+                }
+            }
+    }
+    lds_barrier();
+    last_transform<T, D, L1, L2>(a, tw, Sx);
+    double acc = 0.0;
+    {
+        const int total = a.rpb * L;
+        const long long pt0 = row0 * L;
+        const long long left = a.g.rows * (long long)L - pt0;
+        const int lim = left < total ? (int)left : total;
+        constexpr int KU = (epi == EPI_CHEB || epi == EPI_EM) && ku_for(L) > 2 ? 2 : ku_for(L);
+        for (int base = 0; base < total; base += KU * blockDim.x)
+            acc += lastfirst_chunk<T, D, L, epi, KU>(a, tab, tabinv, base, total, lim, pt0, Zr);
+        if ((a.rpb * D) & 1)  // the imaginary half of the last packed row is a zero row
+            for (int i = threadIdx.x; i < L; i += blockDim.x) Sx[(npairs - 1) * (L + 1) + i].y = T(0);
+    }
+    lds_barrier();
+    first_transform_store_ip<T, D, L1, L2, L + 1>(a, row0, tw, Sx);
     const double tot = block_sum(acc, red);
     if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
 }
