@@ -388,6 +388,69 @@ void fill_opplan(fgh_plan p, OpPlan* op, bool f32)
     op->stream = p->stream;
 }
 
+// Tile width of the strided axis-1 passes (3D), measured at plan creation like the middle pass's:
+// powers of two and the widths that split the Hb columns of a half-spectrum row into equal tiles
+// (a ragged last tile leaves most of its workgroup idle).  The per-column arithmetic does not
+// depend on the width, so results are identical whatever is chosen.
+fgh_status tune_axis(fgh_plan p, OpPlan* op, bool f32)
+{
+    if (p->d != 3 || env_int("FGH_TUNE", 1) == 0 || env_int("FGH_P_EXACT", 0) != 0) return FGH_OK;
+    static std::mutex mu;
+    static std::map<std::vector<long long>, int> cache;
+    const Geo& g = op->g;
+    const std::vector<long long> key = {f32 ? 1 : 0, g.L[1], g.B[1], g.Hb, g.L[0], op->v2_axis ? 1 : 0};
+    const size_t cs = f32 ? 8 : 16;
+    const size_t L1 = (size_t)g.L[1];
+    auto lds_of = [&](int P) { return op->v2_axis ? (L1 + (size_t)P * L1) * cs : (L1 + 2 * (size_t)P * L1) * cs; };
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            op->P_axis = it->second;
+            op->lds_axis = lds_of(op->P_axis);
+            return FGH_OK;
+        }
+    }
+    std::vector<int> cand = {4, 8, 12, 16};
+    for (int P = 6; P <= 24; P++)
+        if (g.Hb % P == 0 && std::find(cand.begin(), cand.end(), P) == cand.end()) cand.push_back(P);
+    hipEvent_t e0, e1;
+    HIPOK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return FGH_E_DEVICE;
+    }
+    int best = op->P_axis;
+    float best_ms = 1e30f;
+    hipError_t err = hipSuccess;
+    for (int P : cand) {
+        if (lds_of(P) > lds_budget() || P > g.Hb) continue;
+        OpPlan o = *op;
+        o.P_axis = P;
+        o.lds_axis = lds_of(P);
+        o.prof = nullptr;
+        if ((err = f32 ? run_axis_only<float>(o) : run_axis_only<double>(o)) != hipSuccess) break;
+        if ((err = hipEventRecord(e0, o.stream)) != hipSuccess) break;
+        for (int r = 0; r < 3 && err == hipSuccess; r++) err = f32 ? run_axis_only<float>(o) : run_axis_only<double>(o);
+        if (err != hipSuccess || (err = hipEventRecord(e1, o.stream)) != hipSuccess) break;
+        if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.0f;
+        if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = P;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return FGH_E_DEVICE;
+    op->P_axis = best;
+    op->lds_axis = lds_of(best);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = best;
+    return FGH_OK;
+}
+
 // Tile width of the middle pass, measured at plan creation.  The per-column arithmetic does not
 // depend on the width (results are identical for every choice); the best width depends on how
 // the tile count meets the resident workgroups of the CUs, so a few widths are timed once per
@@ -1275,6 +1338,8 @@ fgh_status fgh_plan_create(fgh_plan* out, int d, const int32_t* N, fgh_rule rule
     if ((s = upload_twiddles(p))) return fail(s);
     if ((s = tune_middle(p, &p->op64, false))) return fail(s);
     if (precision == FGH_FP32_REFINED && (s = tune_middle(p, &p->op32, true))) return fail(s);
+    if ((s = tune_axis(p, &p->op64, false))) return fail(s);
+    if (precision == FGH_FP32_REFINED && (s = tune_axis(p, &p->op32, true))) return fail(s);
     if ((s = tune_first(p, &p->op64, false, p->r64))) return fail(s);
     if (precision == FGH_FP32_REFINED && (s = tune_first(p, &p->op32, true, p->r32))) return fail(s);
 

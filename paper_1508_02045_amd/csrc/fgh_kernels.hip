@@ -1302,6 +1302,33 @@ template hipError_t run_middle_only<double>(const OpPlan&);
 template hipError_t run_middle_only<float>(const OpPlan&);
 
 template <typename T>
+hipError_t run_axis_only(const OpPlan& op)
+{
+    const Geo& g = op.g;
+    if (g.d != 3) return hipErrorInvalidValue;
+    AxisArgs<T> xa;
+    xa.ax = op.ax[1];
+    xa.nin = g.L[1];
+    xa.nout = g.B[1];
+    xa.bin = 0;
+    xa.bout = 1;
+    xa.inner = g.Hb;
+    xa.P = op.P_axis;
+    xa.ntiles = (g.Hb + op.P_axis - 1) / op.P_axis;
+    xa.in_os = (long long)g.L[1] * g.Hb;
+    xa.out_os = (long long)g.B[1] * g.Hb;
+    xa.in_cs = g.s1;
+    xa.out_cs = g.s2;
+    xa.in = static_cast<cpx<T>*>(op.SA);
+    xa.out = static_cast<cpx<T>*>(op.SB);
+    xa.twg = static_cast<const cpx<T>*>(op.tw[1]);
+    xa.done = nullptr;
+    return op.v2_axis ? v2_axis<T>(op, xa, false, g.L[0], g.B[1]) : launch_axis<T>(op, xa, false, g.L[0]);
+}
+template hipError_t run_axis_only<double>(const OpPlan&);
+template hipError_t run_axis_only<float>(const OpPlan&);
+
+template <typename T>
 hipError_t run_first_only(const OpPlan& op, const T* x)
 {
     const Geo& g = op.g;

@@ -102,6 +102,11 @@ hipError_t run_reduce(const OpPlan& op, int n, int redop, double* host_out);
 template <typename T>
 hipError_t run_middle_only(const OpPlan& op);
 
+// The forward axis-1 pass alone (3D) from the first into the second spectrum buffer (tile-width
+// tuning at plan creation; the second buffer's contents are overwritten).
+template <typename T>
+hipError_t run_axis_only(const OpPlan& op);
+
 // The first pass alone (identity operator) from the vector x into the plan's first spectrum
 // buffer (tile tuning at plan creation).
 template <typename T>

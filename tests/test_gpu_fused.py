@@ -1,0 +1,61 @@
+"""Fused loop bodies: for Richardson, Chebyshev and Eyre-Milton the last pass also runs the next
+body's first pass (the update is pointwise, so the next operand is known where it is computed).
+The arithmetic is unchanged, so iterates, iteration counts and A_H must be bitwise identical to
+the unfused loop (FGH_FUSE=0), in FP64 and in the FP32 inner solves of defect correction, for
+lengths with specialised row kernels in 2D and 3D, with ragged last tiles."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1508_02045_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1508_02045_amd import fgh
+    fgh.lib()
+
+
+def F():
+    from paper_1508_02045_amd import fgh as m
+    return m
+
+
+def solve_both(plan, solver, E, tol):
+    out = []
+    for fuse in ("0", "1"):
+        os.environ["FGH_FUSE"] = fuse
+        try:
+            e, st, stats = plan.solve(solver, E, tol, max_iter=20000)
+        finally:
+            os.environ.pop("FGH_FUSE", None)
+        assert st == 0, stats
+        out.append((e.cpu().numpy(), stats[0]))
+    return out
+
+
+# FP32 refinement runs Chebyshev and Eyre-Milton inner solves (Richardson is not offered there)
+CASES = [(s, N, 0) for s in ("richardson", "chebyshev", "eyre_milton") for N in ((45, 63, 81), (125, 45))] + \
+        [(s, (81, 45, 63), 1) for s in ("chebyshev", "eyre_milton")]
+
+
+@pytest.mark.parametrize("solver,N,prec", CASES)
+def test_fused_equals_unfused(solver, N, prec):
+    m = F()
+    d = len(N)
+    rng = np.random.default_rng(sum(N))
+    ph, _, _ = I.boolean_spheres(N, 4.0, 0.3, rng)
+    tab = np.stack([I.sym_pack(t[None])[:, 0] for t in I.iso_tables(d, [1.0, 30.0])])
+    plan = m.Plan(N, precision=prec, phase=torch.from_numpy(ph).cuda(), phase_table=tab)
+    E = np.array([1.0, -0.5, 0.25][:d])
+    print(f"fused vs unfused {solver} N={N} precision={prec}", flush=True)
+    (e0, s0), (e1, s1) = solve_both(plan, solver, E, 1e-8)
+    assert s0["iters"] == s1["iters"] and s0["outer_iters"] == s1["outer_iters"]
+    assert np.array_equal(e0, e1)
