@@ -418,8 +418,19 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ 
     __shared__ double red[kThreads / 64];
     const bool in_loop = op == RED_CG_ALPHA || op == RED_CG_END || op == RED_STEP_END || op == RED_CHEB_END;
     if (in_loop && s->done) return;
+    // each thread sums its partials in index order; loads are issued eight at a time so that one
+    // memory latency covers eight of them
     double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) v += partials[i];
+    const int bd = (int)blockDim.x;
+    int i = threadIdx.x;
+    for (; i + 7 * bd < n; i += 8 * bd) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) t[u] = partials[i + u * bd];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v += t[u];
+    }
+    for (; i < n; i += bd) v += partials[i];
     const double tot = block_sum(v, red);
     if (threadIdx.x == 0) {
         s->total = tot;
@@ -488,7 +499,30 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(long long n, T* __restri
     if (s->done) return;
     const T alpha = T(s->alpha);
     double acc = 0.0;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    // four grid-strided points per batch, all loads issued before any use (one memory latency per
+    // batch); each thread still visits its points in increasing order
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        T xv[4], pv[4], rv[4], qv[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const long long j = i + u * stride;
+            xv[u] = x[j];
+            pv[u] = p[j];
+            rv[u] = r[j];
+            qv[u] = q[j];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const long long j = i + u * stride;
+            x[j] = xv[u] + alpha * pv[u];
+            const T rn = rv[u] - alpha * qv[u];
+            r[j] = rn;
+            acc += double(rn) * double(rn);
+        }
+    }
+    for (; i < n; i += stride) {
         x[i] += alpha * p[i];
         const T rv = r[i] - alpha * q[i];
         r[i] = rv;
