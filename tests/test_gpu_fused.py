@@ -28,14 +28,14 @@ def F():
     return m
 
 
-def solve_both(plan, solver, E, tol):
+def solve_both(plan, solver, E, tol, switch="FGH_FUSE"):
     out = []
-    for fuse in ("0", "1"):
-        os.environ["FGH_FUSE"] = fuse
+    for on in ("0", "1"):
+        os.environ[switch] = on
         try:
             e, st, stats = plan.solve(solver, E, tol, max_iter=20000)
         finally:
-            os.environ.pop("FGH_FUSE", None)
+            os.environ.pop(switch, None)
         assert st == 0, stats
         out.append((e.cpu().numpy(), stats[0]))
     return out
@@ -59,3 +59,4 @@ def test_fused_equals_unfused(solver, N, prec):
     (e0, s0), (e1, s1) = solve_both(plan, solver, E, 1e-8)
     assert s0["iters"] == s1["iters"] and s0["outer_iters"] == s1["outer_iters"]
     assert np.array_equal(e0, e1)
+
