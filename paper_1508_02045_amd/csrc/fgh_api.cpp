@@ -423,6 +423,8 @@ fgh_status tune_axis(fgh_plan p, OpPlan* op, bool f32)
     int best = op->P_axis;
     float best_ms = 1e30f;
     hipError_t err = hipSuccess;
+    // two rounds over the candidates: the fastest single timing wins (robust to a noisy first round)
+    for (int round = 0; round < 2 && err == hipSuccess; round++)
     for (int P : cand) {
         if (lds_of(P) > lds_budget() || P > g.Hb) continue;
         OpPlan o = *op;
@@ -484,6 +486,7 @@ fgh_status tune_middle(fgh_plan p, OpPlan* op, bool f32)
     int best = op->P_mid, best_pad = 0;
     float best_ms = 1e30f;
     hipError_t err = hipSuccess;
+    for (int round = 0; round < 2 && err == hipSuccess; round++)
     for (int pad = 0; pad < 2 && err == hipSuccess; pad++)
         for (int P : cand) {
             if (lds_of(P, pad) > 128 * 1024 || P > g.cols_mid) continue;
@@ -551,6 +554,7 @@ fgh_status tune_first(fgh_plan p, OpPlan* op, bool f32, const void* x)
     int best = op->rpb_first;
     float best_ms = 1e30f;
     hipError_t err = hipSuccess;
+    for (int round = 0; round < 2 && err == hipSuccess; round++)
     for (int r : cand) {
         if (lds_of(r) > 128 * 1024 || r > g.rows) continue;
         OpPlan o = *op;

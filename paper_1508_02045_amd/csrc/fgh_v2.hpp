@@ -1096,7 +1096,7 @@ __global__ __launch_bounds__(kThreads) void k2_lastfirst(LastArgs<T> a)
         const long long pt0 = row0 * L;
         const long long left = a.g.rows * (long long)L - pt0;
         const int lim = left < total ? (int)left : total;
-        constexpr int KU = (epi == EPI_CHEB || epi == EPI_EM) && ku_for(L) > 2 ? 2 : ku_for(L);
+        constexpr int KU = epi == EPI_RICH ? (ku_for(L) > 3 ? 3 : ku_for(L)) : (ku_for(L) > 2 ? 2 : ku_for(L));
         for (int base = 0; base < total; base += KU * blockDim.x)
             acc += lastfirst_chunk<T, D, L, epi, KU>(a, tab, tabinv, base, total, lim, pt0, Zr);
         if ((a.rpb * D) & 1)  // the imaginary half of the last packed row is a zero row
