@@ -675,14 +675,6 @@ __device__ __forceinline__ void middle_body(const MidArgs<T>& a)
         const int k2 = job / P;
         const int p = job - k2 * P;
         const int j = tile * P + p;
-        cpx<T> s[D][L1];
-#pragma unroll
-        for (int c = 0; c < D; c++) {
-            const cpx<T>* y = Y + c * PL + p * YS + k2;
-#pragma unroll
-            for (int n1 = 0; n1 < L1; n1++) s[c][n1] = y[n1 * L2];
-            reg_dft<T, L1, false>(s[c]);
-        }
         int kv1 = 0, kv2 = 0;
         if (D == 2) {
             kv1 = j;
@@ -694,36 +686,92 @@ __device__ __forceinline__ void middle_body(const MidArgs<T>& a)
         const bool colok = j < a.cols;
         // |k|^2 is an integer below 2^24 at these lengths, exact in T
         const T kperp = T(kv1 * kv1 + kv2 * kv2);
+        if constexpr (MULT == MULT_G) {
+            // G^ is rank one per frequency, (G^ z)_c = k_c t with t = k.z / |k|^2, and along this
+            // column only k_0 varies: the components c >= 1 enter through sum_c k_c z_c on the way
+            // in and leave as k_c times one inverse transform of t.  Two forward and two inverse
+            // L1-point DFTs instead of D of each.
+            cpx<T> z0[L1], zp[L1];
+            {
+                const cpx<T>* y = Y + p * YS + k2;
 #pragma unroll
-        for (int k1 = 0; k1 < L1; k1++) {
-            const int pos = k2 + L2 * k1;
-            const int k0 = signed_index(pos, L);
-            const bool inband = colok && (2 * (k0 < 0 ? -k0 : k0) < a.B0);
-            const T kk = T(k0 * k0) + kperp;
-            // w = scale / |k|^2, and 0 at k = 0 (G^ vanishes, I - 2G^ is the identity) and outside
-            // the band (Ga; Eyre-Milton runs on the GaNi grid only, where every k is in the band)
-            const T w = (inband && kk > T(0)) ? scale * recip_int(kk) : T(0);
-            const T kvec[3] = {T(k0), T(kv1), T(kv2)};
-            cpx<T> kz = {T(0), T(0)};
-#pragma unroll
-            for (int c = 0; c < D; c++) kz = kz + kvec[c] * s[c][k1];
-            const cpx<T> wkz = w * kz;
-#pragma unroll
-            for (int c = 0; c < D; c++) {
-                const cpx<T> gz = kvec[c] * wkz;  // scale G^ z
-                s[c][k1] = (MULT == MULT_G) ? gz : scale * s[c][k1] - T(2) * gz;
+                for (int n1 = 0; n1 < L1; n1++) z0[n1] = y[n1 * L2];
             }
-        }
 #pragma unroll
-        for (int c = 0; c < D; c++) {
-            reg_dft<T, L1, true>(s[c]);
-            cpx<T>* y = Y + c * PL + p * YS + k2;
+            for (int n1 = 0; n1 < L1; n1++) zp[n1] = {T(0), T(0)};
+#pragma unroll
+            for (int c = 1; c < D; c++) {
+                const T kc = T(c == 1 ? kv1 : kv2);
+                const cpx<T>* y = Y + c * PL + p * YS + k2;
+#pragma unroll
+                for (int n1 = 0; n1 < L1; n1++) zp[n1] = zp[n1] + kc * y[n1 * L2];
+            }
+            reg_dft<T, L1, false>(z0);
+            reg_dft<T, L1, false>(zp);
+#pragma unroll
+            for (int k1 = 0; k1 < L1; k1++) {
+                const int pos = k2 + L2 * k1;
+                const int k0 = signed_index(pos, L);
+                const bool inband = colok && (2 * (k0 < 0 ? -k0 : k0) < a.B0);
+                const T kk = T(k0 * k0) + kperp;
+                // w = scale / |k|^2, and 0 at k = 0 (G^ vanishes there) and outside the band (Ga)
+                const T w = (inband && kk > T(0)) ? scale * recip_int(kk) : T(0);
+                const cpx<T> t = w * (T(k0) * z0[k1] + zp[k1]);
+                zp[k1] = t;
+                z0[k1] = T(k0) * t;
+            }
+            reg_dft<T, L1, true>(z0);
+            reg_dft<T, L1, true>(zp);
+            cpx<T>* y = Y + p * YS + k2;
             int m = 0;
 #pragma unroll
             for (int n1 = 0; n1 < L1; n1++) {
-                y[n1 * L2] = n1 ? cmul(s[c][n1], conj(tw[m])) : s[c][n1];
+                const cpx<T> tw_n = conj(tw[m]);
+                const cpx<T> v0 = n1 ? cmul(z0[n1], tw_n) : z0[n1];
+                const cpx<T> vt = n1 ? cmul(zp[n1], tw_n) : zp[n1];
+                y[n1 * L2] = v0;
+                y[PL + n1 * L2] = T(kv1) * vt;
+                if (D == 3) y[2 * PL + n1 * L2] = T(kv2) * vt;
                 m += k2;
                 if (m >= L) m -= L;
+            }
+        } else {
+            cpx<T> s[D][L1];
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                const cpx<T>* y = Y + c * PL + p * YS + k2;
+#pragma unroll
+                for (int n1 = 0; n1 < L1; n1++) s[c][n1] = y[n1 * L2];
+                reg_dft<T, L1, false>(s[c]);
+            }
+#pragma unroll
+            for (int k1 = 0; k1 < L1; k1++) {
+                const int pos = k2 + L2 * k1;
+                const int k0 = signed_index(pos, L);
+                const bool inband = colok && (2 * (k0 < 0 ? -k0 : k0) < a.B0);
+                const T kk = T(k0 * k0) + kperp;
+                // w = scale / |k|^2, and 0 at k = 0 (I - 2G^ is the identity there); Eyre-Milton
+                // runs on the GaNi grid only, where every k is in the band
+                const T w = (inband && kk > T(0)) ? scale * recip_int(kk) : T(0);
+                const T kvec[3] = {T(k0), T(kv1), T(kv2)};
+                cpx<T> kz = {T(0), T(0)};
+#pragma unroll
+                for (int c = 0; c < D; c++) kz = kz + kvec[c] * s[c][k1];
+                const cpx<T> wkz = w * kz;
+#pragma unroll
+                for (int c = 0; c < D; c++) s[c][k1] = scale * s[c][k1] - T(2) * (kvec[c] * wkz);
+            }
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                reg_dft<T, L1, true>(s[c]);
+                cpx<T>* y = Y + c * PL + p * YS + k2;
+                int m = 0;
+#pragma unroll
+                for (int n1 = 0; n1 < L1; n1++) {
+                    y[n1 * L2] = n1 ? cmul(s[c][n1], conj(tw[m])) : s[c][n1];
+                    m += k2;
+                    if (m >= L) m -= L;
+                }
             }
         }
     }
