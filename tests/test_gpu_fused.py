@@ -60,3 +60,21 @@ def test_fused_equals_unfused(solver, N, prec):
     assert s0["iters"] == s1["iters"] and s0["outer_iters"] == s1["outer_iters"]
     assert np.array_equal(e0, e1)
 
+
+
+@pytest.mark.parametrize("solver", ["richardson", "chebyshev"])
+@pytest.mark.parametrize("N", [(23, 23, 23), (41, 63)])
+def test_fused_equals_unfused_ga(solver, N):
+    """Exact integration on the double grid 2N - 1 (45^3; 81 x 125): the fused bodies run on the
+    double-grid coefficients A_{2N-1} there, with the band-limited projection."""
+    m = F()
+    d = len(N)
+    rng = np.random.default_rng(sum(N) + 7)
+    ph = (rng.uniform(size=N) < 0.35).astype(np.uint8)
+    tab = np.stack([I.sym_pack(t[None])[:, 0] for t in I.iso_tables(d, [1.0, 20.0])])
+    plan = m.Plan(N, rule=m.FGH_GA, phase=torch.from_numpy(ph).cuda(), phase_table=tab)
+    E = np.array([1.0, -0.5, 0.25][:d])
+    print(f"fused vs unfused Ga {solver} N={N}", flush=True)
+    (e0, s0), (e1, s1) = solve_both(plan, solver, E, 1e-8)
+    assert s0["iters"] == s1["iters"]
+    assert np.array_equal(e0, e1)
