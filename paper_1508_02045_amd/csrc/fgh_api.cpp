@@ -795,6 +795,15 @@ bool fuse_loop(fgh_plan p, const OpPlan& op)
     return fusable(op) && !p->hist_fn && !(v && v[0] == '0');
 }
 
+// Deferred loop reductions (see ApplyArgs::defer_redop): with fused bodies in 3D with the
+// specialised axis kernels.  The host then sees a body's stopping test one body later, so a loop
+// may launch one more chunk of bodies that return at once.  FGH_DEFER=0 turns this off.
+bool defer_reduction(const OpPlan& op, bool fuse)
+{
+    const char* v = std::getenv("FGH_DEFER");
+    return fuse && op.g.d == 3 && op.v2_axis && op.v2_row && !(v && v[0] == '0');
+}
+
 // The loop's prologue of a fused loop: the first body's first pass alone.
 template <typename T>
 hipError_t fused_prologue(const OpPlan& op, ApplyArgs a)
@@ -840,13 +849,15 @@ fgh_status cheb_core(fgh_plan p, T* x, T* r, T* pv, double tol_rel, int max_iter
         a.skip_first = true;
         a.next_op = OP_AX;
     }
+    const bool defer = defer_reduction(op, fuse);
+    a.defer_redop = defer ? RED_CHEB_END : -1;
     auto body = [&]() -> hipError_t {
         int nb = 0;
         hipError_t e = run_apply<T>(op, a, &nb);
-        if (e != hipSuccess) return e;
+        if (e != hipSuccess || defer) return e;
         return run_reduce_async(op, nb, RED_CHEB_END);
     };
-    const uint64_t key = key_of({2, sizeof(T), bits(x), bits(r), bits(pv), (uint64_t)fuse});
+    const uint64_t key = key_of({2, sizeof(T), bits(x), bits(r), bits(pv), (uint64_t)fuse, (uint64_t)defer});
     return run_loop(p, op, body, key, fixed > 0, normb, out);
 }
 
@@ -874,14 +885,16 @@ fgh_status rich_core(fgh_plan p, T* x, const double* E0, double thr, int max_ite
         a.skip_first = true;
         a.next_op = OP_AX;
     }
+    const bool defer = defer_reduction(op, fuse);
+    a.defer_redop = defer ? RED_STEP_END : -1;
     auto body = [&]() -> hipError_t {
         int nb = 0;
         hipError_t e = run_apply<T>(op, a, &nb);
-        if (e != hipSuccess) return e;
+        if (e != hipSuccess || defer) return e;
         return run_reduce_async(op, nb, RED_STEP_END);
     };
     const uint64_t key = key_of({3, sizeof(T), bits(x), bits(E0[0]), bits(E0[1]), bits(p->d == 3 ? E0[2] : 0.0),
-                                 bits(omega), (uint64_t)fuse});
+                                 bits(omega), (uint64_t)fuse, (uint64_t)defer});
     return run_loop(p, op, body, key, fixed > 0, scale, out);
 }
 
@@ -913,14 +926,16 @@ fgh_status em_core(fgh_plan p, T* x, const double* E, const T* src, double thr, 
         a.skip_first = true;
         a.next_op = OP_EM;
     }
+    const bool defer = defer_reduction(op, fuse);
+    a.defer_redop = defer ? RED_STEP_END : -1;
     auto body = [&]() -> hipError_t {
         int nb = 0;
         hipError_t e = run_apply<T>(op, a, &nb);
-        if (e != hipSuccess) return e;
+        if (e != hipSuccess || defer) return e;
         return run_reduce_async(op, nb, RED_STEP_END);
     };
     const uint64_t key = key_of({4, sizeof(T), bits(x), bits(src), bits(E[0]), bits(E[1]),
-                                 bits(p->d == 3 ? E[2] : 0.0), bits(omega), (uint64_t)fuse});
+                                 bits(p->d == 3 ? E[2] : 0.0), bits(omega), (uint64_t)fuse, (uint64_t)defer});
     return run_loop(p, op, body, key, fixed > 0, scale, out);
 }
 

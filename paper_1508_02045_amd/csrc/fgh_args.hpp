@@ -107,6 +107,8 @@ struct AxisArgs {
     const cpx<T>* in;
     cpx<T>* out;
     const cpx<T>* twg;
+    Scalars* red_sc;          // non-null: workgroup 0 completes a deferred loop reduction first
+    const double* partials;
 };
 
 template <typename T>
@@ -141,6 +143,8 @@ struct LastArgs {
     double* partials;
     const cpx<T>* twg;
     cpx<T>* out;    // fused last + first pass: the next body's first spectrum (rows of this tile)
+    Scalars* defer_sc;  // non-null: the loop reduction redop of these partials is left to the next body
+    int redop;
 };
 
 }  // namespace fgh

@@ -86,7 +86,8 @@ struct Scalars {
     int done;           // 0 running, 1 stopping test met, 2 iteration cap, 3 diverged
     int m;              // loop bodies executed
     int limit;          // cap on m
-    int pad;
+    int pend_n;         // partial sums of a loop reduction deferred to the next body (0: none)
+    int pend_op;        //   and its RedOp
     double aux[40];     // [0, 16): loads for fgh_effective; [16, 40): multi-value reductions
 };
 

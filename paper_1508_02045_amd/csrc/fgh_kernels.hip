@@ -400,60 +400,13 @@ __global__ __launch_bounds__(kThreads) void k_last(LastArgs<T> a)
 // ------------------------------------------------------------------------------------------
 // Reductions and vector kernels.
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ void end_body(Scalars* s, double v)
-{
-    s->m += 1;
-    const double q = sqrt(v / s->npts);
-    s->last = q;
-    if (!(v == v) || v > 1.0e300 || (s->blowup > 0.0 && q > s->blowup))
-        s->done = 3;
-    else if (s->thr >= 0.0 && q <= s->thr)
-        s->done = 1;
-    else if (s->m >= s->limit)
-        s->done = 2;
-}
-
 __global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ partials, int n, Scalars* s, int op)
 {
     __shared__ double red[kThreads / 64];
     const bool in_loop = op == RED_CG_ALPHA || op == RED_CG_END || op == RED_STEP_END || op == RED_CHEB_END;
     if (in_loop && s->done) return;
-    // each thread sums its partials in index order; loads are issued eight at a time so that one
-    // memory latency covers eight of them
-    double v = 0.0;
-    const int bd = (int)blockDim.x;
-    int i = threadIdx.x;
-    for (; i + 7 * bd < n; i += 8 * bd) {
-        double t[8];
-#pragma unroll
-        for (int u = 0; u < 8; u++) t[u] = partials[i + u * bd];
-#pragma unroll
-        for (int u = 0; u < 8; u++) v += t[u];
-    }
-    for (; i < n; i += bd) v += partials[i];
-    const double tot = block_sum(v, red);
-    if (threadIdx.x == 0) {
-        s->total = tot;
-        if (op == RED_CG_ALPHA) {
-            s->qp = tot;
-            s->alpha = s->rr / tot;
-        } else if (op == RED_CG_END) {
-            s->rr_new = tot;
-            s->beta = tot / s->rr;
-            s->rr = tot;
-            end_body(s, tot);
-        } else if (op == RED_SET_RR) {
-            s->rr = tot;
-        } else if (op == RED_STEP_END) {
-            end_body(s, tot);
-        } else if (op == RED_CHEB_END) {
-            end_body(s, tot);
-            // Algorithm 3: alpha, beta of the next body
-            const double al = 1.0 / (s->cheb_delta + s->beta / s->alpha);
-            s->alpha = al;
-            s->beta = -(s->cheb_c * al * 0.5) * (s->cheb_c * al * 0.5);
-        }
-    }
+    const double tot = block_sum(sum_partials(partials, n), red);
+    if (threadIdx.x == 0) apply_redop(s, op, tot);
 }
 
 // Start a solver loop: m = 0, done = 0 and the loop's constants (no memset: a plain kernel).
@@ -472,6 +425,7 @@ __global__ void k_init_loop(Scalars* s, double rr, double alpha, double beta, do
     s->m = 0;
     s->limit = limit;
     s->last = 0.0;
+    s->pend_n = 0;
 }
 
 // Reduce nvals interleaved partial sums [nblocks][nvals] (fixed order).
@@ -1230,7 +1184,7 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
 
     cpx<T>* mid = SA;
     if (D == 3) {
-        AxisArgs<T> xa;
+        AxisArgs<T> xa{};
         xa.ax = op.ax[1];
         xa.nin = g.L[1];
         xa.nout = g.B[1];
@@ -1247,6 +1201,9 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
         xa.out = SB;
         xa.twg = static_cast<const cpx<T>*>(op.tw[1]);
         xa.done = done;
+        // the previous body's deferred loop reduction is completed by this pass's first workgroup
+        xa.red_sc = a.defer_redop >= 0 ? op.sc : nullptr;
+        xa.partials = op.partials;
         const bool prof_PK_AXIS_FWD = op.prof && op.prof->wants(PK_AXIS_FWD);
         if (prof_PK_AXIS_FWD && (e = op.prof->begin(PK_AXIS_FWD)) != hipSuccess) return e;
         if ((e = op.v2_axis ? v2_axis<T>(op, xa, false, g.L[0], g.B[1]) : launch_axis<T>(op, xa, false, g.L[0])) != hipSuccess)
@@ -1262,7 +1219,7 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     if (prof_PK_MIDDLE && (e = op.prof->end()) != hipSuccess) return e;
 
     if (D == 3) {
-        AxisArgs<T> xa;
+        AxisArgs<T> xa{};
         xa.ax = op.ax[1];
         xa.nin = g.B[1];
         xa.nout = g.L[1];
@@ -1286,7 +1243,7 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
         if (prof_PK_AXIS_INV && (e = op.prof->end()) != hipSuccess) return e;
     }
 
-    LastArgs<T> la;
+    LastArgs<T> la{};
     la.g = g;
     la.ax = op.ax[last];
     la.rpb = op.rpb;
@@ -1309,6 +1266,9 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     la.done = done;
     la.sc = a.cheb_dev ? op.sc : nullptr;
     la.out = SA;
+    if (a.defer_redop >= 0 && !(D == 3 && op.v2_axis && op.v2_row)) return hipErrorInvalidValue;
+    la.defer_sc = a.defer_redop >= 0 ? op.sc : nullptr;
+    la.redop = a.defer_redop;
     const bool fused = a.next_op >= 0;
     if (fused && (!fusable(op) || a.next_op != (a.epi == EPI_EM ? OP_EM : OP_AX) ||
                   (a.epi != EPI_RICH && a.epi != EPI_CHEB && a.epi != EPI_EM)))
@@ -1340,7 +1300,7 @@ hipError_t run_axis_only(const OpPlan& op)
 {
     const Geo& g = op.g;
     if (g.d != 3) return hipErrorInvalidValue;
-    AxisArgs<T> xa;
+    AxisArgs<T> xa{};
     xa.ax = op.ax[1];
     xa.nin = g.L[1];
     xa.nout = g.B[1];

@@ -87,6 +87,10 @@ struct ApplyArgs {
     int next_op = -1;
     bool skip_first = false;
     bool first_only = false;
+    // >= 0 (3D, specialised row and axis kernels): the loop reduction (RedOp) of this body's last
+    // pass is left to the first workgroup of the next body's forward axis pass, which replaces
+    // the separate single-block reduction launch
+    int defer_redop = -1;
 };
 
 // Whether the plan's last pass can run the next body's first pass (see ApplyArgs::next_op).

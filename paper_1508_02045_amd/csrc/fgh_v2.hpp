@@ -33,6 +33,77 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+__device__ __forceinline__ void end_body(Scalars* s, double v)
+{
+    s->m += 1;
+    const double q = sqrt(v / s->npts);
+    s->last = q;
+    if (!(v == v) || v > 1.0e300 || (s->blowup > 0.0 && q > s->blowup))
+        s->done = 3;
+    else if (s->thr >= 0.0 && q <= s->thr)
+        s->done = 1;
+    else if (s->m >= s->limit)
+        s->done = 2;
+}
+
+// The scalar update that ends a loop reduction (RedOp) from its total.
+__device__ __forceinline__ void apply_redop(Scalars* s, int op, double tot)
+{
+    s->total = tot;
+    if (op == RED_CG_ALPHA) {
+        s->qp = tot;
+        s->alpha = s->rr / tot;
+    } else if (op == RED_CG_END) {
+        s->rr_new = tot;
+        s->beta = tot / s->rr;
+        s->rr = tot;
+        end_body(s, tot);
+    } else if (op == RED_SET_RR) {
+        s->rr = tot;
+    } else if (op == RED_STEP_END) {
+        end_body(s, tot);
+    } else if (op == RED_CHEB_END) {
+        end_body(s, tot);
+        // Algorithm 3: alpha, beta of the next body
+        const double al = 1.0 / (s->cheb_delta + s->beta / s->alpha);
+        s->alpha = al;
+        s->beta = -(s->cheb_c * al * 0.5) * (s->cheb_c * al * 0.5);
+    }
+}
+
+// This thread's share of n partial sums, in index order (thread t sums t, t + blockDim, ...);
+// loads are issued eight at a time so that one memory latency covers eight of them.
+__device__ __forceinline__ double sum_partials(const double* partials, int n)
+{
+    double v = 0.0;
+    const int bd = (int)blockDim.x;
+    int i = threadIdx.x;
+    for (; i + 7 * bd < n; i += 8 * bd) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) t[u] = partials[i + u * bd];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v += t[u];
+    }
+    for (; i < n; i += bd) v += partials[i];
+    return v;
+}
+
+// A loop reduction deferred by the last pass of the previous body (Scalars::pend_n partial sums)
+// is completed by the first workgroup of the next body's first kernel: the partials were written
+// by an earlier kernel, so no fence or counter is needed.  Same summation order and scalar update
+// as the separate reduction kernel.  All threads of the workgroup call this.
+__device__ __forceinline__ void finish_deferred(Scalars* s, const double* partials, double* red)
+{
+    const int n = s->pend_n;
+    if (n == 0) return;
+    const double tot = block_sum(sum_partials(partials, n), red);
+    if (threadIdx.x == 0) {
+        apply_redop(s, s->pend_op, tot);
+        s->pend_n = 0;
+    }
+}
+
 constexpr int smallest_factor(int n)
 {
     for (int p = 2; p * p <= n; p++)
@@ -568,6 +639,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
 template <typename T, int L1, int L2, bool INV>
 __global__ __launch_bounds__(kThreads) void k2_axis(AxisArgs<T> a, int B)
 {
+    if (a.red_sc && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) {
+        __shared__ double red[kThreads / 64];
+        finish_deferred(a.red_sc, a.partials, red);
+    }
     if (a.done && *a.done) return;
     constexpr int L = L1 * L2;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -944,6 +1019,10 @@ __global__ __launch_bounds__(kThreads) void k2_last(LastArgs<T> a)
     const double acc = last_epilogue_tile<T, D, L, epi>(a, tab, row0, Zr);
     const double tot = block_sum(acc, red);
     if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
+    if (a.defer_sc && blockIdx.x == 0 && threadIdx.x == 0) {
+        a.defer_sc->pend_n = (int)gridDim.x;
+        a.defer_sc->pend_op = a.redop;
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1154,6 +1233,10 @@ __global__ __launch_bounds__(kThreads) void k2_lastfirst(LastArgs<T> a)
     first_transform_store_ip<T, D, L1, L2, L + 1>(a, row0, tw, Sx);
     const double tot = block_sum(acc, red);
     if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
+    if (a.defer_sc && blockIdx.x == 0 && threadIdx.x == 0) {
+        a.defer_sc->pend_n = (int)gridDim.x;
+        a.defer_sc->pend_op = a.redop;
+    }
 }
 
 // Lengths with specialised kernels; their splits L = L1 * L2 (L1 = 5, 7 or 9: the middle pass holds

@@ -78,3 +78,37 @@ def test_fused_equals_unfused_ga(solver, N):
     (e0, s0), (e1, s1) = solve_both(plan, solver, E, 1e-8)
     assert s0["iters"] == s1["iters"]
     assert np.array_equal(e0, e1)
+
+
+@pytest.mark.parametrize("solver,N,prec", [("richardson", (45, 63, 81), 0), ("chebyshev", (63, 45, 81), 0),
+                                           ("eyre_milton", (45, 63, 81), 0), ("chebyshev", (81, 45, 63), 1),
+                                           ("eyre_milton", (81, 45, 63), 1)])
+def test_deferred_reduction_equals_separate(solver, N, prec):
+    """In 3D the loop reduction of a fused body is completed by the first workgroup of the next
+    body's forward axis pass instead of a separate launch (FGH_DEFER=0): same partials, same
+    summation order, same stopping decisions and iterates."""
+    m = F()
+    d = len(N)
+    rng = np.random.default_rng(sum(N) + 3)
+    ph, _, _ = I.boolean_spheres(N, 4.0, 0.3, rng)
+    tab = np.stack([I.sym_pack(t[None])[:, 0] for t in I.iso_tables(d, [1.0, 30.0])])
+    plan = m.Plan(N, precision=prec, phase=torch.from_numpy(ph).cuda(), phase_table=tab)
+    E = np.array([1.0, -0.5, 0.25][:d])
+    print(f"deferred vs separate reduction {solver} N={N} precision={prec}", flush=True)
+    (e0, s0), (e1, s1) = solve_both(plan, solver, E, 1e-8, switch="FGH_DEFER")
+    assert s0["iters"] == s1["iters"] and s0["outer_iters"] == s1["outer_iters"]
+    assert s0["rel_res_recursive"] == s1["rel_res_recursive"]
+    assert np.array_equal(e0, e1)
+    if prec != 0:
+        return  # fixed-count solves are FP64 only
+    # a fixed number of bodies ends with the same count and iterate
+    f0, f1 = [], []
+    for on, out in (("0", f0), ("1", f1)):
+        os.environ["FGH_DEFER"] = on
+        try:
+            e, st, stats = plan.solve_fixed(solver, E, 7)
+        finally:
+            os.environ.pop("FGH_DEFER", None)
+        assert st == 0
+        out.append((e.cpu().numpy(), stats[0]["iters"]))
+    assert f0[0][1] == f1[0][1] == 7 and np.array_equal(f0[0][0], f1[0][0])
