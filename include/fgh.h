@@ -149,8 +149,9 @@ fgh_status fgh_ga_coefficients(fgh_plan plan, double* out);
  * (inner bodies per outer step for FGH_FP32_REFINED).  stats: host fgh_stats[nrhs] or NULL.
  * FGH_FP32_REFINED: outer FP64 residual r = b - C x, inner FP32 solve of C delta = r to the
  * relative tolerance max(tol_abs/||r||, 1e-4) by the same solver, then x += G delta in FP64;
- * stops on the true FP64 residual ||b - C x|| <= tol ||b|| (Richardson, CG, Chebyshev) or on
- * the outer step norm (Eyre-Milton).  Blocks until done.  Returns the worst load status. */
+ * stops on the true FP64 residual ||b - C x|| <= tol ||b|| (CG, Chebyshev) or on the outer
+ * step norm (Eyre-Milton); Richardson is not offered there (FGH_E_UNSUPPORTED).  Blocks until
+ * done.  Returns the worst load status. */
 fgh_status fgh_solve(fgh_plan plan, fgh_solver solver, const double* E, int nrhs, double tol,
                      int max_iter, double* e, fgh_stats* stats);
 
