@@ -378,6 +378,8 @@ void fill_opplan(fgh_plan p, OpPlan* op, bool f32)
     op->lds_first = c.lds_first;
     op->lds_first_v2 = c.lds_first_v2;
     op->lds_last_v2 = c.lds_last_v2;
+    op->rpb_fused = c.rpb;
+    op->lds_fused = c.lds_last_v2 + kMaxPhases * 6 * (f32 ? 4 : 8);
     op->lds_axis = c.lds_axis;
     op->lds_mid = c.lds_mid;
     op->v2_row = c.v2_row;
@@ -583,6 +585,74 @@ fgh_status tune_first(fgh_plan p, OpPlan* op, bool f32, const void* x)
     if (err != hipSuccess) return FGH_E_DEVICE;
     op->rpb_first = best;
     op->lds_first_v2 = lds_of(best);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = best;
+    return FGH_OK;
+}
+
+// Rows per block of the fused last + first pass, measured at plan creation like the first pass's:
+// the last pass's count and even counts above it (so the partial sums fit the buffer sized for
+// the last pass, and rows pair into complex transforms as in the separate passes: results do not
+// depend on the choice).
+fgh_status tune_fused(fgh_plan p, OpPlan* op, bool f32, void* x)
+{
+    if (!op->v2_row || env_int("FGH_TUNE", 1) == 0 || std::getenv("FGH_RPB")) return FGH_OK;
+    static std::mutex mu;
+    static std::map<std::vector<long long>, int> cache;
+    const Geo& g = op->g;
+    const std::vector<long long> key = {f32 ? 1 : 0, g.d, g.L[g.d - 1], g.Hb, g.rows, (long long)op->A.kind,
+                                        op->rpb};
+    const size_t cs = f32 ? 8 : 16;
+    const size_t tabb = kMaxPhases * 6 * (f32 ? 4 : 8);
+    const int L = g.L[g.d - 1];
+    auto lds_of = [&](int r) { return (size_t)(L + (size_t)((r * g.d + 1) / 2) * (L + 1)) * cs + 2 * tabb; };
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            op->rpb_fused = it->second;
+            op->lds_fused = lds_of(it->second);
+            return FGH_OK;
+        }
+    }
+    std::vector<int> cand = {op->rpb};
+    for (int r : {8, 10, 12, 16})
+        if (r > op->rpb) cand.push_back(r);
+    hipEvent_t e0, e1;
+    HIPOK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return FGH_E_DEVICE;
+    }
+    int best = op->rpb_fused;
+    float best_ms = 1e30f;
+    hipError_t err = hipSuccess;
+    for (int round = 0; round < 2 && err == hipSuccess; round++)
+    for (int r : cand) {
+        if (lds_of(r) > 128 * 1024 || r > g.rows) continue;
+        OpPlan o = *op;
+        o.rpb_fused = r;
+        o.lds_fused = lds_of(r);
+        auto run = [&]() {
+            return f32 ? run_fused_only<float>(o, static_cast<float*>(x)) : run_fused_only<double>(o, static_cast<double*>(x));
+        };
+        if ((err = run()) != hipSuccess) break;
+        if ((err = hipEventRecord(e0, o.stream)) != hipSuccess) break;
+        for (int k = 0; k < 3 && err == hipSuccess; k++) err = run();
+        if (err != hipSuccess || (err = hipEventRecord(e1, o.stream)) != hipSuccess) break;
+        if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.0f;
+        if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = r;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return FGH_E_DEVICE;
+    op->rpb_fused = best;
+    op->lds_fused = lds_of(best);
     std::lock_guard<std::mutex> lk(mu);
     cache[key] = best;
     return FGH_OK;
@@ -1491,6 +1561,9 @@ fgh_status fgh_plan_create(fgh_plan* out, int d, const int32_t* N, fgh_rule rule
             return fail(FGH_E_DEVICE);
         p->op32.A.coef = c32;
     }
+    // the fused pass multiplies by A: tuned once the operator's coefficients are in place
+    if ((s = tune_fused(p, &p->op64, false, p->r64))) return fail(s);
+    if (precision == FGH_FP32_REFINED && (s = tune_fused(p, &p->op32, true, p->r32))) return fail(s);
     if (hipStreamSynchronize(p->stream) != hipSuccess) return fail(FGH_E_DEVICE);
     *out = p;
     return FGH_OK;

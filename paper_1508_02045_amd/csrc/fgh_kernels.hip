@@ -1062,7 +1062,7 @@ static hipError_t v2_last(const OpPlan& op, const LastArgs<T>& la, int epi, unsi
 template <typename T, int D, int EPI>
 static hipError_t v2_lastfirst_epi(const OpPlan& op, const LastArgs<T>& la, unsigned* nblk)
 {
-    const size_t lds = op.lds_last_v2 + kMaxPhases * 6 * sizeof(T);
+    const size_t lds = op.lds_fused;
     switch (la.ax.L) {
 #define C(LL, A1, A2) \
     case LL: LAUNCH_LDS((k2_lastfirst<T, D, A1, A2, EPI>), dim3(*nblk), lds, op.stream, la); break;
@@ -1273,6 +1273,12 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     if (fused && (!fusable(op) || a.next_op != (a.epi == EPI_EM ? OP_EM : OP_AX) ||
                   (a.epi != EPI_RICH && a.epi != EPI_CHEB && a.epi != EPI_EM)))
         return hipErrorInvalidValue;
+    if (fused) {
+        // the fused pass has its own (tuned, even) rows per block
+        la.rpb = op.rpb_fused;
+        la.npen = (op.rpb_fused * D + 1) / 2;
+        nblk = (unsigned)((g.rows + op.rpb_fused - 1) / op.rpb_fused);
+    }
     const bool prof_PK_LAST = op.prof && op.prof->wants(PK_LAST);
     if (prof_PK_LAST && (e = op.prof->begin(PK_LAST)) != hipSuccess) return e;
     if ((e = fused        ? v2_lastfirst<T, D>(op, la, a.epi, &nblk)
@@ -1342,6 +1348,33 @@ hipError_t run_first_only(const OpPlan& op, const T* x)
 }
 template hipError_t run_first_only<double>(const OpPlan&, const double*);
 template hipError_t run_first_only<float>(const OpPlan&, const float*);
+
+template <typename T>
+hipError_t run_fused_only(const OpPlan& op, T* x)
+{
+    // the pass multiplies by A: the plan's coefficients must be set
+    if (op.A.kind == AK_PHASE ? op.A.phase == nullptr : op.A.coef == nullptr) return hipErrorInvalidValue;
+    OpPlan o = op;
+    o.prof = nullptr;
+    const Geo& g = op.g;
+    LastArgs<T> la{};
+    la.g = g;
+    la.ax = op.ax[g.d - 1];
+    la.rpb = op.rpb_fused;
+    la.npen = (op.rpb_fused * g.d + 1) / 2;
+    la.in = static_cast<const cpx<T>*>(op.SA);
+    la.x = x;
+    la.omega = 0.0;
+    la.sgn = 1.0;
+    la.A = op.A;
+    la.partials = op.partials;
+    la.twg = static_cast<const cpx<T>*>(op.tw[g.d - 1]);
+    la.out = static_cast<cpx<T>*>(op.SA);
+    unsigned nblk = (unsigned)((g.rows + op.rpb_fused - 1) / op.rpb_fused);
+    return g.d == 2 ? v2_lastfirst<T, 2>(o, la, EPI_RICH, &nblk) : v2_lastfirst<T, 3>(o, la, EPI_RICH, &nblk);
+}
+template hipError_t run_fused_only<double>(const OpPlan&, double*);
+template hipError_t run_fused_only<float>(const OpPlan&, float*);
 
 // One strided-axis launch with explicit geometry (generic kernel, any length): transform along
 // an axis of length ax.L for `outer` blocks of `inner` contiguous columns per component.

@@ -55,6 +55,8 @@ struct OpPlan {
     size_t lds_first, lds_axis, lds_mid;
     size_t lds_first_v2;     // the specialised first pass (one row buffer)
     size_t lds_last_v2;      // the specialised last pass (one row buffer)
+    int rpb_fused;           // the fused last + first pass: rows per block (even or the last pass's; tuned)
+    size_t lds_fused;        //   and its LDS (one row buffer, two coefficient tables)
     bool v2_row, v2_axis, v2_mid;  // size-specialised kernels for the row / axis-1 / axis-0 passes
     double* partials;        // one double per block of the last pass (and of vector kernels)
     Scalars* sc;
@@ -115,6 +117,11 @@ hipError_t run_axis_only(const OpPlan& op);
 // buffer (tile tuning at plan creation).
 template <typename T>
 hipError_t run_first_only(const OpPlan& op, const T* x);
+
+// The fused last + first Richardson pass alone, with step 0 (x is read and rewritten unchanged),
+// on the plan's first spectrum buffer (tile tuning at plan creation; the buffer is overwritten).
+template <typename T>
+hipError_t run_fused_only(const OpPlan& op, T* x);
 
 // Trigonometric prolongation of a real vector field from the N grid of `opn` to the 2N-1 grid of
 // `opm` (both double precision; opm's spectrum buffers are used as scratch).
