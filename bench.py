@@ -387,8 +387,8 @@ def main():
                     help="with --applies-only: the 135^3 r=8 f=0.30 or the 243^3 r=12 f=0.25 Boolean spheres")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not part "
-              f"of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU "
+              f"path: a solve runs on one device", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
