@@ -587,18 +587,18 @@ int orc_solve(int d, const int* N, int rule, const double* A, const double* E, i
     } while (0)
 
     if (solver == ORC_RICHARDSON) {
-        /* Alg. 1: x_m = x_{m-1} - omega (C x_{m-1} - b), omega = 2/(c_A + C_A);
-         * C x - b = G A (E + x), so the step is s = -omega G A (E + x). */
+        /* Alg. 1 is the stationary iteration x_m = x_{m-1} + w (b - C x_{m-1}) with
+         * w = 2/(c_A + C_A) from x_0 = 0 (eq:optimal_richard): the step is w times the residual,
+         * and the loop ends once that step is small, ||x_m - x_{m-1}||_2 <= eps |E|. */
         const double omega = 2.0 / (cA + CA);
         res_hist[0] = 1.0;
         ENERGY_AT(x);
         while (m < limit) {
-            for (long i = 0; i < L; i++) t[i] = Ef[i] + x[i];
-            pointwise_A(&g, A, t, q);
-            spectral_op(&g, band, q, p, 0);
+            pointwise_A(&g, A, x, t);
+            spectral_op(&g, band, t, q, 0); /* q = C x */
             double ss = 0.0;
             for (long i = 0; i < L; i++) {
-                double s = -omega * p[i];
+                const double s = omega * (b[i] - q[i]);
                 x[i] += s;
                 ss += s * s;
             }
@@ -610,7 +610,7 @@ int orc_solve(int d, const int* N, int rule, const double* A, const double* E, i
             if (fixed_iters <= 0 && step <= eps * normE) break;
         }
     } else if (solver == ORC_CG) {
-        /* Alg. 2 with x_0 = 0: r_0 = b, p_0 = r_0. */
+        /* Alg. 2 is the Hestenes-Stiefel conjugate-gradient recurrence; x_0 = 0, r_0 = b, p_0 = r_0. */
         for (long i = 0; i < L; i++) { r[i] = b[i]; p[i] = b[i]; }
         double rr = dot2(L, r, r, S);
         res_hist[0] = zero_rhs ? 0.0 : 1.0;
@@ -637,26 +637,31 @@ int orc_solve(int d, const int* N, int rule, const double* A, const double* E, i
             }
         }
     } else if (solver == ORC_CHEBYSHEV) {
-        /* Alg. 3 (negative-beta two-term recurrence on [c_A, C_A]); the paper's scalar d is
-         * called delta here. */
+        /* Alg. 3 is Chebyshev semi-iteration on [c_A, C_A]: the residual after m bodies is
+         * r_m = P_m(C) b with the scaled Chebyshev polynomial
+         *     P_m(t) = T_m((delta - t)/c) / T_m(delta/c),  delta = (c_A + C_A)/2,  c = (C_A - c_A)/2
+         * (delta is the paper's d).  Here it is built from the three-term recurrence of T_m in
+         * correction form: x_{m+1} = x_m + d_m, r_{m+1} = r_m - C d_m, with
+         *     d_0 = r_0 / delta,
+         *     d_m = rho_m rho_{m-1} d_{m-1} + 2 rho_m / c r_m,   rho_m = T_m(s)/T_{m+1}(s),  s = delta/c,
+         * and T_{m+1}(s) = 2 s T_m(s) - T_{m-1}(s) gives rho_0 = 1/s, rho_m = 1/(2 s - rho_{m-1}).
+         * With k_m = c rho_m the coefficients stay finite for a one-point interval (c = 0, where
+         * the method is Richardson with step 1/delta):
+         *     k_0 = c^2 / delta,  D_m = 2 delta - k_{m-1} = c / rho_m,  k_m = c^2 / D_m,
+         *     d_m = (k_{m-1} / D_m) d_{m-1} + (2 / D_m) r_m. */
         const double c = 0.5 * (CA - cA), delta = 0.5 * (cA + CA);
-        double alpha = 1.0 / delta;
-        double beta = -0.5 * (c / delta) * (c / delta);
-        for (long i = 0; i < L; i++) { r[i] = b[i]; p[i] = b[i]; }
+        double k = c * c / delta;
+        double* dv = p;
+        for (long i = 0; i < L; i++) { r[i] = b[i]; dv[i] = b[i] / delta; }
         res_hist[0] = zero_rhs ? 0.0 : 1.0;
         ENERGY_AT(x);
         if (!zero_rhs && (fixed_iters > 0 || sqrt(dot2(L, r, r, S)) > eps * normb)) {
             while (m < limit) {
-                if (m + 1 > 1) {
-                    alpha = 1.0 / (delta + beta / alpha);
-                    beta = -(c * alpha / 2.0) * (c * alpha / 2.0);
-                }
-                pointwise_A(&g, A, p, t);
-                spectral_op(&g, band, t, q, 0); /* q = C p */
+                pointwise_A(&g, A, dv, t);
+                spectral_op(&g, band, t, q, 0); /* q = C d_m */
                 for (long i = 0; i < L; i++) {
-                    r[i] -= alpha * q[i];
-                    x[i] += alpha * p[i];
-                    p[i] = r[i] - beta * p[i];
+                    x[i] += dv[i];
+                    r[i] -= q[i];
                 }
                 double rr = dot2(L, r, r, S);
                 m++;
@@ -664,6 +669,10 @@ int orc_solve(int d, const int* N, int rule, const double* A, const double* E, i
                 ENERGY_AT(x);
                 if (!isfinite(rr)) { status = ORC_E_DIVERGED; break; }
                 if (fixed_iters <= 0 && sqrt(rr) <= eps * normb) break;
+                const double D = 2.0 * delta - k; /* c / rho_m */
+                const double keep = k / D, gain = 2.0 / D;
+                for (long i = 0; i < L; i++) dv[i] = keep * dv[i] + gain * r[i];
+                k = c * c / D;
             }
         }
     } else if (solver == ORC_EYRE_MILTON) {

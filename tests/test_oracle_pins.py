@@ -707,3 +707,115 @@ def test_ritz_interlacing_inside_phase_bounds():
         if prev is not None:
             assert rv[0] <= prev[0] + 1e-12 and rv[-1] >= prev[-1] - 1e-10
         prev = rv
+
+
+# ------------------------------------------------------------------------------------------
+# Stopping tests and their scale (Alg. 1, 3, 4; the normalised norm of the Notation paragraph):
+# on a pixel-aligned two-phase laminate loaded across its layers every iterate stays in a
+# one- or two-dimensional space, so the step and residual norms have closed forms that involve
+# no transform.  With n_j layers of phase j (n = n_0 + n_1, f_j = n_j / n) and E = e_0:
+#   b = -G(a E) = -(a - <a>) e_0,   ||b||_2^2 = f_0 f_1 (a_1 - a_0)^2   (1/|grid| in the norm),
+#   C b = lam b with lam = (a_1 n_0 + a_0 n_1) / n   (see test_ritz_laminate_closed_form).
+# Dropping the 1/|grid| of the inner product on one side of a test scales these by sqrt(|grid|).
+# ------------------------------------------------------------------------------------------
+LAMINATE_STOP_CASES = [((9, 7), [1, 1, 0, 0, 0, 1, 0, 0, 0], 1.0, 10.0),
+                       ((7, 5, 9), [0, 1, 1, 0, 1, 0, 0], 2.0, 30.0),
+                       ((11, 3), [1, 0, 0, 0, 1, 1, 1, 0, 0, 1, 0], 1.0, 100.0)]
+
+
+def _laminate_case(N, layers, a0, a1):
+    d = len(N)
+    ph = I.laminate(N, 0, layers)
+    A = I.phase_to_full(ph, I.iso_tables(d, [a0, a1]))
+    n = len(layers)
+    n1 = int(sum(layers))
+    n0 = n - n1
+    E = np.zeros(d)
+    E[0] = 1.0
+    lam = (a1 * n0 + a0 * n1) / n
+    normb = np.sqrt((n0 / n) * (n1 / n)) * abs(a1 - a0)
+    return A, E, n0, n1, lam, normb
+
+
+def _first_below(hist, tol):
+    for m in range(1, len(hist)):
+        if hist[m] <= tol:
+            return m
+    return None
+
+
+@pytest.mark.parametrize("N,layers,a0,a1", LAMINATE_STOP_CASES)
+def test_richardson_step_norm_closed_form(N, layers, a0, a1):
+    """Alg. 1 with x_0 = 0: the step s_m = x_m - x_{m-1} = w (b - C x_{m-1}) = w (1 - w lam)^(m-1) b,
+    so ||s_m||_2 / |E| = w |1 - w lam|^(m-1) ||b||_2 (w = 2 / (c_A + C_A)), and the loop stops at
+    the first m where that is <= tol.  Pins the scale of the step-norm test (reading R8)."""
+    A, E, n0, n1, lam, normb = _laminate_case(N, layers, a0, a1)
+    w = 2.0 / (a0 + a1)
+    tol = 1e-9
+    closed = [1.0] + [w * abs(1.0 - w * lam) ** (m - 1) * normb for m in range(1, 400)]
+    m_stop = _first_below(closed, tol)
+    assert m_stop is not None and m_stop > 3
+    assert abs(closed[m_stop] - tol) > 1e-3 * tol  # no tie at the threshold
+    r = orc.solve(N, orc.GANI, A, E, "richardson", a0, a1, tol)
+    assert r.status == orc.OK and r.iters == m_stop
+    for m in range(r.iters + 1):
+        assert abs(r.res_hist[m] - closed[m]) <= 1e-12 * max(closed[m], 1e-3)
+
+
+@pytest.mark.parametrize("N,layers,a0,a1", LAMINATE_STOP_CASES)
+def test_chebyshev_residual_polynomial_closed_form(N, layers, a0, a1):
+    """Alg. 3 on [c_A, C_A] = [a_0, a_1]: r_m = P_m(C) b with the scaled Chebyshev polynomial
+    P_m(t) = T_m((delta - t) / c) / T_m(delta / c), delta = (c_A + C_A) / 2, c = (C_A - c_A) / 2.
+    b is an eigenvector, so ||r_m|| / ||b|| = |T_m((delta - lam) / c)| / T_m(delta / c) with
+    T_m(cos th) = cos(m th) and T_m(cosh u) = cosh(m u).  Pins the coefficient recurrence and the
+    sign convention of beta (reading R10)."""
+    A, E, n0, n1, lam, normb = _laminate_case(N, layers, a0, a1)
+    delta, c = 0.5 * (a0 + a1), 0.5 * (a1 - a0)
+    th = np.arccos((delta - lam) / c)
+    u = np.arccosh(delta / c)
+    tol = 1e-9
+    closed = [abs(np.cos(m * th)) / np.cosh(m * u) for m in range(0, 400)]
+    m_stop = _first_below(closed, tol)
+    assert m_stop is not None and m_stop > 3
+    assert abs(closed[m_stop] - tol) > 1e-3 * tol
+    r = orc.solve(N, orc.GANI, A, E, "chebyshev", a0, a1, tol)
+    assert r.status == orc.OK and r.iters == m_stop
+    for m in range(r.iters + 1):
+        assert abs(r.res_hist[m] - closed[m]) <= 1e-12 * max(closed[m], 1e-3)
+
+
+@pytest.mark.parametrize("N,layers,a0,a1", LAMINATE_STOP_CASES)
+def test_eyre_milton_two_phase_reduction(N, layers, a0, a1):
+    """Alg. 4 on the laminate loaded across its layers: every iterate is E plus a field constant on
+    each phase along e_0 (the transverse components stay 0), and on such fields (I - 2G) f =
+    2<f> - f, so the iteration reduces to two numbers u_0, u_1 per step:
+      g_j = (a_j - w) u_j,  u_j <- (2 (f_0 g_0 + f_1 g_1) - g_j + 2 w) / (a_j + w),  w = sqrt(a_0 a_1),
+    with step norm sqrt(f_0 du_0^2 + f_1 du_1^2) / |E|.  Pins the mean source (reading R1), the
+    step-norm scale (reading R8), the stopping count and the returned fluctuation."""
+    A, E, n0, n1, lam, normb = _laminate_case(N, layers, a0, a1)
+    f0, f1 = n0 / (n0 + n1), n1 / (n0 + n1)
+    w = np.sqrt(a0 * a1)
+    tol = 1e-9
+    u = [1.0, 1.0]
+    hist = [1.0]
+    states = [list(u)]
+    for _ in range(2000):
+        g = [(a0 - w) * u[0], (a1 - w) * u[1]]
+        mean = f0 * g[0] + f1 * g[1]
+        new = [(2 * mean - g[0] + 2 * w) / (a0 + w), (2 * mean - g[1] + 2 * w) / (a1 + w)]
+        hist.append(np.sqrt(f0 * (new[0] - u[0]) ** 2 + f1 * (new[1] - u[1]) ** 2))
+        u = new
+        states.append(list(u))
+        if hist[-1] <= tol:
+            break
+    m_stop = len(hist) - 1
+    assert hist[-1] <= tol and m_stop > 3 and abs(hist[-1] - tol) > 1e-3 * tol
+    r = orc.solve(N, orc.GANI, A, E, "eyre_milton", a0, a1, tol)
+    assert r.status == orc.OK and r.iters == m_stop
+    for m in range(m_stop + 1):
+        assert abs(r.res_hist[m] - hist[m]) <= 1e-11 * max(hist[m], 1e-3)
+    # returned fluctuation: x_m - E, constant per phase along e_0, zero across
+    ph = I.laminate(N, 0, layers)
+    want0 = np.where(ph == 1, states[-1][1], states[-1][0]) - 1.0
+    assert np.abs(r.e[0] - want0).max() <= 1e-12
+    assert np.abs(r.e[1:]).max() <= 1e-13
