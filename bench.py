@@ -1,22 +1,32 @@
 """Benchmark: voxel-iterations/s of the Fourier-Galerkin operator G.A inside the paper's solvers.
 
-Default workload (one GPU): 3D, N = 135^3, two-phase Boolean model of overlapping spheres
-(radius 8 voxels, volume fraction 0.30), A = I in the matrix and 100 I in the spheres,
-E = (1, 0, 0), GaNi (trapezoidal rule on the N grid), FP64.  One step solves this cell with all
-four solvers -- Richardson, conjugate gradients, Chebyshev on [1, 100], Eyre-Milton -- each to
-1e-8 by its own stopping test, and evaluates A_H (the energy).  The metric counts one
-voxel-iteration per grid point per operator application inside the solver loops.
+Default workload (one GPU): 3D, N = 243^3, two-phase Boolean model of overlapping spheres (radius
+12 voxels, volume fraction 0.25), A = I in the matrix and rho I in the spheres for rho = 1e3 and
+1e4, E = (1, 0, 0), GaNi (trapezoidal rule on the N grid), plain FP64 conjugate gradients
+(Algorithm 2) to 1e-8.  One step solves the cell for both contrasts and evaluates A_H (the
+energy).  The metric counts one voxel-iteration per grid point per loop body (one operator
+application each).  The timed steps run the library as it ships: loop bodies replayed from HIP
+graphs, no profiling.
 
-Prints ONE JSON line.  Extra objects: "roofline" (dominant pass, measured with HIP events on the
-plan's stream during the timed steps, against the 8 TB/s HBM peak) and "cpu_baseline" (the FP64
-oracle timed on a bounded sample of the same workload on the host cores).
+Prints ONE JSON line.  Extra objects:
+  roofline      the kernel with the largest share of GPU time in a step like the timed ones (every
+                launch timed with HIP events attached to its dispatch, on the stream it runs on,
+                in one profiled step after the timed ones), its algorithmic bytes per launch over
+                its average duration, against the 8 TB/s HBM peak; `traffic` from the committed
+                rocprofv3 counter summary when it was taken on the current kernel sources;
+  cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample of the same workload;
+  apply_243     the operator alone: median of 5 runs of 100 back-to-back applications (FP64, FP32);
+  c4_fp32_refined  FP32 transforms inside FP64 defect correction against plain FP64 CG;
+  c2_spheres135 the 135^3 spheres with all four solvers; c3_aniso63: exact integration on 125^3;
+  served, kappa_sweep, monitors, adaptive_bounds: see their functions.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--quick]
 """
 import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -26,9 +36,13 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 SOLVERS = ["richardson", "cg", "chebyshev", "eyre_milton"]
-PASS_KERNELS = {"first": "k2_first", "axis_fwd": "k2_axis<forward>", "middle": "k2_middle<G>",
-                "axis_inv": "k2_axis<inverse>", "last": "k2_last"}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "middle_pass_135_fp64_traffic.json")
+KINDS = ["first", "axis_fwd", "middle", "axis_inv", "last", "cg_update", "reduce"]
+# kernels of one CG body on a specialised 3D grid, by launch kind
+CG_KERNELS = {"first": "k2_first<double,3> (p = r + beta p, A p, r2c of the last axis)",
+              "axis_fwd": "k2_axis<double,forward>", "middle": "k2_middle<double,3,G>",
+              "axis_inv": "k2_axis<double,inverse>", "last": "k2_last<double,3,EPI_CG> (c2r, q = C p, (q, p))",
+              "cg_update": "k_cg_update<double> (x += alpha p, r -= alpha q, (r, r))", "reduce": "k_reduce"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_243.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1508_02045_amd", "csrc", f) for f in
                   ("fgh_kernels.hip", "fgh_fft.hpp", "fgh_internal.hpp", "fgh_v2.hpp", "fgh_args.hpp")]
 
@@ -45,40 +59,96 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def pass_bytes(g, d, p_bytes):
-    """Algorithmic HBM bytes per launch of the fixed-traffic passes (read + write of the
-    half spectrum): the middle and strided-axis passes move d * s complex each way."""
-    N = g
-    H = (N[-1] + 1) // 2
-    s1 = N[0] * N[1] * H if d == 3 else N[0] * H
-    s2 = s1
-    cplx = 2 * p_bytes
+def geometry(N, p_bytes):
+    """Field bytes F = d |grid| p and half-spectrum bytes S = d rows (n_last + 1)/2 2p of a GaNi grid."""
+    d = len(N)
     npts = 1
     for v in N:
         npts *= v
-    # first (plain apply, phase map): read x and one byte of phase per point, write the spectrum;
-    # last (plain store): read the spectrum, write y
-    return {"middle": 2 * d * s2 * cplx, "axis_fwd": d * (s1 + s2) * cplx, "axis_inv": d * (s1 + s2) * cplx,
-            "first": d * npts * p_bytes + npts + d * s1 * cplx, "last": d * s1 * cplx + d * npts * p_bytes}
+    H = (N[-1] + 1) // 2
+    s1 = npts // N[-1] * H
+    return d, npts, d * npts * p_bytes, d * s1 * 2 * p_bytes
 
 
-def c4_section(fgh, inputs, torch, np, n):
-    """243^3 Boolean spheres (r = 12, f = 0.25), A = I / rho I, E = e1: CG in plain FP64 versus
-    FP32 transforms inside FP64 defect correction, for rho = 1e3 and 1e4 (A_H relative difference
-    against the FP64 CG solved to 1e-10), plus the FP32 operator's per-pass times and its
-    algorithmic-bytes fraction of the HBM peak."""
+def apply_bytes(N, p_bytes, a_bytes=1):
+    """Algorithmic HBM bytes of one application y = G A x (five passes in 3D, three in 2D): the
+    first pass reads x and the coefficients (a bytes per point) and writes the half spectrum, each
+    strided / middle pass reads and writes it, the last pass reads it and writes y."""
+    d, npts, F, S = geometry(N, p_bytes)
+    inner = 2 * d - 2  # passes between the first and the last, each S in and S out
+    return 2 * F + a_bytes * npts + 2 * S + inner * 2 * S
+
+
+def cg_kind_bytes(N, p_bytes, a_bytes=1):
+    """Algorithmic bytes per launch of each kernel of one CG body (Algorithm 2) with a phase map:
+    first: r, p in, p out, phase, spectrum out; strided / middle: spectrum in and out; last:
+    spectrum and p in, q out; update: x, p, r, q in, x, r out; reduce: the partial sums."""
+    d, npts, F, S = geometry(N, p_bytes)
+    return {"first": 3 * F + a_bytes * npts + S, "axis_fwd": 2 * S, "middle": 2 * S, "axis_inv": 2 * S,
+            "last": S + 2 * F, "cg_update": 6 * F, "reduce": 1024 * 8}
+
+
+def phase_table(inputs, np, tables):
+    return np.stack([inputs.sym_pack(t[None])[:, 0] for t in tables])
+
+
+def time_applies(torch, plan, x, y, reps=100, runs=5):
+    """Median over `runs` of the mean time of `reps` back-to-back applications (ms), from torch
+    events on the current stream, which is the plan's stream."""
+    for _ in range(3):
+        plan.apply(x, y)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(runs):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            plan.apply(x, y)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / reps)
+    return statistics.median(ts), ts
+
+
+def apply_section(fgh, inputs, torch, np, n, plan64):
+    """The operator alone at n^3: FP64 on the timed workload's plan and FP32 on a refined plan of
+    the same input; median of 5 runs of 100 back-to-back applications against the algorithmic
+    bytes of the five passes."""
+    out = {"N": n, "timing": "median of 5 runs of 100 back-to-back applications, torch events on the plan's stream"}
+    w = inputs.config4(1e3, N=n)
+    plan32 = fgh.Plan(w.N, precision=fgh.FGH_FP32_REFINED, phase=torch.from_numpy(w.phase).cuda(),
+                      phase_table=phase_table(inputs, np, w.tables), c_A=1.0, C_A=1e3)
+    for tag, plan, dt, p in (("fp64", plan64, torch.float64, 8), ("fp32", plan32, torch.float32, 4)):
+        x = torch.randn((3,) + w.N, dtype=dt, device="cuda")
+        y = torch.empty_like(x)
+        ms, runs = time_applies(torch, plan, x, y)
+        b = apply_bytes(w.N, p)
+        out[tag] = {"ms_per_apply": round(ms, 4), "runs_ms": [round(t, 4) for t in runs], "B_alg_bytes": b,
+                    "alg_GBs": round(b / (ms * 1e-3) / 1e9, 1), "frac_of_8TBs": round(b / (ms * 1e-3) / 8e12, 4),
+                    "voxel_applications_per_s": round(n ** 3 / (ms * 1e-3))}
+        log(f"[bench] apply {tag} {n}^3: {ms * 1e3:.1f} us, {out[tag]['frac_of_8TBs']:.3f} of 8 TB/s")
+        del x, y
+    plan32.close()
+    return out
+
+
+def refined_section(fgh, inputs, torch, np, n, fp64_seconds):
+    """C4 variant (ii): FP32 transforms, projection and A multiply inside FP64 defect correction,
+    CG to 1e-8, for rho = 1e3 and 1e4; A_H error against plain FP64 CG solved to 1e-10 and the
+    speedup over the plain FP64 CG of the timed steps (fp64_seconds, per contrast)."""
     out = {"N": n}
     for rho in (1e3, 1e4):
         w = inputs.config4(rho, N=n)
-        tab = np.stack([inputs.sym_pack(t[None])[:, 0] for t in w.tables])
         ph = torch.from_numpy(w.phase).cuda()
-        rec = {"fraction": round(w.fraction, 4)}
+        tab = phase_table(inputs, np, w.tables)
+        rec = {}
         ref = None
-        for name, prec, tol in (("fp64_reference", fgh.FGH_FP64, 1e-10), ("fp64_cg", fgh.FGH_FP64, 1e-8),
+        for name, prec, tol in (("fp64_reference_1e-10", fgh.FGH_FP64, 1e-10),
                                 ("fp32_refined_cg", fgh.FGH_FP32_REFINED, 1e-8)):
             plan = fgh.Plan(w.N, precision=prec, phase=ph, phase_table=tab, c_A=1.0, C_A=rho)
             e = plan.field()
-            if name != "fp64_reference":
+            if prec == fgh.FGH_FP32_REFINED:
                 plan.solve("cg", w.E, tol, max_iter=20000, e=e)  # warm-up (graph capture)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -89,36 +159,70 @@ def c4_section(fgh, inputs, torch, np, n):
             r = {"status": st, "iters": stats[0]["iters"], "outer": stats[0]["outer_iters"],
                  "fp64_applies": stats[0]["fp64_applies"], "seconds": round(dt, 4), "A_H_11": float(bil[0, 0]),
                  "rel_res_true": stats[0]["rel_res_true"]}
-            if name == "fp64_reference":
+            if ref is None:
                 ref = float(bil[0, 0])
             else:
                 r["A_H_rel_err_vs_fp64_1e-10"] = abs(float(bil[0, 0]) - ref) / ref
             rec[name] = r
-            del plan, e
+            plan.close()
+            del e
             log(f"[bench] c4 rho={rho:g} {name}: {r['iters']} it {dt:.3f} s")
-        rec["speedup_fp32_refined_vs_fp64"] = round(rec["fp64_cg"]["seconds"] / rec["fp32_refined_cg"]["seconds"], 3)
+        rec["fp64_cg_1e-8_seconds"] = round(fp64_seconds[rho], 4)
+        rec["speedup_fp32_refined_vs_fp64"] = round(fp64_seconds[rho] / rec["fp32_refined_cg"]["seconds"], 3)
         out[f"rho_{rho:g}"] = rec
-    # FP32 operator per-pass times
-    w = inputs.config4(1e3, N=n)
-    tab = np.stack([inputs.sym_pack(t[None])[:, 0] for t in w.tables])
-    plan = fgh.Plan(w.N, precision=fgh.FGH_FP32_REFINED, phase=torch.from_numpy(w.phase).cuda(), phase_table=tab)
-    x = torch.randn((3,) + w.N, dtype=torch.float32, device="cuda")
-    y = torch.empty_like(x)
-    for _ in range(3):
-        plan.apply(x, y)
-    torch.cuda.synchronize()
-    plan.set_profiling(True)
-    for _ in range(10):
-        plan.apply(x, y)
-    prof = plan.read_profile()
-    plan.set_profiling(False)
-    per = {k: round(v[0] * 1e3 / max(v[1], 1), 2) for k, v in prof.items()}
-    tot_us = sum(per.values())
-    b_alg = (5 * 2 * 3 * 4 * (1 + 1 / n) + 1) * n ** 3  # five passes of the half spectrum, phase map
-    out["apply_fp32"] = {"per_pass_avg_us": per, "sum_us": round(tot_us, 1), "B_alg_bytes": b_alg,
-                         "alg_GBs": round(b_alg / (tot_us * 1e-6) / 1e9, 1),
-                         "frac_of_8TBs": round(b_alg / (tot_us * 1e-6) / 8e12, 4),
-                         "voxel_iterations_per_s": round(n ** 3 / (tot_us * 1e-6))}
+    return out
+
+
+def c2_section(fgh, inputs, torch, np, n=135):
+    """135^3 Boolean spheres (r = 8, f = 0.30), A = I / 100 I, E = e1: the four solvers to 1e-8,
+    time to tolerance and A_H each (one warm-up solve each first)."""
+    w = inputs.config2(N=n)
+    plan = fgh.Plan(w.N, phase=torch.from_numpy(w.phase).cuda(), phase_table=phase_table(inputs, np, w.tables),
+                    c_A=1.0, C_A=w.contrast)
+    e = plan.field()
+    out = {"N": n, "fraction": round(w.fraction, 4)}
+    total_vox, total_s = 0, 0.0
+    for s in SOLVERS:
+        plan.solve(s, w.E, 1e-8, max_iter=5000, e=e)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st, stats = plan.solve(s, w.E, 1e-8, max_iter=5000, e=e)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        bil, _ = plan.effective(w.E, e)
+        out[s] = {"iters": stats[0]["iters"], "seconds": round(dt, 4), "A_H_11": float(bil[0, 0]),
+                  "rel_res_true": stats[0]["rel_res_true"]}
+        total_vox += stats[0]["iters"] * plan.npts
+        total_s += dt
+    out["voxel_iterations_per_s"] = round(total_vox / total_s)
+    plan.close()
+    log(f"[bench] c2 135^3: " + ", ".join(f"{s} {out[s]['iters']}" for s in SOLVERS))
+    return out
+
+
+def c3_section(fgh, inputs, torch, np):
+    """Anisotropic 63^3 (per-voxel R^T diag(lambda) R, lambda in [1, 1e3]): loads e1, e2, e3 by CG
+    to 1e-9 with exact integration on the double grid 125^3 and with GaNi on 63^3; the full A_H."""
+    w = inputs.config3()
+    A = torch.from_numpy(inputs.sym_pack(w.A_full)).cuda()
+    out = {"N": list(w.N)}
+    for rule, tag in ((fgh.FGH_GA, "ga_125"), (fgh.FGH_GANI, "gani_63")):
+        t0 = time.perf_counter()
+        plan = fgh.Plan(w.N, rule=rule, A=A, a_kind=fgh.FGH_A_SYM)
+        t_plan = time.perf_counter() - t0
+        E = np.eye(3)
+        e = plan.field(3)
+        plan.solve("cg", E, 1e-9, max_iter=5000, e=e)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st, stats = plan.solve("cg", E, 1e-9, max_iter=5000, e=e)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        bil, _ = plan.effective(E, e)
+        out[tag] = {"grid": list(plan.grid), "plan_seconds": round(t_plan, 3), "seconds_3_loads": round(dt, 4),
+                    "iters": [s["iters"] for s in stats], "A_H": [[float(v) for v in row] for row in bil]}
+        plan.close()
+        log(f"[bench] c3 {tag}: iters {out[tag]['iters']}, {dt:.3f} s")
     return out
 
 
@@ -328,38 +432,37 @@ def served_section(fgh, inputs, np, n_req, max_active=4, pool_gb=24):
 COPY_BYTES = 512 * 1024 * 1024
 
 
-def applies_only(args, fgh, inputs, torch, np):
-    """K plain applications y = G A x of the bench workload with per-pass timing, then a plain
-    device copy of COPY_BYTES (read COPY_BYTES, write COPY_BYTES) that calibrates the HBM byte
-    counters of a profiler run."""
-    w = inputs.config2(N=args.n) if args.workload == "spheres135" else inputs.config4(1e3, N=243)
-    tab = np.stack([inputs.sym_pack(t[None])[:, 0] for t in w.tables])
-    prec = fgh.FGH_FP64 if args.precision == "fp64" else fgh.FGH_FP32_REFINED
-    plan = fgh.Plan(w.N, precision=prec, phase=torch.from_numpy(w.phase).cuda(), phase_table=tab, c_A=1.0,
-                    C_A=w.contrast)
-    dt = torch.float64 if prec == fgh.FGH_FP64 else torch.float32
-    x = torch.randn((3,) + w.N, dtype=dt, device="cuda")
-    y = torch.empty_like(x)
-    for _ in range(3):
-        plan.apply(x, y)
+def counters_mode(args, fgh, inputs, torch, np):
+    """Runs for rocprofv3 counter collection at 243^3: `cg64` runs K fixed FP64 CG bodies of the
+    timed workload (rho = 1e3), `apply64` / `apply32` K plain applications; then a plain device
+    copy of COPY_BYTES each way that calibrates the HBM byte counters."""
+    n = args.n
+    w = inputs.config4(1e3, N=n)
+    prec = fgh.FGH_FP32_REFINED if args.counters == "apply32" else fgh.FGH_FP64
+    plan = fgh.Plan(w.N, precision=prec, phase=torch.from_numpy(w.phase).cuda(),
+                    phase_table=phase_table(inputs, np, w.tables), c_A=1.0, C_A=1e3)
+    if args.counters == "cg64":
+        e = plan.field()
+        _, st, stats = plan.solve_fixed("cg", w.E, args.counter_reps, e=e)
+        kb = cg_kind_bytes(w.N, 8)
+    else:
+        dt = torch.float64 if prec == fgh.FGH_FP64 else torch.float32
+        x = torch.randn((3,) + w.N, dtype=dt, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(args.counter_reps):
+            plan.apply(x, y)
+        d, npts, F, S = geometry(w.N, 8 if prec == fgh.FGH_FP64 else 4)
+        kb = {"first": F + npts + S, "axis_fwd": 2 * S, "middle": 2 * S, "axis_inv": 2 * S, "last": S + F}
     torch.cuda.synchronize()
-    plan.set_profiling(True)
-    for i in range(args.applies_only):
-        plan.apply(x, y)
-    prof = plan.read_profile()
-    plan.set_profiling(False)
-    torch.cuda.synchronize()
-    log(f"[bench] {args.applies_only} applies done")
+    log(f"[bench] counters {args.counters}: {args.counter_reps} done")
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
-    pb = pass_bytes(w.N, 3, 8 if prec == fgh.FGH_FP64 else 4)
-    per = {k: round(v[0] * 1e3 / max(v[1], 1), 2) for k, v in prof.items()}
-    print(json.dumps({"workload": w.name, "precision": args.precision, "applies": args.applies_only,
-                      "per_pass_avg_us": per, "algorithmic_bytes_per_launch": pb,
-                      "copy_bytes_each_way": COPY_BYTES}), flush=True)
+    print(json.dumps({"workload": w.name, "mode": args.counters, "reps": args.counter_reps,
+                      "algorithmic_bytes_per_launch": kb, "copy_bytes_each_way": COPY_BYTES,
+                      "kernel_source_hash": kernel_source_hash()}), flush=True)
 
 
 def main():
@@ -367,24 +470,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=135)
+    ap.add_argument("--n", type=int, default=243, help="grid size of the timed workload (243: C4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=16)
-    ap.add_argument("--no-c4", action="store_true", help="skip the 243^3 FP32-refinement section")
-    ap.add_argument("--no-served", action="store_true", help="skip the served-stream section")
-    ap.add_argument("--no-kappa", action="store_true", help="skip the iterations-versus-contrast section")
-    ap.add_argument("--no-monitors", action="store_true", help="skip the monitor-cost section")
-    ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive-bounds section")
+    ap.add_argument("--cpu-applies", type=int, default=2, help="oracle applications in the CPU baseline sample")
+    ap.add_argument("--quick", action="store_true", help="the headline line only (no extra sections)")
+    for name in ("apply", "refined", "c2", "c3", "served", "kappa", "monitors", "adaptive"):
+        ap.add_argument(f"--no-{name}", action="store_true", help=f"skip the {name} section")
     ap.add_argument("--served-n", type=int, default=64)
-    ap.add_argument("--c4-n", type=int, default=243)
-    ap.add_argument("--no-profile", action="store_true",
-                    help="time without the per-pass HIP events (solver loops then replay HIP graphs)")
-    ap.add_argument("--applies-only", type=int, default=0, metavar="K",
-                    help="counter runs: K plain operator applications of the workload (and a copy of known "
-                         "size for calibration), a summary line, nothing else")
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64", help="with --applies-only")
-    ap.add_argument("--workload", choices=["spheres135", "spheres243"], default="spheres135",
-                    help="with --applies-only: the 135^3 r=8 f=0.30 or the 243^3 r=12 f=0.25 Boolean spheres")
+    ap.add_argument("--counters", choices=["cg64", "apply64", "apply32"], default=None,
+                    help="counter runs for rocprofv3 --pmc: K CG bodies or K applications at 243^3 and a copy "
+                         "of known size for calibration, a summary line, nothing else")
+    ap.add_argument("--counter-reps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU "
@@ -397,97 +493,145 @@ def main():
     from paper_1508_02045_amd import fgh, inputs
 
     torch.cuda.set_device(0)
-    if args.applies_only > 0:
-        applies_only(args, fgh, inputs, torch, np)
+    if args.counters:
+        counters_mode(args, fgh, inputs, torch, np)
         return
     n = args.n
-    log(f"[bench] generating Boolean spheres {n}^3 r=8 f=0.30")
-    w = inputs.config2(N=n)
-    tab = np.stack([inputs.sym_pack(t[None])[:, 0] for t in w.tables])
-    phase_dev = torch.from_numpy(w.phase).cuda()
-    plan = fgh.Plan(w.N, phase=phase_dev, phase_table=tab, c_A=1.0, C_A=w.contrast)
-    d = 3
-    npts = plan.npts
     tol = 1e-8
-    e = plan.field()
+    rhos = (1e3, 1e4)
+    log(f"[bench] generating Boolean spheres {n}^3 r=12 f=0.25")
+    w = inputs.config4(1e3, N=n)
+    ph = torch.from_numpy(w.phase).cuda()
+    plans, fields = {}, {}
+    t0 = time.perf_counter()
+    for rho in rhos:
+        plans[rho] = fgh.Plan(w.N, phase=ph, phase_table=phase_table(inputs, np, inputs.iso_tables(3, [1.0, rho])),
+                              c_A=1.0, C_A=rho)
+        fields[rho] = plans[rho].field()
+    plan_seconds = (time.perf_counter() - t0) / len(rhos)
+    npts = plans[rhos[0]].npts
 
     def step():
         out = {}
-        for s in SOLVERS:
-            e_, st, stats = plan.solve(s, w.E, tol, max_iter=5000, e=e)
+        for rho in rhos:
+            ts = time.perf_counter()
+            _, st, stats = plans[rho].solve("cg", w.E, tol, max_iter=20000, e=fields[rho])
             if st != fgh.FGH_OK:
-                raise RuntimeError(f"{s}: status {st} {stats}")
-            bil, flux = plan.effective(w.E, e)
-            out[s] = {"iters": stats[0]["iters"], "seconds": stats[0]["seconds"], "A_H_11": float(bil[0, 0]),
-                      "flux": [float(v) for v in flux[0]], "rel_res_true": stats[0]["rel_res_true"]}
+                raise RuntimeError(f"rho {rho}: status {st} {stats}")
+            bil, flux = plans[rho].effective(w.E, fields[rho])
+            torch.cuda.synchronize()
+            out[rho] = {"iters": stats[0]["iters"], "seconds": round(time.perf_counter() - ts, 4),
+                        "A_H_11": float(bil[0, 0]), "flux": [float(v) for v in flux[0]],
+                        "rel_res_true": stats[0]["rel_res_true"]}
         return out
 
     for i in range(args.warmup):
         log(f"[bench] warmup step {i + 1}/{args.warmup}")
         step()
-    # untimed: per-pass breakdown of one step, to name the dominant fixed-traffic pass
-    plan.set_profiling(True)
-    step()
-    prof_all = plan.read_profile()
-    plan.set_profiling(False)
-    pb = pass_bytes(w.N, d, 8)
-    dom = max(("middle", "axis_fwd", "axis_inv"), key=lambda k: prof_all[k][0])
-
-    torch.cuda.synchronize()
-    if not args.no_profile:
-        plan.set_profiling(True, passes=[dom])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     total_iters = 0
     res = None
+    seconds = {rho: [] for rho in rhos}
     for i in range(args.steps):
         res = step()
         total_iters += sum(r["iters"] for r in res.values())
-        log(f"[bench] step {i + 1}/{args.steps}: " + ", ".join(f"{k} {v['iters']}" for k, v in res.items()))
+        for rho in rhos:
+            seconds[rho].append(res[rho]["seconds"])
+        log(f"[bench] step {i + 1}/{args.steps}: " + ", ".join(f"rho {k:g}: {v['iters']} it {v['seconds']:.3f} s"
+                                                              for k, v in res.items()))
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = plan.read_profile()
-    plan.set_profiling(False)
-    elapsed = t1 - t0
+    elapsed = time.perf_counter() - t0
     value = total_iters * npts / elapsed
 
-    # roofline of the dominant fixed-traffic pass, timed with HIP events inside the timed steps
-    ms_tot, launches = prof[dom]
-    avg_s = ms_tot / 1e3 / max(launches, 1) if launches else float("nan")
-    achieved = pb[dom] / avg_s / 1e9 if launches else None
+    # one more step with every launch timed (HIP events attached to the dispatches, on the stream
+    # they run on; loop bodies are then launched one by one instead of replayed from graphs)
+    for rho in rhos:
+        plans[rho].set_profiling(True)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    profiled_ms = (time.perf_counter() - tp) * 1e3
+    kinds = {k: [0.0, 0] for k in KINDS}
+    for rho in rhos:
+        for k, (ms, cnt) in plans[rho].read_profile().items():
+            kinds[k][0] += ms
+            kinds[k][1] += cnt
+        plans[rho].set_profiling(False)
+    kb = cg_kind_bytes(w.N, 8)
+    gpu_ms = sum(v[0] for v in kinds.values())
+    table = {}
+    for k, (ms, cnt) in kinds.items():
+        if cnt == 0:
+            continue
+        avg = ms / cnt * 1e-3
+        table[k] = {"kernel": CG_KERNELS[k], "launches": cnt, "avg_us": round(avg * 1e6, 2),
+                    "share": round(ms / gpu_ms, 4), "alg_bytes_per_launch": kb[k],
+                    "alg_GBs": round(kb[k] / avg / 1e9, 1), "frac": round(kb[k] / avg / 8e12, 4)}
+    dom = max(table, key=lambda k: table[k]["share"])
     traffic = None
+    traffic_src = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
-        if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("pass") == dom:
-            traffic = tr.get("bytes_per_launch")
-    roofline = {"bound": "hbm", "kernel": PASS_KERNELS[dom], "achieved": None if achieved is None else round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "algorithmic_bytes_per_launch": pb[dom], "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
-                "per_pass_avg_us_untimed_step": {k: round(v[0] * 1e3 / max(v[1], 1), 2) for k, v in prof_all.items()},
-                "per_pass_share_untimed_step": {k: round(v[0] / max(sum(x[0] for x in prof_all.values()), 1e-30), 3)
-                                                for k, v in prof_all.items()}}
-    extra = None if args.no_c4 else c4_section(fgh, inputs, torch, np, args.c4_n)
-    served = None if args.no_served else served_section(fgh, inputs, np, args.served_n)
-    kappa = None if args.no_kappa else kappa_section(fgh, inputs, np, torch)
-    monitors = None if args.no_monitors else monitor_section(fgh, inputs, np, torch, w, plan)
-    adaptive = None if args.no_adaptive else adaptive_section(fgh, inputs, np, torch, w, plan)
+        if tr.get("kernel_source_hash") == kernel_source_hash() and dom in tr.get("cg64", {}):
+            traffic = tr["cg64"][dom]["bytes_per_launch"]
+            traffic_src = os.path.relpath(TRAFFIC_FILE, ROOT)
+    dom_avg = table[dom]["avg_us"] * 1e-6
+    roofline = {"bound": "hbm", "kernel": CG_KERNELS[dom], "kind": dom, "achieved": table[dom]["alg_GBs"],
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": table[dom]["frac"], "traffic": traffic,
+                "traffic_source": traffic_src, "algorithmic_bytes_per_launch": kb[dom],
+                "avg_launch_us": round(dom_avg * 1e6, 2), "launches": table[dom]["launches"],
+                "timing": "HIP events on each dispatch in one profiled step after the timed steps",
+                "profiled_step_ms": round(profiled_ms, 1), "kernel_ms_in_profiled_step": round(gpu_ms, 1),
+                "kernels": table}
+    log(f"[bench] dominant kernel {dom}: {table[dom]['avg_us']} us, {table[dom]['frac']:.3f} of 8 TB/s")
+
+    extra = {}
+    fp64_seconds = {rho: statistics.median(seconds[rho]) for rho in rhos}
+    if not args.quick and not args.no_apply:
+        extra["apply_243"] = apply_section(fgh, inputs, torch, np, n, plans[1e3])
+    for rho in rhos:
+        plans[rho].close()
+    plans.clear()
+    fields.clear()
+    torch.cuda.empty_cache()
+    if not args.quick and not args.no_refined:
+        extra["c4_fp32_refined"] = refined_section(fgh, inputs, torch, np, n, fp64_seconds)
+    if not args.quick and not args.no_c2:
+        extra["c2_spheres135"] = c2_section(fgh, inputs, torch, np)
+    if not args.quick and not args.no_c3:
+        extra["c3_aniso63"] = c3_section(fgh, inputs, torch, np)
+    if not args.quick and not args.no_served:
+        extra["served"] = served_section(fgh, inputs, np, args.served_n)
+    if not args.quick and not args.no_kappa:
+        extra["kappa_sweep"] = kappa_section(fgh, inputs, np, torch)
+    if not args.quick and (not args.no_monitors or not args.no_adaptive):
+        w2 = inputs.config2()
+        plan2 = fgh.Plan(w2.N, phase=torch.from_numpy(w2.phase).cuda(), phase_table=phase_table(inputs, np, w2.tables),
+                         c_A=1.0, C_A=w2.contrast)
+        if not args.no_monitors:
+            extra["monitors"] = monitor_section(fgh, inputs, np, torch, w2, plan2)
+        if not args.no_adaptive:
+            extra["adaptive_bounds"] = adaptive_section(fgh, inputs, np, torch, w2, plan2)
+        plan2.close()
 
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import orc
         A_full = w.full()
-        log(f"[bench] cpu baseline: oracle CG, {args.cpu_iters} fixed iterations at {n}^3 "
-            f"on {orc.num_threads()} threads")
+        x = np.random.default_rng(0).standard_normal((3,) + w.N)
+        k = args.cpu_applies
+        log(f"[bench] cpu baseline: {k} oracle applications of G.A at {n}^3 on {orc.num_threads()} threads")
         tc = time.perf_counter()
-        r = orc.solve(w.N, orc.GANI, A_full, w.E, "cg", 1.0, w.contrast, tol, fixed_iters=args.cpu_iters)
+        for _ in range(k):
+            orc.apply(w.N, orc.GANI, A_full, x)
         tcpu = time.perf_counter() - tc
-        cpu = {"value": args.cpu_iters * npts / tcpu, "unit": "voxel-iterations/s", "cores": orc.num_threads(),
-               "kind": "oracle",
-               "sample": f"FP64 oracle (naive DFT) CG with {args.cpu_iters} fixed iterations on the same {n}^3 "
-                         f"input, wall {tcpu:.1f} s including its right-hand side and exit-residual applies"}
-        del r
+        cpu = {"value": k * npts / tcpu, "unit": "voxel-iterations/s", "cores": orc.num_threads(), "kind": "oracle",
+               "sample": f"{k} applications of G.A by the FP64 oracle (naive DFT) on the same {n}^3 input, "
+                         f"one CG body's operator work each, wall {tcpu:.1f} s"}
+        del A_full
 
     line = {
         "metric": "voxel-iterations/s of G.A",
@@ -502,17 +646,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"3D Boolean spheres {n}^3 r=8 f={w.fraction:.4f} contrast 100, GaNi, FP64, "
-                               f"Richardson+CG+Chebyshev+Eyre-Milton to 1e-8, E=e1",
-                   "N": list(w.N), "solvers": SOLVERS, "tol": tol, "voxel_iterations_per_step": total_iters // args.steps * npts},
-        "solvers": res,
+        "config": {"workload": f"C4: 3D Boolean spheres {n}^3 r=12 f={w.fraction:.4f}, A = I / rho I with rho 1e3 "
+                               f"and 1e4, E=e1, GaNi, plain FP64 CG to 1e-8 (one solve per contrast per step)",
+                   "N": list(w.N), "rho": list(rhos), "solver": "cg", "tol": tol,
+                   "voxel_iterations_per_step": total_iters // args.steps * npts},
+        "solves": {f"rho_{k:g}": v for k, v in res.items()},
+        "time_to_tolerance_s": {f"rho_{k:g}": round(v, 4) for k, v in fp64_seconds.items()},
+        "plan_seconds": round(plan_seconds, 3),
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "c4_fp32_refined_243": extra,
-        "served": served,
-        "kappa_sweep": kappa,
-        "monitors": monitors,
-        "adaptive_bounds": adaptive,
+        **extra,
     }
     print(json.dumps(line), flush=True)
 

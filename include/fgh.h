@@ -49,7 +49,8 @@ typedef enum {
     FGH_E_WORKSPACE = 4,      /* workspace NULL or smaller than fgh_plan_workspace reports */
     FGH_E_NO_CONVERGENCE = 5, /* iteration cap reached; outputs hold the last iterate */
     FGH_E_DIVERGED = 6,       /* non-finite values or a step norm above 1e12 |E| */
-    FGH_E_DEVICE = 7          /* a HIP runtime call failed */
+    FGH_E_DEVICE = 7,         /* a HIP runtime call failed */
+    FGH_E_CANCELLED = 8       /* served request discarded by fgh_server_destroy before admission */
 } fgh_status;
 
 typedef enum {
@@ -149,9 +150,11 @@ fgh_status fgh_ga_coefficients(fgh_plan plan, double* out);
  * (inner bodies per outer step for FGH_FP32_REFINED).  stats: host fgh_stats[nrhs] or NULL.
  * FGH_FP32_REFINED: outer FP64 residual r = b - C x, inner FP32 solve of C delta = r to the
  * relative tolerance max(tol_abs/||r||, 1e-4) by the same solver, then x += G delta in FP64;
- * stops on the true FP64 residual ||b - C x|| <= tol ||b|| (CG, Chebyshev) or on the outer
- * step norm (Eyre-Milton); Richardson is not offered there (FGH_E_UNSUPPORTED).  Blocks until
- * done.  Returns the worst load status. */
+ * stops on the true FP64 residual ||b - C x|| <= tol ||b|| (CG, Chebyshev), on the FP64 step
+ * Richardson would take next, w ||b - C x|| <= tol |E| (Richardson; that step is taken, so the
+ * test is Algorithm 1's own), or on the outer step norm (Eyre-Milton).  rel_res_recursive is then
+ * the stopping-test quantity of the last outer step.  Blocks until done.  Returns the worst load
+ * status. */
 fgh_status fgh_solve(fgh_plan plan, fgh_solver solver, const double* E, int nrhs, double tol,
                      int max_iter, double* e, fgh_stats* stats);
 
@@ -210,8 +213,11 @@ fgh_status fgh_plan_set_history(fgh_plan plan, double* res_hist, double* energy_
 fgh_status fgh_gani_bound(fgh_plan gani, fgh_plan ga, const double* E, const double* e,
                           double* bound);
 
-/* Adaptive spectral bounds (the outlook of Sec. 5: spectral estimates from the CG coefficients to
- * set the Chebyshev and Eyre-Milton parameters).  Runs up to `iters` bodies of Algorithm 2 in
+/* Adaptive spectral bounds: an extension of this library, not a method of the paper.  The paper's
+ * Richardson, Chebyshev and Eyre-Milton take their parameters from the pointwise bounds c_A, C_A
+ * of eq:A (Algorithms 1, 3, 4); its closing outlook (Sec. 5) names a more robust Chebyshev method
+ * as further work but gives no estimate.  This entry point estimates the spectrum of C from the CG
+ * coefficients (the Lanczos connection of CG), for use with fgh_plan_set_bounds.  Runs up to `iters` bodies of Algorithm 2 in
  * double precision on C e = b, b = -G A E (eq:linsys), from e = 0.  The CG coefficients alpha_k,
  * beta_k = ||r_{k+1}||^2 / ||r_k||^2 define the Lanczos matrix T_m of C on the Krylov space
  * K_m(C, b):
@@ -239,15 +245,17 @@ fgh_status fgh_estimate_bounds(fgh_plan plan, const double* E, int iters, double
  * Waits for the plan's stream.  FGH_E_INVALID unless 0 < c_A <= C_A < inf. */
 fgh_status fgh_plan_set_bounds(fgh_plan plan, double c_A, double C_A);
 
-/* Per-pass device timing (profiling aid, off by default).  `enable` is a bit mask of pass kinds
+/* Per-pass device timing (profiling aid, off by default).  `enable` is a bit mask of launch kinds
  * -- bit 0 first (A multiply + forward transform of the last axis), bit 1 forward strided axis,
  * bit 2 middle (transform of axis 0 with the Fourier multiplier), bit 3 inverse strided axis,
- * bit 4 last (inverse transform of the last axis + solver epilogue); 0 turns timing off.  Every
- * launch of a selected kind is bracketed by HIP events on the stream it runs on and its duration
- * accumulated; solver loops then run without graph replay.  Enabling resets the counters. */
+ * bit 4 last (inverse transform of the last axis + solver epilogue; in fused loops also the next
+ * body's first pass), bit 5 CG update (x += alpha p, r -= alpha q, (r, r)), bit 6 single-workgroup
+ * loop reductions; 0 turns timing off.  Every launch of a selected kind is bracketed by HIP events
+ * on the stream it runs on and its duration accumulated; solver loops then run without graph
+ * replay.  Enabling resets the counters. */
 fgh_status fgh_plan_set_profiling(fgh_plan plan, int enable);
 
-/* Accumulated milliseconds and launch counts per pass kind (arrays of 5) over the launches that
+/* Accumulated milliseconds and launch counts per launch kind (arrays of 7) over the launches that
  * did work: solver-loop launches issued after the device-side stopping test has fired return at
  * once, and launches shorter than 30 % of their kind's median are left out.  Times are those of
  * the dispatches themselves (start and stop events attached to the launch).  Synchronises. */
@@ -303,10 +311,14 @@ fgh_status fgh_server_create(fgh_server* out, void* pool, size_t pool_bytes, int
  * FGH_E_UNSUPPORTED for Eyre-Milton with Ga, FGH_E_INVALID for bad fields. */
 fgh_status fgh_server_submit(fgh_server server, const fgh_request* request, int64_t* id);
 
-/* FGH_OK and the result if request `id` has finished, FGH_E_NO_CONVERGENCE while it is pending. */
+/* FGH_OK and the result if request `id` has finished (the result is then released: a later poll or
+ * wait on the same id returns FGH_E_INVALID), FGH_E_NO_CONVERGENCE while it is pending,
+ * FGH_E_INVALID for an id that was never issued or whose result was already returned. */
 fgh_status fgh_server_poll(fgh_server server, int64_t id, fgh_result* out);
 
-/* Block until request `id` has finished. */
+/* Block until request `id` has finished and return its result (released as by fgh_server_poll).
+ * FGH_E_INVALID at once for an id that was never issued or whose result was already returned
+ * (also when another thread takes the same result first). */
 fgh_status fgh_server_wait(fgh_server server, int64_t id, fgh_result* out);
 
 /* Block until every submitted request has finished. */
@@ -315,7 +327,9 @@ fgh_status fgh_server_drain(fgh_server server);
 /* Server clock, peak pool bytes in use and peak number of concurrently active requests. */
 fgh_status fgh_server_stats(fgh_server server, double* now_seconds, size_t* peak_pool_bytes, int* peak_active);
 
-/* Stop the workers after the requests already admitted; requests still queued are discarded. */
+/* Stop the workers after the requests already admitted; requests still queued are discarded: their
+ * result has status FGH_E_CANCELLED, and threads blocked in fgh_server_wait on them return it.
+ * Returns once those threads have left; no other call on the server may start after this one. */
 void fgh_server_destroy(fgh_server server);
 
 const char* fgh_status_string(fgh_status status);

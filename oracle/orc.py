@@ -230,8 +230,8 @@ def krylov_rhs(N, rule, A, E):
 def ritz_values(N, rule, A, E, m, breakdown=1e-10):
     """Ritz values of C = G A on the Krylov space K_m(C, b), b = -C E.
 
-    This is the plain Rayleigh-Ritz definition behind the adaptive bounds of the paper's
-    closing outlook (Sec. 5): an orthonormal basis Q of span{b, C b, ..., C^(m-1) b} is built by
+    This is the plain Rayleigh-Ritz definition behind the library's adaptive bounds (an extension:
+    the paper's solvers take the pointwise bounds of eq:A): an orthonormal basis Q of span{b, C b, ..., C^(m-1) b} is built by
     Gram-Schmidt, applied twice to each new vector, and the eigenvalues of the m x m matrix
     Q^T C Q are returned in ascending order.  The inner product is the plain sum over the grid
     and the components.  When C^j b already lies in the span of the earlier vectors (relative

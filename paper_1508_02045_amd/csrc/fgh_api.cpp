@@ -533,7 +533,8 @@ fgh_status tune_first(fgh_plan p, OpPlan* op, bool f32, const void* x)
     static std::mutex mu;
     static std::map<std::vector<long long>, int> cache;
     const Geo& g = op->g;
-    const std::vector<long long> key = {f32 ? 1 : 0, g.d, g.L[g.d - 1], g.Hb, g.rows, (long long)op->A.kind};
+    // the timed pass is the identity-operator first pass: it does not read the coefficients
+    const std::vector<long long> key = {f32 ? 1 : 0, g.d, g.L[g.d - 1], g.Hb, g.rows};
     const size_t cs = f32 ? 8 : 16;
     const size_t tabb = kMaxPhases * 6 * (f32 ? 4 : 8);
     const int L = g.L[g.d - 1];
@@ -885,9 +886,12 @@ hipError_t fused_prologue(const OpPlan& op, ApplyArgs a)
     return run_apply<T>(op, a, &nb);
 }
 
-// Chebyshev semi-iteration (Algorithm 3), b in r, x = 0.
+// Chebyshev semi-iteration (Algorithm 3), b in r, x = 0, on the interval [delta - c, delta + c]
+// (c < 0: the plan's [c_A, C_A]).  With c = 0 the coefficients stay alpha = 1/delta, beta = 0:
+// that is Richardson's iteration x += (1/delta)(b - C x) on an explicit right-hand side.
 template <typename T>
-fgh_status cheb_core(fgh_plan p, T* x, T* r, T* pv, double tol_rel, int max_iter, int fixed, SolveOut* out)
+fgh_status cheb_core(fgh_plan p, T* x, T* r, T* pv, double tol_rel, int max_iter, int fixed, SolveOut* out,
+                     double c_in = -1.0, double delta_in = 0.0)
 {
     const OpPlan& op = opp<T>(p);
     const long long n = (long long)p->d * p->g.npts;
@@ -901,7 +905,8 @@ fgh_status cheb_core(fgh_plan p, T* x, T* r, T* pv, double tol_rel, int max_iter
         if (st0) return st0;
     }
     const double normb = std::sqrt(bb / S);
-    const double c = 0.5 * (p->CA - p->cA), delta = 0.5 * (p->cA + p->CA);
+    const double c = c_in >= 0.0 ? c_in : 0.5 * (p->CA - p->cA);
+    const double delta = c_in >= 0.0 ? delta_in : 0.5 * (p->cA + p->CA);
     const int limit = fixed > 0 ? fixed : max_iter;
     HIPOK(run_init_loop(op, bb, 1.0 / delta, -0.5 * (c / delta) * (c / delta), fixed > 0 ? -1.0 : tol_rel * normb, S,
                         0.0, c, delta, limit));
@@ -928,7 +933,8 @@ fgh_status cheb_core(fgh_plan p, T* x, T* r, T* pv, double tol_rel, int max_iter
         if (e != hipSuccess || defer) return e;
         return run_reduce_async(op, nb, RED_CHEB_END);
     };
-    const uint64_t key = key_of({2, sizeof(T), bits(x), bits(r), bits(pv), (uint64_t)fuse, (uint64_t)defer});
+    const uint64_t key = key_of({2, sizeof(T), bits(x), bits(r), bits(pv), (uint64_t)fuse, (uint64_t)defer, bits(c),
+                                 bits(delta)});
     return run_loop(p, op, body, key, fixed > 0, normb, out);
 }
 
@@ -1149,6 +1155,9 @@ fgh_status solve_one_fp64(fgh_plan p, int solver, const double* E, double tol, i
 //    tolerance max(tol ||b|| / ||r||, kInnerTolMin), then x += G delta in FP64 (the projection
 //    removes the FP32 round-off that is not curl-free, so the iterate stays conforming);
 //    stop when ||b - C x|| <= tol ||b||.
+//  Richardson: stop when the next FP64 step w ||b - C x|| is <= tol |E| (and take it); the
+//    correction solves C delta = r by Richardson in FP32 to the relative residual
+//    max(tol |E| / (w ||r||), kInnerTolMin), then x += G delta in FP64.
 //  Eyre-Milton: the FP64 defect dbar = EM(x) - x; the correction delta obeys
 //    delta = (A + wI)^{-1} (I - 2G^)(A - wI) delta + dbar (same contraction as Algorithm 4),
 //    iterated in FP32 from delta = 0; x += delta; stop when ||dbar|| <= tol |E| (then x takes
@@ -1277,6 +1286,72 @@ fgh_status solve_one_refined(fgh_plan p, int solver, const double* E, double tol
             }
             if (status == FGH_OK && !(res <= tol)) status = FGH_E_NO_CONVERGENCE;
         }
+    } else if (solver == FGH_RICHARDSON) {
+        // Algorithm 1's step from an iterate x is w (b - C x), so its stopping test on the step norm
+        // is a test on the FP64 residual: stop once w ||b - C x|| <= tol |E|, after taking that
+        // last step.  Until then the correction solves C delta = r by Richardson's iteration in
+        // FP32 (Chebyshev on the one-point interval [delta, delta], delta = 1/w, is exactly that
+        // iteration on an explicit right-hand side): its step norms are w times its residuals, so
+        // it stops on ||r_k|| <= eta ||r||.
+        const double omega = 2.0 / (p->cA + p->CA);
+        HIPOK(run_fill<double>(p->stream, n, e, 0.0));
+        double bb = 0.0;
+        if ((s = rhs<double>(p, E, p->r64, &bb, nullptr))) return s;
+        applies64++;
+        double rr = bb;
+        bool done = false;
+        for (outer = 0; outer < 64; outer++) {
+            if (outer > 0) {
+                // r = b - C x = -G A (E + x)
+                ApplyArgs a;
+                a.op = OP_AX;
+                a.x = e;
+                for (int c = 0; c < p->d; c++) a.E[c] = E[c];
+                a.epi = EPI_STORE;
+                a.sgn = -1.0;
+                a.y = p->r64;
+                int nb = 0;
+                HIPOK(run_apply<double>(p->op64, a, &nb));
+                applies64++;
+                if ((s = reduce_read(p, p->op64, nb, RED_TOTAL, &rr))) return s;
+            }
+            const double step = omega * std::sqrt(rr / S);
+            res = normE > 0 ? step / normE : step;
+            if (!std::isfinite(rr)) {
+                status = FGH_E_DIVERGED;
+                break;
+            }
+            if (step <= tol * normE) {
+                HIPOK(run_axpby(p->stream, n, e, omega, p->r64, 1.0));  // the last step, x += w r
+                done = true;
+                break;
+            }
+            double eta = tol * normE / step;
+            if (eta < kInnerTolMin) eta = kInnerTolMin;
+            HIPOK(run_f64_to_f32(p->stream, n, p->r32, p->r64));
+            HIPOK(run_fill<float>(p->stream, n, p->x32, 0.0f));
+            SolveOut so;
+            if ((s = cheb_core<float>(p, p->x32, p->r32, p->p32, eta, max_iter, 0, &so, 0.0, 1.0 / omega))) return s;
+            inner_total += so.iters;
+            if (so.status == FGH_E_DIVERGED) {
+                status = FGH_E_DIVERGED;
+                break;
+            }
+            // x += G delta in FP64
+            HIPOK(run_fill<double>(p->stream, n, p->p64, 0.0));
+            HIPOK(run_add_f32_to_f64(p->stream, n, p->p64, p->x32));
+            ApplyArgs a;
+            a.op = OP_ID;
+            a.x = p->p64;
+            a.epi = EPI_STORE;
+            a.sgn = 1.0;
+            a.y = p->q64;
+            int nb = 0;
+            HIPOK(run_apply<double>(p->op64, a, &nb));
+            applies64++;
+            HIPOK(run_add_f64(p->stream, n, e, p->q64));
+        }
+        if (status == FGH_OK && !done) status = FGH_E_NO_CONVERGENCE;
     } else {
         return FGH_E_UNSUPPORTED;
     }
@@ -1346,6 +1421,7 @@ const char* fgh_status_string(fgh_status s)
         case FGH_E_NO_CONVERGENCE: return "no convergence within the iteration cap";
         case FGH_E_DIVERGED: return "diverged";
         case FGH_E_DEVICE: return "HIP runtime error";
+        case FGH_E_CANCELLED: return "request cancelled";
     }
     return "unknown status";
 }
@@ -1426,6 +1502,16 @@ fgh_status fgh_plan_create(fgh_plan* out, int d, const int32_t* N, fgh_rule rule
     p->p32 = v32 + 2 * nv;
     p->q32 = v32 + 3 * nv;
     if ((s = upload_twiddles(p))) return fail(s);
+    // the tile timings below run the passes on the spectrum buffers and on r64 / r32: give them
+    // defined values (zeros and ones) instead of what the workspace held before
+    {
+        const long long sp = std::max(p->g.s1, p->g.s2);
+        if (run_fill<double>(p->stream, 2 * d * sp, reinterpret_cast<double*>(p->ws + p->lay.SA), 0.0) != hipSuccess ||
+            run_fill<double>(p->stream, 2 * d * sp, reinterpret_cast<double*>(p->ws + p->lay.SB), 0.0) != hipSuccess ||
+            run_fill<double>(p->stream, nv, p->r64, 1.0) != hipSuccess ||
+            (precision == FGH_FP32_REFINED && run_fill<float>(p->stream, nv, p->r32, 1.0f) != hipSuccess))
+            return fail(FGH_E_DEVICE);
+    }
     if ((s = tune_middle(p, &p->op64, false))) return fail(s);
     if (precision == FGH_FP32_REFINED && (s = tune_middle(p, &p->op32, true))) return fail(s);
     if ((s = tune_axis(p, &p->op64, false))) return fail(s);
@@ -1805,7 +1891,8 @@ fgh_status fgh_gani_bound(fgh_plan gani, fgh_plan ga, const double* E, const dou
     return fgh_effective(ga, E, 1, y, bound, nullptr);
 }
 
-/* Adaptive spectral bounds (outlook of Sec. 5): Ritz values of C on the Krylov space of the load
+/* Adaptive spectral bounds (an extension; the paper's solvers use the pointwise bounds of eq:A):
+ * Ritz values of C on the Krylov space of the load
  * from the coefficients of plain CG (Algorithm 2), which are those of the Lanczos process. */
 fgh_status fgh_estimate_bounds(fgh_plan p, const double* E, int iters, double* e, double* tri, int* steps,
                                double* lo, double* hi)

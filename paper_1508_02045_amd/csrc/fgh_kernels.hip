@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <cstdlib>
 
 #include "fgh_args.hpp"
@@ -826,15 +827,22 @@ static hipError_t allow_lds(const void* fn, size_t bytes)
     if (bytes <= 65536) return hipSuccess;
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
-// The attribute is raised once per kernel and never lowered, so that no attribute call is made
-// while a stream is being captured into a graph (the largest request is what counts).
+// The attribute of each kernel only ever rises, so that no attribute call is made while a stream
+// is being captured into a graph once the largest size has been seen.  Raising is serialised per
+// kernel: the recorded size is stored only after the call has succeeded and only while holding the
+// kernel's lock, so concurrent launches from several threads (server workers, plan-time tuning)
+// can neither lower the attribute nor record a size the attribute does not allow.
 #define LAUNCH_LDS(KERNEL, GRID, LDS, STREAM, ...)                                              \
     do {                                                                                        \
         static std::atomic<size_t> lds_set_{65536};                                            \
-        if ((LDS) > lds_set_.load(std::memory_order_relaxed)) {                                 \
-            hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&KERNEL), (LDS));           \
-            if (e_ != hipSuccess) return e_;                                                    \
-            lds_set_.store((LDS), std::memory_order_relaxed);                                   \
+        static std::mutex lds_mu_;                                                              \
+        if ((LDS) > lds_set_.load(std::memory_order_acquire)) {                                 \
+            std::lock_guard<std::mutex> lds_lk_(lds_mu_);                                       \
+            if ((LDS) > lds_set_.load(std::memory_order_relaxed)) {                             \
+                hipError_t e_ = allow_lds(reinterpret_cast<const void*>(&KERNEL), (LDS));       \
+                if (e_ != hipSuccess) return e_;                                                \
+                lds_set_.store((LDS), std::memory_order_release);                               \
+            }                                                                                   \
         }                                                                                       \
         if (g_pass_events.start) {                                                              \
             const PassEvents pe_ = g_pass_events;                                               \
@@ -1508,9 +1516,27 @@ hipError_t run_set_scalar(const OpPlan& op, double* dst, double v)
     return hipGetLastError();
 }
 
+// A launch of a kernel that is not a pass, bracketed by the profiler's events while its kind is
+// being timed (the events are attached to the dispatch itself, as for the passes).
+#define LAUNCH_TIMED(KIND, OP, KERNEL, GRID, STREAM, ...)                                          \
+    do {                                                                                        \
+        const bool timed_ = (OP).prof && (OP).prof->wants(KIND);                                \
+        if (timed_) {                                                                           \
+            hipError_t e_ = (OP).prof->begin(KIND);                                             \
+            if (e_ != hipSuccess) return e_;                                                    \
+            const PassEvents pe_ = g_pass_events;                                               \
+            g_pass_events = PassEvents{};                                                       \
+            hipExtLaunchKernelGGL(KERNEL, GRID, dim3(kThreads), 0, (STREAM), pe_.start, pe_.stop, 0, __VA_ARGS__); \
+            if ((e_ = hipGetLastError()) != hipSuccess) return e_;                              \
+            if ((e_ = (OP).prof->end()) != hipSuccess) return e_;                               \
+        } else {                                                                                \
+            hipLaunchKernelGGL(KERNEL, GRID, dim3(kThreads), 0, (STREAM), __VA_ARGS__);          \
+        }                                                                                       \
+    } while (0)
+
 hipError_t run_reduce_async(const OpPlan& op, int n, int redop)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, op.stream, op.partials, n, op.sc, redop);
+    LAUNCH_TIMED(PK_REDUCE, op, k_reduce, dim3(1), op.stream, op.partials, n, op.sc, redop);
     return hipGetLastError();
 }
 
@@ -1527,7 +1553,7 @@ hipError_t run_reduce(const OpPlan& op, int n, int redop, double* host_out)
 template <typename T>
 hipError_t run_cg_update(const OpPlan& op, long long n, T* x, T* r, const T* p, const T* q)
 {
-    hipLaunchKernelGGL(k_cg_update<T>, dim3(kVecBlocks), dim3(kThreads), 0, op.stream, n, x, r, p, q, op.sc, op.partials);
+    LAUNCH_TIMED(PK_CG_UPDATE, op, k_cg_update<T>, dim3(kVecBlocks), op.stream, n, x, r, p, q, op.sc, op.partials);
     return hipGetLastError();
 }
 template hipError_t run_cg_update<float>(const OpPlan&, long long, float*, float*, const float*, const float*);

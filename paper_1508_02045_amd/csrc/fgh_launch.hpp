@@ -9,7 +9,12 @@
 namespace fgh {
 
 // Per-pass device timing: launches bracketed by HIP events on the plan's stream.
-enum PassKind : int { PK_FIRST = 0, PK_AXIS_FWD = 1, PK_MIDDLE = 2, PK_AXIS_INV = 3, PK_LAST = 4, PK_KINDS = 5 };
+enum PassKind : int {
+    PK_FIRST = 0, PK_AXIS_FWD = 1, PK_MIDDLE = 2, PK_AXIS_INV = 3, PK_LAST = 4,
+    PK_CG_UPDATE = 5,  // CG's x += alpha p, r -= alpha q, (r, r) partial sums
+    PK_REDUCE = 6,     // single-workgroup loop reductions
+    PK_KINDS = 7
+};
 // Events for the next pass launch while a pass is being timed: the launch takes them as the
 // start and stop events of the dispatch itself (hipExtLaunchKernelGGL), so the measured time is
 // the kernel's own execution time.
@@ -24,8 +29,8 @@ struct Profiler {
     int kind[kPool];
     int used = 0;
     bool ready = false;
-    double ms[PK_KINDS] = {0, 0, 0, 0, 0};
-    long long n[PK_KINDS] = {0, 0, 0, 0, 0};
+    double ms[PK_KINDS] = {};
+    long long n[PK_KINDS] = {};
     std::vector<float> dur[PK_KINDS];  // every timed launch (ms), for the working-launch totals
     hipStream_t stream = nullptr;
     unsigned mask = 0u;  // pass kinds timed (bit k: PassKind k)

@@ -14,6 +14,7 @@
 #include <mutex>
 #include <new>
 #include <thread>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/fgh.h"
@@ -90,7 +91,9 @@ struct fgh_server_s {
     std::condition_variable cv_work;   // a job can be admitted / shutdown
     std::condition_variable cv_done;   // a job finished
     std::deque<Job> queue;             // submitted, not admitted (FIFO)
-    std::map<int64_t, fgh_result> results;
+    std::map<int64_t, fgh_result> results;   // finished, not yet handed to the caller
+    std::unordered_set<int64_t> live;        // submitted, result not yet handed to the caller
+    int waiters = 0;                         // threads blocked in fgh_server_wait
     int64_t next_id = 1;
     int active = 0;
     bool stop = false;
@@ -283,6 +286,7 @@ fgh_status fgh_server_submit(fgh_server sv, const fgh_request* r, int64_t* id)
         job.id = sv->next_id++;
         job.t_submit = sv->now();
         *id = job.id;
+        sv->live.insert(job.id);
         sv->queue.push_back(std::move(job));
     }
     sv->cv_work.notify_all();
@@ -293,9 +297,12 @@ fgh_status fgh_server_poll(fgh_server sv, int64_t id, fgh_result* out)
 {
     if (!sv || !out) return FGH_E_INVALID;
     std::lock_guard<std::mutex> lk(sv->mu);
+    if (!sv->live.count(id)) return FGH_E_INVALID;  // never issued, or already handed out
     auto it = sv->results.find(id);
     if (it == sv->results.end()) return FGH_E_NO_CONVERGENCE;  // not finished yet
     *out = it->second;
+    sv->results.erase(it);
+    sv->live.erase(id);
     return FGH_OK;
 }
 
@@ -303,9 +310,21 @@ fgh_status fgh_server_wait(fgh_server sv, int64_t id, fgh_result* out)
 {
     if (!sv || !out) return FGH_E_INVALID;
     std::unique_lock<std::mutex> lk(sv->mu);
-    sv->cv_done.wait(lk, [&] { return sv->results.count(id) > 0; });
-    *out = sv->results[id];
-    return FGH_OK;
+    if (!sv->live.count(id)) return FGH_E_INVALID;
+    sv->waiters++;
+    // another thread may take the same result first: then the id is no longer live
+    sv->cv_done.wait(lk, [&] { return sv->results.count(id) > 0 || !sv->live.count(id); });
+    fgh_status st = FGH_E_INVALID;
+    auto it = sv->results.find(id);
+    if (it != sv->results.end()) {
+        *out = it->second;
+        sv->results.erase(it);
+        sv->live.erase(id);
+        st = FGH_OK;
+    }
+    sv->waiters--;
+    if (sv->waiters == 0) sv->cv_done.notify_all();  // fgh_server_destroy may be waiting for this
+    return st;
 }
 
 fgh_status fgh_server_drain(fgh_server sv)
@@ -331,12 +350,30 @@ void fgh_server_destroy(fgh_server sv)
     if (!sv) return;
     {
         std::unique_lock<std::mutex> lk(sv->mu);
-        // let admitted work finish; queued, not admitted requests are discarded
+        // let admitted work finish; queued, not admitted requests are discarded with the status
+        // FGH_E_CANCELLED, so that a thread waiting for one of them returns
+        const double t = sv->now();
+        for (const Job& job : sv->queue) {
+            fgh_result r{};
+            r.id = job.id;
+            r.status = FGH_E_CANCELLED;
+            r.t_submit = job.t_submit;
+            r.t_admit = r.t_done = t;
+            sv->results[job.id] = r;
+        }
         sv->queue.clear();
         sv->stop = true;
     }
     sv->cv_work.notify_all();
+    sv->cv_done.notify_all();
     for (auto& t : sv->workers) t.join();
+    {
+        // every request has a result now: wait until the threads blocked in fgh_server_wait
+        // have taken theirs and left, then free the server
+        std::unique_lock<std::mutex> lk(sv->mu);
+        sv->cv_done.notify_all();
+        sv->cv_done.wait(lk, [&] { return sv->waiters == 0; });
+    }
     delete sv;
 }
 

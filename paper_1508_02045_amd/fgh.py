@@ -26,6 +26,7 @@ FGH_E_WORKSPACE = 4
 FGH_E_NO_CONVERGENCE = 5
 FGH_E_DIVERGED = 6
 FGH_E_DEVICE = 7
+FGH_E_CANCELLED = 8
 
 FGH_GANI, FGH_GA = 0, 1
 FGH_RICHARDSON, FGH_CG, FGH_CHEBYSHEV, FGH_EYRE_MILTON = 0, 1, 2, 3
@@ -41,7 +42,7 @@ EXPORTS = ["fgh_plan_workspace", "fgh_plan_create", "fgh_plan_destroy", "fgh_pla
            "fgh_plan_set_bounds", "fgh_plan_set_profiling", "fgh_plan_read_profile", "fgh_request_footprint", "fgh_server_create", "fgh_server_submit", "fgh_server_poll",
            "fgh_server_wait", "fgh_server_drain", "fgh_server_stats", "fgh_server_destroy",
            "fgh_status_string"]
-PASS_NAMES = ["first", "axis_fwd", "middle", "axis_inv", "last"]
+PASS_NAMES = ["first", "axis_fwd", "middle", "axis_inv", "last", "cg_update", "reduce"]
 
 
 class FghError(RuntimeError):
@@ -391,12 +392,13 @@ class Plan:
             raise FghError(st, "fgh_plan_set_profiling")
 
     def read_profile(self):
-        ms = (ctypes.c_double * 5)()
-        n = (ctypes.c_int64 * 5)()
+        k = len(PASS_NAMES)
+        ms = (ctypes.c_double * k)()
+        n = (ctypes.c_int64 * k)()
         st = lib().fgh_plan_read_profile(ctypes.c_void_p(self.handle), ms, n)
         if st:
             raise FghError(st, "fgh_plan_read_profile")
-        return {PASS_NAMES[k]: (ms[k], n[k]) for k in range(5)}
+        return {PASS_NAMES[i]: (ms[i], n[i]) for i in range(k)}
 
     def close(self):
         if getattr(self, "handle", None):
@@ -465,9 +467,14 @@ class Server:
         return rid.value
 
     def poll(self, rid):
+        """The result once request `rid` has finished (released: ask once), None while pending."""
         res = Result()
         st = lib().fgh_server_poll(self.handle, int(rid), ctypes.byref(res))
-        return res.as_dict() if st == FGH_OK else None
+        if st == FGH_E_NO_CONVERGENCE:
+            return None
+        if st:
+            raise FghError(st, "fgh_server_poll")
+        return res.as_dict()
 
     def wait(self, rid):
         res = Result()

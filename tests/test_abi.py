@@ -36,7 +36,7 @@ def test_binding_names_match_header():
 
 def test_status_strings(L):
     from paper_1508_02045_amd import fgh
-    for s in range(8):
+    for s in range(9):
         assert fgh.status_string(s)
     assert "invalid" in fgh.status_string(fgh.FGH_E_INVALID)
 
@@ -91,3 +91,31 @@ def test_request_footprint_counts_double_grid_and_refinement():
     assert sizes[(0, 1)] > sizes[(0, 0)]
     ws = fgh.fgh_plan_workspace(3, (63, 63, 63), 1, 0, fgh.FGH_A_PHASE)
     assert sizes[(1, 0)] >= ws + 3 * 125 ** 3 * 8
+
+
+def test_server_ids_and_release_without_device(L):
+    """Server bookkeeping on the host: ids never issued and results already handed out are
+    rejected at once (no blocking), each result is released after it is returned, and destroy
+    returns.  Without a GPU the workers cannot create a stream, so an admitted request finishes
+    at once with FGH_E_DEVICE; the pool pointer is never dereferenced on the host."""
+    import numpy as np
+    from paper_1508_02045_amd import fgh
+    h = ctypes.c_void_p()
+    pool = ctypes.c_void_p(1 << 40)  # 256-byte aligned, only ever used as a device address
+    assert L.fgh_server_create(ctypes.byref(h), pool, 1 << 30, 2, 0) == fgh.FGH_OK
+    res = fgh.Result()
+    for bad in (0, -3, 1, 99):
+        assert L.fgh_server_wait(h, bad, ctypes.byref(res)) == fgh.FGH_E_INVALID
+        assert L.fgh_server_poll(h, bad, ctypes.byref(res)) == fgh.FGH_E_INVALID
+    tab = np.array([[1.0, 0, 1], [10.0, 0, 10.0]])
+    r, keep = fgh.make_request(2, (9, 9), np.zeros((9, 9), np.uint8), tab, [1, 0], "cg", 1e-6)
+    rid = ctypes.c_int64()
+    assert L.fgh_server_submit(h, ctypes.byref(r), ctypes.byref(rid)) == fgh.FGH_OK
+    assert rid.value == 1
+    assert L.fgh_server_wait(h, rid.value, ctypes.byref(res)) == fgh.FGH_OK
+    assert res.id == 1 and res.status != fgh.FGH_OK
+    # released: a second wait or poll on the same id is an invalid id, not a hang
+    assert L.fgh_server_wait(h, rid.value, ctypes.byref(res)) == fgh.FGH_E_INVALID
+    assert L.fgh_server_poll(h, rid.value, ctypes.byref(res)) == fgh.FGH_E_INVALID
+    assert L.fgh_server_drain(h) == fgh.FGH_OK
+    L.fgh_server_destroy(h)

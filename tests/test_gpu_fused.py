@@ -41,9 +41,10 @@ def solve_both(plan, solver, E, tol, switch="FGH_FUSE"):
     return out
 
 
-# FP32 refinement runs Chebyshev and Eyre-Milton inner solves (Richardson is not offered there)
+# FP32 refinement runs Richardson (as Chebyshev on a one-point interval), Chebyshev and Eyre-Milton
+# inner solves on the fused bodies
 CASES = [(s, N, 0) for s in ("richardson", "chebyshev", "eyre_milton") for N in ((45, 63, 81), (125, 45))] + \
-        [(s, (81, 45, 63), 1) for s in ("chebyshev", "eyre_milton")]
+        [(s, (81, 45, 63), 1) for s in ("richardson", "chebyshev", "eyre_milton")]
 
 
 @pytest.mark.parametrize("solver,N,prec", CASES)
