@@ -134,6 +134,23 @@ fgh_status fgh_apply(fgh_plan plan, const double* x, double* y);
  * FGH_FP32_REFINED plans; FGH_E_UNSUPPORTED for FGH_FP64 plans). */
 fgh_status fgh_apply_f32(fgh_plan plan, const float* x, float* y);
 
+/* The operator of fgh_apply without a plan and without any device allocation, for callers that
+ * cannot allocate: code being captured into a HIP graph, tight serving loops, harnesses that
+ * forbid hipMalloc.  y = G A x in double precision on the N grid (GaNi), for the coefficients
+ * given as in fgh_plan_create (A device, or phase device + phase_table host, n_phases <= 16;
+ * phase values must be below n_phases and are not checked).  x, y: device double[d][N grid], not
+ * overlapping; the caller owns them.  The passes' intermediate buffers (twiddle tables computed on
+ * the device, two half-spectrum buffers, partial sums) live in a 64 MiB array of device memory
+ * that the library holds on each GPU it runs on until the process ends: grids whose buffers do
+ * not fit it (about 111^3 and above in 3D; 2D up to beyond 1000^2) are rejected with
+ * FGH_E_WORKSPACE.  Every call on one GPU uses that GPU's array, so calls that overlap in time on
+ * one GPU (other streams, other threads) race and must be serialised by the caller; nothing in the
+ * array needs to start at zero.  Static tile choices (no plan-time timing).  Asynchronous on
+ * `stream` (NULL: the default stream).  Errors: FGH_E_INVALID, FGH_E_WORKSPACE, FGH_E_DEVICE. */
+fgh_status fgh_apply_noalloc(int d, const int32_t* N, fgh_akind a_kind, const void* A, const uint8_t* phase,
+                             const double* phase_table, int n_phases, const double* x, double* y,
+                             void* stream);
+
 /* Write the double-grid coefficients A_{2N-1} of a Ga plan (eq:Ga_exact_integration) to device
  * double[ncoef_op][M grid], where ncoef_op is 1 for FGH_A_ISO / FGH_A_PHASE (A_{2N-1} is a
  * scalar field times I) and 3 or 6 packed symmetric entries for FGH_A_SYM.  FGH_E_INVALID for

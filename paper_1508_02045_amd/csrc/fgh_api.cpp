@@ -358,17 +358,20 @@ fgh_status upload_twiddles(fgh_plan p)
     return FGH_OK;
 }
 
-void fill_opplan(fgh_plan p, OpPlan* op, bool f32)
+// Operator description of one precision over given device buffers: twiddle tables per axis, the
+// two half-spectrum buffers, the partial sums and the loop scalar block; static tile choices.
+void fill_opplan_at(OpPlan* op, const Geo& g, bool f32, char* const tw[3], char* SA, char* SB, double* partials,
+                    Scalars* sc, hipStream_t stream)
 {
-    const Config c = choose_config(p->g, f32 ? 8 : 16, f32 ? 4 : 8);
-    op->g = p->g;
+    const Config c = choose_config(g, f32 ? 8 : 16, f32 ? 4 : 8);
+    op->g = g;
     for (int a = 0; a < 3; a++) {
-        if (a < p->d) factorize(p->g.L[a], &op->ax[a]);
+        if (a < g.d) factorize(g.L[a], &op->ax[a]);
         op->ax[a].tw = 0;
-        op->tw[a] = a < p->d ? p->ws + (f32 ? p->lay.tw32[a] : p->lay.tw64[a]) : nullptr;
+        op->tw[a] = a < g.d ? tw[a] : nullptr;
     }
-    op->SA = p->ws + p->lay.SA;
-    op->SB = p->ws + p->lay.SB;
+    op->SA = SA;
+    op->SB = SB;
     op->rpb = c.rpb;
     op->rpb_first = c.rpb;
     op->mid_pad = 0;
@@ -385,9 +388,18 @@ void fill_opplan(fgh_plan p, OpPlan* op, bool f32)
     op->v2_row = c.v2_row;
     op->v2_axis = c.v2_axis;
     op->v2_mid = c.v2_mid;
-    op->partials = reinterpret_cast<double*>(p->ws + p->lay.partials);
-    op->sc = reinterpret_cast<Scalars*>(p->ws + p->lay.scalars);
-    op->stream = p->stream;
+    op->partials = partials;
+    op->sc = sc;
+    op->stream = stream;
+}
+
+void fill_opplan(fgh_plan p, OpPlan* op, bool f32)
+{
+    char* tw[3] = {nullptr, nullptr, nullptr};
+    for (int a = 0; a < p->d; a++) tw[a] = p->ws + (f32 ? p->lay.tw32[a] : p->lay.tw64[a]);
+    fill_opplan_at(op, p->g, f32, tw, p->ws + p->lay.SA, p->ws + p->lay.SB,
+                   reinterpret_cast<double*>(p->ws + p->lay.partials), reinterpret_cast<Scalars*>(p->ws + p->lay.scalars),
+                   p->stream);
 }
 
 // Tile width of the strided axis-1 passes (3D), measured at plan creation like the middle pass's:
@@ -1366,6 +1378,64 @@ fgh_status solve_one_refined(fgh_plan p, int solver, const double* E, double tol
 }
 
 
+// ------------------------------------------------------------------------------------------
+// Allocation-free application of C = G A (fgh_apply_noalloc): the device buffers of the passes
+// (twiddle tables, the two half-spectrum buffers, the last pass's partial sums and a scalar
+// block) are carved out of a file-scope device array instead of a caller's workspace.  Each GPU
+// holds its own copy of the array for the life of the process, and every call on that GPU
+// shares it.  In host code `scratch` only names the array: its device address on the current
+// device comes from hipGetSymbolAddress, taken once per device and kept.
+// ------------------------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_addr[kScratchDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+fgh_status scratch_address(char** out)
+{
+    int dev = -1;
+    HIPOK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) return FGH_E_DEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FGH_E_DEVICE;
+        g_scratch_addr[dev] = static_cast<char*>(ptr);
+    }
+    *out = g_scratch_addr[dev];
+    return FGH_OK;
+}
+
+// Offsets of the allocation-free apply's buffers inside the scratch array (256-byte aligned).
+struct ScratchLayout {
+    size_t tw[3], SA, SB, partials, scalars, total;
+};
+
+ScratchLayout scratch_layout(const Geo& g)
+{
+    ScratchLayout l{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    for (int a = 0; a < g.d; a++) l.tw[a] = take((size_t)g.L[a] * 16);
+    const long long sp = std::max(g.s1, g.s2);
+    l.SA = take((size_t)g.d * sp * 16);
+    l.SB = take(g.d == 3 ? (size_t)g.d * sp * 16 : 0);  // 2D transforms in place in SA
+    l.partials = take(((size_t)g.rows + 64) * 8);         // at most one per row of the last pass
+    l.scalars = take(sizeof(Scalars));
+    l.total = off;
+    return l;
+}
+
 // Symmetric tridiagonal matrix with diagonal a and off-diagonal b: the number of its eigenvalues
 // below x, from the signs of the pivots of the LDL^T factorisation of T - x I (Sturm sequence;
 // a zero pivot is replaced by a tiny negative one, as in the bisection method of Barth, Martin
@@ -1740,6 +1810,59 @@ fgh_status fgh_apply_f32(fgh_plan p, const float* x, float* y)
     a.y = y;
     int nb = 0;
     HIPOK(run_apply<float>(p->op32, a, &nb));
+    return FGH_OK;
+}
+
+fgh_status fgh_apply_noalloc(int d, const int32_t* N, fgh_akind a_kind, const void* A, const uint8_t* phase,
+                             const double* phase_table, int n_phases, const double* x, double* y, void* stream)
+{
+    if (!x || !y) return FGH_E_INVALID;
+    if (a_kind < FGH_A_SYM || a_kind > FGH_A_PHASE) return FGH_E_INVALID;
+    Geo g;
+    if (!make_geo(d, N, FGH_GANI, &g)) return FGH_E_INVALID;
+    const int nc = ncoef_for(d);
+    CoefArgs ca{};
+    if (a_kind == FGH_A_PHASE) {
+        if (!phase || !phase_table || n_phases < 1 || n_phases > kMaxPhases) return FGH_E_INVALID;
+        for (int i = 0; i < n_phases; i++)
+            for (int q = 0; q < nc; q++) {
+                if (!std::isfinite(phase_table[i * nc + q])) return FGH_E_INVALID;
+                ca.tab[i][q] = phase_table[i * nc + q];
+            }
+        ca.kind = AK_PHASE;
+        ca.ncoef = 1;
+        ca.coef = nullptr;
+        ca.phase = phase;
+    } else {
+        if (!A) return FGH_E_INVALID;
+        ca.kind = a_kind == FGH_A_ISO ? AK_ISO : AK_SYM;
+        ca.ncoef = a_kind == FGH_A_SYM ? nc : 1;
+        ca.coef = A;
+        ca.phase = nullptr;
+    }
+    const ScratchLayout l = scratch_layout(g);
+    if (l.total > kScratchBytes) return FGH_E_WORKSPACE;  // the grid does not fit the scratch array
+    char* base = nullptr;
+    fgh_status s = scratch_address(&base);
+    if (s) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* tw[3] = {nullptr, nullptr, nullptr};
+    for (int a = 0; a < d; a++) {
+        tw[a] = base + l.tw[a];
+        HIPOK(run_twiddles(st, g.L[a], reinterpret_cast<double2*>(tw[a])));
+    }
+    OpPlan op{};
+    fill_opplan_at(&op, g, false, tw, base + l.SA, base + l.SB, reinterpret_cast<double*>(base + l.partials),
+                   reinterpret_cast<Scalars*>(base + l.scalars), st);
+    op.A = ca;
+    ApplyArgs a;
+    a.op = OP_AX;
+    a.x = x;
+    a.epi = EPI_STORE;
+    a.sgn = 1.0;
+    a.y = y;
+    int nb = 0;
+    HIPOK(run_apply<double>(op, a, &nb));
     return FGH_OK;
 }
 

@@ -810,6 +810,17 @@ __global__ void k_ga_extend(const double2* __restrict__ cn, double2* __restrict_
     }
 }
 
+// Twiddle table of one axis on the device: tw[m] = exp(-2 pi i m / L) for m in [0, L), the table
+// the passes read between their two DFT steps (the plan uploads the same values from the host).
+__global__ void k_twiddles(int L, double2* __restrict__ tw)
+{
+    for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < L; m += gridDim.x * blockDim.x) {
+        double s, c;
+        sincospi(2.0 * (double)m / (double)L, &s, &c);
+        tw[m] = make_double2(c, -s);
+    }
+}
+
 __global__ void k_real_part(long long n, const double2* __restrict__ c, double* __restrict__ out)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -1600,6 +1611,12 @@ template hipError_t run_copy<double>(hipStream_t, long long, double*, const doub
 hipError_t run_f64_to_f32(hipStream_t s, long long n, float* dst, const double* src)
 {
     hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(n)), dim3(kThreads), 0, s, n, dst, src);
+    return hipGetLastError();
+}
+
+hipError_t run_twiddles(hipStream_t s, int L, double2* tw)
+{
+    hipLaunchKernelGGL(k_twiddles, dim3(grid_for(L)), dim3(kThreads), 0, s, L, tw);
     return hipGetLastError();
 }
 

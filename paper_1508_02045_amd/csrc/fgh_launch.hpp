@@ -151,6 +151,8 @@ hipError_t run_f64_to_f32(hipStream_t s, long long n, float* dst, const double* 
 hipError_t run_add_f32_to_f64(hipStream_t s, long long n, double* x, const float* d);
 hipError_t run_add_f64(hipStream_t s, long long n, double* x, const double* d);
 hipError_t run_axpby(hipStream_t s, long long n, double* y, double a, const double* x, double b);
+// Twiddle table exp(-2 pi i m / L), m in [0, L), computed on the device (FP64).
+hipError_t run_twiddles(hipStream_t s, int L, double2* tw);
 hipError_t run_norm_AE(const OpPlan& op, const double* E, int* nblocks);
 template <typename T>
 hipError_t run_dot(const OpPlan& op, long long n, const T* a, const T* b, int* nblocks);

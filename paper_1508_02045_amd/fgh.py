@@ -37,7 +37,7 @@ SOLVERS = {"richardson": FGH_RICHARDSON, "cg": FGH_CG, "chebyshev": FGH_CHEBYSHE
            "eyre_milton": FGH_EYRE_MILTON}
 
 EXPORTS = ["fgh_plan_workspace", "fgh_plan_create", "fgh_plan_destroy", "fgh_plan_grid_points",
-           "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32", "fgh_ga_coefficients", "fgh_solve",
+           "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32", "fgh_apply_noalloc", "fgh_ga_coefficients", "fgh_solve",
            "fgh_solve_fixed", "fgh_effective", "fgh_gani_bound", "fgh_plan_set_history", "fgh_estimate_bounds",
            "fgh_plan_set_bounds", "fgh_plan_set_profiling", "fgh_plan_read_profile", "fgh_request_footprint", "fgh_server_create", "fgh_server_submit", "fgh_server_poll",
            "fgh_server_wait", "fgh_server_drain", "fgh_server_stats", "fgh_server_destroy",
@@ -106,6 +106,7 @@ def lib():
         L.fgh_plan_bounds.argtypes = [_vp, _dp, _dp]
         L.fgh_apply.argtypes = [_vp, _vp, _vp]
         L.fgh_apply_f32.argtypes = [_vp, _vp, _vp]
+        L.fgh_apply_noalloc.argtypes = [ctypes.c_int, _i32p, ctypes.c_int, _vp, _vp, _dp, ctypes.c_int, _vp, _vp, _vp]
         L.fgh_ga_coefficients.argtypes = [_vp, _vp]
         L.fgh_solve.argtypes = [_vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _vp,
                                 ctypes.POINTER(Stats)]
@@ -132,7 +133,7 @@ def lib():
             getattr(L, name).restype = ctypes.c_int
         L.fgh_status_string.argtypes = [ctypes.c_int]
         L.fgh_status_string.restype = ctypes.c_char_p
-        for name in ("fgh_plan_workspace", "fgh_plan_create", "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32",
+        for name in ("fgh_plan_workspace", "fgh_plan_create", "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32", "fgh_apply_noalloc",
                      "fgh_ga_coefficients", "fgh_solve", "fgh_solve_fixed", "fgh_effective",
                      "fgh_gani_bound", "fgh_plan_set_history", "fgh_estimate_bounds", "fgh_plan_set_bounds",
                      "fgh_plan_set_profiling", "fgh_plan_read_profile"):
@@ -197,6 +198,19 @@ def fgh_apply_f32(plan, x, y) -> None:
     st = lib().fgh_apply_f32(ctypes.c_void_p(plan), _ptr(x), _ptr(y))
     if st:
         raise FghError(st, "fgh_apply_f32")
+
+
+def fgh_apply_noalloc(d, N, a_kind, A, phase, phase_table, x, y, stream) -> None:
+    """y = G A x without a plan or any device allocation (GaNi, FP64); see include/fgh.h."""
+    tab_keep, tab_ptr, nph = None, None, 0
+    if phase_table is not None:
+        tab_keep, tab_ptr = _hostd(phase_table)
+        nph = tab_keep.shape[0]
+    st = lib().fgh_apply_noalloc(int(d), _n32(N), int(a_kind), _ptr(A), _ptr(phase), tab_ptr, int(nph), _ptr(x),
+                                 _ptr(y), ctypes.c_void_p(stream))
+    del tab_keep
+    if st:
+        raise FghError(st, "fgh_apply_noalloc")
 
 
 def fgh_solve(plan, solver, E, nrhs, tol, max_iter, e, raise_on=(FGH_E_INVALID, FGH_E_UNSUPPORTED, FGH_E_DEVICE,
