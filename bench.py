@@ -75,7 +75,7 @@ def apply_bytes(N, p_bytes, a_bytes=1):
     first pass reads x and the coefficients (a bytes per point) and writes the half spectrum, each
     strided / middle pass reads and writes it, the last pass reads it and writes y."""
     d, npts, F, S = geometry(N, p_bytes)
-    inner = 2 * d - 2  # passes between the first and the last, each S in and S out
+    inner = 2 * d - 3  # passes between the first and the last (3D: axis 1, axis 0, axis 1), each S in and out
     return 2 * F + a_bytes * npts + 2 * S + inner * 2 * S
 
 
