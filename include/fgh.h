@@ -180,6 +180,26 @@ fgh_status fgh_solve(fgh_plan plan, fgh_solver solver, const double* E, int nrhs
 fgh_status fgh_solve_fixed(fgh_plan plan, fgh_solver solver, const double* E, int nrhs,
                            int iters, double* e, fgh_stats* stats);
 
+/* Several independent solves of one shape at once (serving; not a method of the paper): plans[k]
+ * (distinct, same d, N, rule and precision) each solve C e = b for the load E[k] (host
+ * double[n][d]) to tol[k] with `solver`, as fgh_solve on that plan with nrhs = 1 would; e[k]:
+ * device double[d][grid] output of plan k.  For FGH_FP32_REFINED plans of a size-specialised
+ * grid (45, 63, 81, 125, 135, 243 along every axis) with conjugate gradients or Eyre-Milton, the
+ * inner FP32 loop bodies of up to 8 members run in shared launches (one launch per pass for all
+ * of them, one grid row per member) while each member's outer FP64 steps stay its own; a
+ * member's iterates, counts and results are bitwise those of fgh_solve on its plan alone.  Other
+ * combinations solve the members one after another.  retire (may be NULL) is called as
+ * retire(user, k) on the calling thread as soon as member k's e[k] and stats[k] are final, before
+ * the others have finished; after that call plan k is no longer used by this call.  All work runs
+ * on plans[0]'s internal stream after every member's stream has drained; blocks until done;
+ * plans[0]'s captured loop graph is replaced.  stats: host fgh_stats[n] or NULL.  Returns the
+ * worst member status; FGH_E_INVALID for mismatched, repeated or NULL plans, n outside [1, 64]
+ * or a tolerance outside (0, 1). */
+typedef void (*fgh_retire_fn)(void* user, int member);
+fgh_status fgh_solve_batch(fgh_plan* plans, int n, fgh_solver solver, const double* E, const double* tol,
+                           int max_iter, double* const* e, fgh_stats* stats, fgh_retire_fn retire,
+                           void* user);
+
 /* Effective quantities from solved fluctuations (eq:ev_bounds), accumulated in double:
  *   bilinear  host double[nrhs][nrhs] (may be NULL): B[i][j] = (A(E_j + e_j), E_i + e_i)_2;
  *             with the d unit loads this is A_H (eq:ev_bounds_Ga / eq:GaNi).

@@ -171,6 +171,7 @@ bool make_geo(int d, const int32_t* N, int rule, Geo* g)
 
 struct Layout {
     size_t tw64[3], tw32[3], SA, SB, vec64, vec32, partials, scalars, mask, coef64, coef32, sinc[3], twN[3], twM[3];
+    size_t slab;  // argument tables of batched launches led by this plan
     size_t total;
     long long npart;
 };
@@ -213,6 +214,7 @@ Layout make_layout(const Geo& g, const int32_t* N, int rule, int prec, int akind
     l.npart = np + 64;
     l.partials = take((size_t)l.npart * 8);
     l.scalars = take(sizeof(Scalars));
+    l.slab = take(kBatchSlabBytes);
     l.mask = take(16);
     const int ncoef_op = (akind == FGH_A_SYM) ? ncoef_for(d) : 1;
     l.coef64 = take(rule == FGH_GA ? (size_t)ncoef_op * g.npts * 8 : 0);
@@ -1436,6 +1438,421 @@ ScratchLayout scratch_layout(const Geo& g)
     return l;
 }
 
+// ------------------------------------------------------------------------------------------
+// Batches: FP32-refined solves of one shape whose inner FP32 loops share launches.  Each member
+// keeps its own plan, buffers, loop scalars and partial sums; its outer FP64 steps are the
+// plan's own (solve_one_refined); its inner loop bodies run in batched launches whose
+// per-member arithmetic is that of the plan alone, so every member's iterates, counts and
+// results are those of fgh_solve on its plan.
+// ------------------------------------------------------------------------------------------
+struct BatchMember {
+    fgh_plan p;
+    int index;            // position in the caller's arrays
+    const double* E;      // load (host [d])
+    double tol;
+    double* e;            // device [d][grid]
+    double normE = 0.0, normb = 0.0, rr = 0.0, res = 0.0, dnorm = 0.0;
+    int outer = 0, inner = 0, applies = 0, status = FGH_OK;
+    bool done = false;    // stopping test met
+    bool active = true;   // still iterating
+    double eta = 0.0;     // inner relative tolerance of the current outer step
+};
+
+// Plans whose loop bodies can share launches: same grid, rule, precision and launch configuration.
+bool same_launch_shape(fgh_plan a, fgh_plan b)
+{
+    if (a->d != b->d || a->rule != b->rule || a->prec != b->prec) return false;
+    for (int k = 0; k < 3; k++)
+        if (a->N[k] != b->N[k]) return false;
+    const OpPlan& x = a->op32;
+    const OpPlan& y = b->op32;
+    return x.rpb == y.rpb && x.rpb_first == y.rpb_first && x.rpb_fused == y.rpb_fused && x.P_axis == y.P_axis &&
+           x.P_mid == y.P_mid && x.mid_pad == y.mid_pad && x.lds_first_v2 == y.lds_first_v2 &&
+           x.lds_last_v2 == y.lds_last_v2 && x.lds_fused == y.lds_fused && x.lds_axis == y.lds_axis &&
+           x.lds_mid == y.lds_mid && x.v2_row == y.v2_row && x.v2_axis == y.v2_axis && x.v2_mid == y.v2_mid;
+}
+
+// Copies the members' argument blocks into the lead plan's table region (one upload per inner
+// solve; the tables do not change between loop bodies: the loop's scalars live on the device).
+fgh_status upload_tables(fgh_plan lead, int nb, const std::vector<ApplyBundle<float>>& bu,
+                         const std::vector<ReduceArgs>& r1, const std::vector<ReduceArgs>& r2,
+                         const std::vector<UpdateArgs<float>>& up, hipStream_t s, BatchTables<float>* dev)
+{
+    std::vector<char> host(kBatchSlabBytes, 0);
+    BatchTables<float> h = batch_tables<float>(host.data());
+    *dev = batch_tables<float>(lead->ws + lead->lay.slab);
+    for (int k = 0; k < nb; k++) {
+        h.fa[k] = bu[k].fa;
+        h.xf[k] = bu[k].xf;
+        h.xi[k] = bu[k].xi;
+        h.ma[k] = bu[k].ma;
+        h.la[k] = bu[k].la;
+        if (!r1.empty()) h.red[k] = r1[k];
+        if (!r2.empty()) h.red2[k] = r2[k];
+        if (!up.empty()) h.upd[k] = up[k];
+    }
+    HIPOK(hipMemcpyAsync(lead->ws + lead->lay.slab, host.data(), h.bytes, hipMemcpyHostToDevice, s));
+    HIPOK(hipStreamSynchronize(s));  // the host image is released on return
+    return FGH_OK;
+}
+
+// Loop bodies of a batch in chunks, as run_loop does for one plan (graph replay when the stream
+// can be captured); the device stops each member by its own test; returns when all have stopped,
+// with each member's count, test quantity (relative to scale[k]) and status.
+template <typename Body>
+fgh_status run_loop_batch(fgh_plan lead, const std::vector<BatchMember*>& A, hipStream_t s, Body body, uint64_t key,
+                          const std::vector<double>& scale, std::vector<SolveOut>* outs)
+{
+    const bool use_graph = graphs_enabled() && s != nullptr;
+    if (use_graph && (lead->gkey != key || !lead->gexec)) {
+        drop_graph(lead);
+        HIPOK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t ce = hipSuccess;
+        for (int k = 0; k < kGraphBodies && ce == hipSuccess; k++) ce = body();
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(s, &g);
+        if (ce != hipSuccess || ee != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return FGH_E_DEVICE;
+        }
+        lead->graph = g;
+        HIPOK(hipGraphInstantiate(&lead->gexec, g, nullptr, nullptr, 0));
+        lead->gkey = key;
+    }
+    const int nb = (int)A.size();
+    int chunk = 1;
+    for (;;) {
+        for (int k = 0; k < chunk; k++) {
+            if (use_graph) {
+                HIPOK(hipGraphLaunch(lead->gexec, s));
+            } else {
+                for (int b = 0; b < kGraphBodies; b++) HIPOK(body());
+            }
+        }
+        for (int k = 0; k < nb; k++)
+            HIPOK(hipMemcpyAsync(A[k]->p->host_buf, A[k]->p->op32.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+        HIPOK(hipStreamSynchronize(s));
+        bool all = true;
+        for (int k = 0; k < nb; k++) all = all && reinterpret_cast<const Scalars*>(A[k]->p->host_buf)->done != 0;
+        if (all) break;
+        if (chunk < 4) chunk *= 2;
+    }
+    outs->assign(nb, SolveOut{});
+    for (int k = 0; k < nb; k++) {
+        const Scalars* h = reinterpret_cast<const Scalars*>(A[k]->p->host_buf);
+        SolveOut& o = (*outs)[k];
+        o.iters = h->m;
+        o.res = scale[k] > 0 ? h->last / scale[k] : h->last;
+        o.status = h->done == 3 ? FGH_E_DIVERGED : h->done == 2 ? FGH_E_NO_CONVERGENCE : FGH_OK;
+    }
+    return FGH_OK;
+}
+
+uint64_t batch_key(uint64_t kind, const std::vector<BatchMember*>& A)
+{
+    uint64_t h = key_of({kind, (uint64_t)A.size()});
+    for (const BatchMember* m : A) h = mix_key(h, bits(m->p));
+    return h;
+}
+
+// The inner FP32 CG solves C delta = r32 of the active members (cg_core's set-up per member,
+// then bodies in shared launches).
+fgh_status cg_inner_batch(const std::vector<BatchMember*>& A, int max_iter, hipStream_t s, std::vector<SolveOut>* outs)
+{
+    const int nb = (int)A.size();
+    std::vector<ApplyBundle<float>> bu(nb);
+    std::vector<ReduceArgs> r1(nb), r2(nb);
+    std::vector<UpdateArgs<float>> up(nb);
+    std::vector<double> scale(nb);
+    for (int k = 0; k < nb; k++) {
+        fgh_plan p = A[k]->p;
+        const OpPlan& op = p->op32;
+        const long long n = (long long)p->d * p->g.npts;
+        const double S = (double)p->g.npts;
+        HIPOK(run_copy<float>(s, n, p->p32, p->r32));
+        double bb = 0.0;
+        int nbk = 0;
+        HIPOK(run_dot<float>(op, n, p->r32, p->r32, &nbk));
+        fgh_status st = reduce_read(p, op, nbk, RED_TOTAL, &bb);
+        if (st) return st;
+        scale[k] = std::sqrt(bb / S);
+        HIPOK(run_init_loop(op, bb, 0.0, 0.0, A[k]->eta * scale[k], S, 0.0, 0.0, 0.0, max_iter));
+        ApplyArgs a;
+        a.op = OP_AP_CG;
+        a.p_cg = p->p32;
+        a.r_cg = p->r32;
+        a.epi = EPI_CG;
+        a.eq = p->q32;
+        a.ep = p->p32;
+        a.loop = true;
+        HIPOK(build_bundle<float>(op, a, &bu[k]));
+        r1[k] = ReduceArgs{op.partials, (int)bu[k].nblk_last, op.sc};
+        r2[k] = ReduceArgs{op.partials, vec_blocks(), op.sc};
+        up[k] = UpdateArgs<float>{n, p->x32, p->r32, p->p32, p->q32, op.sc, op.partials};
+    }
+    BatchTables<float> t;
+    fgh_plan lead = A[0]->p;
+    fgh_status st = upload_tables(lead, nb, bu, r1, r2, up, s, &t);
+    if (st) return st;
+    const OpPlan& op0 = lead->op32;
+    auto body = [&]() -> hipError_t {
+        hipError_t e = run_apply_batch<float>(op0, bu[0], t, nb);
+        if (e != hipSuccess) return e;
+        if ((e = run_reduce_batch(s, t.red, nb, RED_CG_ALPHA)) != hipSuccess) return e;
+        if ((e = run_cg_update_batch<float>(s, t.upd, nb)) != hipSuccess) return e;
+        return run_reduce_batch(s, t.red2, nb, RED_CG_END);
+    };
+    return run_loop_batch(lead, A, s, body, batch_key(21, A), scale, outs);
+}
+
+// The inner FP32 Eyre-Milton correction solves of the active members (em_core's correction
+// form: delta = (A + wI)^{-1}(I - 2G^)(A - wI) delta + r32 from delta = 0), fused bodies.
+fgh_status em_inner_batch(const std::vector<BatchMember*>& A, int max_iter, hipStream_t s, std::vector<SolveOut>* outs)
+{
+    const int nb = (int)A.size();
+    std::vector<ApplyBundle<float>> pro(nb), bu(nb);
+    std::vector<ReduceArgs> r1(nb);
+    std::vector<double> scale(nb);
+    bool defer = false;
+    for (int k = 0; k < nb; k++) {
+        fgh_plan p = A[k]->p;
+        const OpPlan& op = p->op32;
+        const double S = (double)p->g.npts;
+        const double omega = std::sqrt(p->cA * p->CA);
+        scale[k] = A[k]->dnorm;
+        HIPOK(run_init_loop(op, 0.0, 0.0, 0.0, A[k]->eta * A[k]->dnorm, S, 1e12 * (A[k]->dnorm > 0 ? A[k]->dnorm : 1.0),
+                            0.0, 0.0, max_iter));
+        if (!fuse_loop(p, op)) return FGH_E_UNSUPPORTED;
+        ApplyArgs a;
+        a.op = OP_EM;
+        a.x = p->x32;
+        a.omega = omega;
+        a.mult = MULT_EM;
+        a.epi = EPI_EM;
+        a.ex = p->x32;
+        a.src = p->r32;
+        for (int c = 0; c < p->d; c++) a.E[c] = A[k]->E[c];
+        a.loop = true;
+        ApplyArgs ap = a;  // the loop's prologue: the first body's first pass alone
+        ap.first_only = true;
+        ap.loop = false;
+        HIPOK(build_bundle<float>(op, ap, &pro[k]));
+        a.skip_first = true;
+        a.next_op = OP_EM;
+        defer = defer_reduction(op, true);
+        a.defer_redop = defer ? RED_STEP_END : -1;
+        HIPOK(build_bundle<float>(op, a, &bu[k]));
+        bu[k].fa = pro[k].fa;  // the body skips its first pass: the table slot holds the prologue's
+        r1[k] = ReduceArgs{op.partials, (int)bu[k].nblk_last, op.sc};
+    }
+    BatchTables<float> t;
+    fgh_plan lead = A[0]->p;
+    fgh_status st = upload_tables(lead, nb, bu, r1, {}, {}, s, &t);
+    if (st) return st;
+    const OpPlan& op0 = lead->op32;
+    HIPOK(run_apply_batch<float>(op0, pro[0], t, nb));
+    auto body = [&]() -> hipError_t {
+        hipError_t e = run_apply_batch<float>(op0, bu[0], t, nb);
+        if (e != hipSuccess || defer) return e;
+        return run_reduce_batch(s, t.red, nb, RED_STEP_END);
+    };
+    return run_loop_batch(lead, A, s, body, batch_key(defer ? 23 : 22, A), scale, outs);
+}
+
+// rel_res_true of a finished member (as solve_common reports it) and its stats.
+fgh_status finish_member(BatchMember* m, fgh_stats* st, double seconds)
+{
+    fgh_plan p = m->p;
+    st->iters = m->inner;
+    st->outer_iters = m->outer;
+    st->fp64_applies = m->applies;
+    st->status = m->status;
+    st->rel_res_recursive = m->res;
+    st->seconds = seconds;
+    st->c_A = p->cA;
+    st->C_A = p->CA;
+    double bb = 0.0;
+    fgh_status s = rhs<double>(p, m->E, p->r64, &bb, nullptr);
+    if (s) return s;
+    double rt = 0.0;
+    if ((s = true_residual(p, m->E, m->e, bb, &rt))) return s;
+    st->rel_res_true = rt;
+    return FGH_OK;
+}
+
+// The outer FP64 defect-correction steps of solve_one_refined for every member in lockstep, with
+// the inner solves of the members still iterating batched.  retire(k) is called for member k as
+// soon as its result is final.
+fgh_status refined_batch(std::vector<BatchMember>& ms, fgh_solver solver, int max_iter, hipStream_t s,
+                         fgh_stats* stats, const std::function<void(int)>& retire)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    auto finish = [&](BatchMember& m) -> fgh_status {
+        if (solver == FGH_EYRE_MILTON) {  // the fluctuation x - E
+            fgh_plan p = m.p;
+            const long long n = (long long)p->d * p->g.npts;
+            double negE[3] = {-m.E[0], -m.E[1], p->d == 3 ? -m.E[2] : 0.0};
+            HIPOK(run_fill_field<double>(s, p->d, p->g.npts, p->q64, negE));
+            HIPOK(run_add_f64(s, n, m.e, p->q64));
+        }
+        if (m.status == FGH_OK && !m.done) m.status = FGH_E_NO_CONVERGENCE;
+        m.active = false;
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        fgh_stats st{};
+        fgh_status r = finish_member(&m, &st, secs);
+        if (r) return r;
+        HIPOK(hipStreamSynchronize(s));
+        if (stats) stats[m.index] = st;
+        if (retire) retire(m.index);
+        return FGH_OK;
+    };
+    const int outer_cap = solver == FGH_EYRE_MILTON ? 200 : 64;
+    // set-up per member (solve_one_refined's first steps)
+    for (BatchMember& m : ms) {
+        fgh_plan p = m.p;
+        const long long n = (long long)p->d * p->g.npts;
+        const double S = (double)p->g.npts;
+        for (int c = 0; c < p->d; c++) m.normE += m.E[c] * m.E[c];
+        m.normE = std::sqrt(m.normE);
+        if (solver == FGH_EYRE_MILTON) {
+            HIPOK(run_fill_field<double>(s, p->d, p->g.npts, m.e, m.E));  // x = E
+        } else {
+            HIPOK(run_fill<double>(s, n, m.e, 0.0));
+            double bb = 0.0, ae2 = 0.0;
+            fgh_status st = rhs<double>(p, m.E, p->r64, &bb, &ae2);
+            if (st) return st;
+            m.applies++;
+            const bool zero = !(std::sqrt(bb / S) > kZeroRhs * std::sqrt(ae2 / S));
+            m.normb = std::sqrt(bb / S);
+            m.rr = bb;
+            if (zero) {
+                m.done = true;
+                fgh_status r = finish(m);
+                if (r) return r;
+            }
+        }
+    }
+    for (int outer = 0; outer < outer_cap; outer++) {
+        std::vector<BatchMember*> A;
+        for (BatchMember& m : ms) {
+            if (!m.active) continue;
+            fgh_plan p = m.p;
+            const long long n = (long long)p->d * p->g.npts;
+            const double S = (double)p->g.npts;
+            m.outer = outer;
+            fgh_status st;
+            if (solver == FGH_EYRE_MILTON) {
+                const double omega = std::sqrt(p->cA * p->CA);
+                HIPOK(run_copy<double>(s, n, p->r64, m.e));
+                ApplyArgs a;
+                a.op = OP_EM;
+                a.x = p->r64;
+                a.omega = omega;
+                a.mult = MULT_EM;
+                a.epi = EPI_EM;
+                a.ex = p->r64;
+                for (int c = 0; c < p->d; c++) a.E[c] = m.E[c];
+                int nbk = 0;
+                HIPOK(run_apply<double>(p->op64, a, &nbk));
+                m.applies++;
+                double dd;
+                if ((st = reduce_read(p, p->op64, nbk, RED_TOTAL, &dd))) return st;
+                m.dnorm = std::sqrt(dd / S);
+                m.res = m.normE > 0 ? m.dnorm / m.normE : m.dnorm;
+                if (!std::isfinite(m.dnorm) || m.dnorm > 1e12 * (m.normE > 0 ? m.normE : 1.0)) {
+                    m.status = FGH_E_DIVERGED;
+                    if ((st = finish(m))) return st;
+                    continue;
+                }
+                if (m.dnorm <= m.tol * m.normE) {
+                    HIPOK(run_copy<double>(s, n, m.e, p->r64));
+                    m.done = true;
+                    if ((st = finish(m))) return st;
+                    continue;
+                }
+                HIPOK(run_axpby(s, n, p->q64, 1.0, p->r64, 0.0));
+                HIPOK(run_axpby(s, n, p->q64, -1.0, m.e, 1.0));
+                HIPOK(run_f64_to_f32(s, n, p->r32, p->q64));
+                HIPOK(run_fill<float>(s, n, p->x32, 0.0f));
+                m.eta = std::max(m.tol * m.normE / m.dnorm, kInnerTolMin);
+            } else {
+                if (outer > 0) {
+                    ApplyArgs a;
+                    a.op = OP_AX;
+                    a.x = m.e;
+                    for (int c = 0; c < p->d; c++) a.E[c] = m.E[c];
+                    a.epi = EPI_STORE;
+                    a.sgn = -1.0;
+                    a.y = p->r64;
+                    int nbk = 0;
+                    HIPOK(run_apply<double>(p->op64, a, &nbk));
+                    m.applies++;
+                    if ((st = reduce_read(p, p->op64, nbk, RED_TOTAL, &m.rr))) return st;
+                }
+                m.res = std::sqrt(m.rr / S) / m.normb;
+                if (!std::isfinite(m.rr)) {
+                    m.status = FGH_E_DIVERGED;
+                    if ((st = finish(m))) return st;
+                    continue;
+                }
+                if (m.res <= m.tol) {
+                    m.done = true;
+                    if ((st = finish(m))) return st;
+                    continue;
+                }
+                m.eta = std::max(m.tol / m.res, kInnerTolMin);
+                HIPOK(run_f64_to_f32(s, n, p->r32, p->r64));
+                HIPOK(run_fill<float>(s, n, p->x32, 0.0f));
+            }
+            A.push_back(&m);
+        }
+        if (A.empty()) break;
+        for (size_t c = 0; c < A.size(); c += kMaxBatch) {
+            std::vector<BatchMember*> G(A.begin() + c, A.begin() + std::min(A.size(), c + kMaxBatch));
+            std::vector<SolveOut> outs;
+            fgh_status st = solver == FGH_EYRE_MILTON ? em_inner_batch(G, max_iter, s, &outs)
+                                                      : cg_inner_batch(G, max_iter, s, &outs);
+            if (st) return st;
+            for (size_t k = 0; k < G.size(); k++) {
+                BatchMember& m = *G[k];
+                fgh_plan p = m.p;
+                const long long n = (long long)p->d * p->g.npts;
+                m.inner += outs[k].iters;
+                if (outs[k].status == FGH_E_DIVERGED) {
+                    m.status = FGH_E_DIVERGED;
+                    if ((st = finish(m))) return st;
+                    continue;
+                }
+                if (solver == FGH_EYRE_MILTON) {
+                    HIPOK(run_add_f32_to_f64(s, n, m.e, p->x32));
+                } else {
+                    // x += G delta in FP64
+                    HIPOK(run_fill<double>(s, n, p->p64, 0.0));
+                    HIPOK(run_add_f32_to_f64(s, n, p->p64, p->x32));
+                    ApplyArgs a;
+                    a.op = OP_ID;
+                    a.x = p->p64;
+                    a.epi = EPI_STORE;
+                    a.sgn = 1.0;
+                    a.y = p->q64;
+                    int nbk = 0;
+                    HIPOK(run_apply<double>(p->op64, a, &nbk));
+                    m.applies++;
+                    HIPOK(run_add_f64(s, n, m.e, p->q64));
+                }
+            }
+        }
+    }
+    for (BatchMember& m : ms)
+        if (m.active) {
+            m.outer = outer_cap;
+            fgh_status st = finish(m);
+            if (st) return st;
+        }
+    return FGH_OK;
+}
+
+
 // Symmetric tridiagonal matrix with diagonal a and off-diagonal b: the number of its eigenvalues
 // below x, from the signs of the pivots of the LDL^T factorisation of T - x I (Sturm sequence;
 // a zero pivot is replaced by a tiny negative one, as in the bisection method of Barth, Martin
@@ -1943,6 +2360,73 @@ fgh_status fgh_solve_fixed(fgh_plan p, fgh_solver solver, const double* E, int n
     if (iters < 1) return FGH_E_INVALID;
     if (p && p->prec != FGH_FP64) return FGH_E_UNSUPPORTED;
     return solve_common(p, solver, E, nrhs, 0.5, iters, iters, e, stats);
+}
+
+fgh_status fgh_solve_batch(fgh_plan* plans, int n, fgh_solver solver, const double* E, const double* tol,
+                           int max_iter, double* const* e, fgh_stats* stats, fgh_retire_fn retire, void* user)
+{
+    if (!plans || n < 1 || n > 64 || !E || !tol || !e) return FGH_E_INVALID;
+    if (solver < FGH_RICHARDSON || solver > FGH_EYRE_MILTON || max_iter < 1) return FGH_E_INVALID;
+    for (int k = 0; k < n; k++) {
+        fgh_plan p = plans[k];
+        if (!p || !e[k] || !(tol[k] > 0.0) || !(tol[k] < 1.0)) return FGH_E_INVALID;
+        if (p->d != plans[0]->d || p->rule != plans[0]->rule || p->prec != plans[0]->prec) return FGH_E_INVALID;
+        for (int a = 0; a < 3; a++)
+            if (p->N[a] != plans[0]->N[a]) return FGH_E_INVALID;
+        for (int c = 0; c < p->d; c++)
+            if (!std::isfinite(E[k * p->d + c])) return FGH_E_INVALID;
+        for (int j = 0; j < k; j++)
+            if (plans[j] == p) return FGH_E_INVALID;  // members must not share buffers
+    }
+    if (solver == FGH_EYRE_MILTON && plans[0]->rule == FGH_GA) return FGH_E_UNSUPPORTED;
+    const int d = plans[0]->d;
+    bool shared = plans[0]->prec == FGH_FP32_REFINED && (solver == FGH_CG || solver == FGH_EYRE_MILTON) &&
+                  batchable(plans[0]->op32) && std::getenv("FGH_BATCH") == nullptr;
+    for (int k = 0; k < n && shared; k++)
+        shared = same_launch_shape(plans[0], plans[k]) && !plans[k]->hist_fn && !plans[k]->op32.prof &&
+                 !plans[k]->op64.prof;
+    int worst = FGH_OK;
+    if (!shared) {
+        // one member after another, each exactly as fgh_solve
+        for (int k = 0; k < n; k++) {
+            fgh_stats st{};
+            const fgh_status s = solve_common(plans[k], solver, E + k * d, 1, tol[k], max_iter, 0, e[k], &st);
+            if (s && s != FGH_E_NO_CONVERGENCE && s != FGH_E_DIVERGED) return s;
+            if (stats) stats[k] = st;
+            if (st.status != FGH_OK && worst == FGH_OK) worst = st.status;
+            if (retire) retire(user, k);
+        }
+        return (fgh_status)worst;
+    }
+    for (int k = 0; k < n; k++)
+        if (hipStreamSynchronize(plans[k]->caller) != hipSuccess) return FGH_E_DEVICE;
+    // every member's work runs on the first member's internal stream (capturable)
+    hipStream_t s = plans[0]->sstream;
+    struct Swap {
+        fgh_plan* P;
+        int n;
+        ~Swap()
+        {
+            (void)hipStreamSynchronize(P[0]->sstream);
+            for (int k = 0; k < n; k++) P[k]->stream = P[k]->op64.stream = P[k]->op32.stream = P[k]->caller;
+        }
+    } swap{plans, n};
+    for (int k = 0; k < n; k++) plans[k]->stream = plans[k]->op64.stream = plans[k]->op32.stream = s;
+    std::vector<BatchMember> ms(n);
+    for (int k = 0; k < n; k++) {
+        ms[k].p = plans[k];
+        ms[k].index = k;
+        ms[k].E = E + k * d;
+        ms[k].tol = tol[k];
+        ms[k].e = e[k];
+    }
+    std::function<void(int)> rf;
+    if (retire) rf = [retire, user](int k) { retire(user, k); };
+    const fgh_status st = refined_batch(ms, solver, max_iter, s, stats, rf);
+    if (st) return st;
+    for (const BatchMember& m : ms)
+        if (m.status != FGH_OK && worst == FGH_OK) worst = m.status;
+    return (fgh_status)worst;
 }
 
 fgh_status fgh_effective(fgh_plan p, const double* E, int nrhs, const double* e, double* bilinear, double* flux)

@@ -401,13 +401,25 @@ __global__ __launch_bounds__(kThreads) void k_last(LastArgs<T> a)
 // ------------------------------------------------------------------------------------------
 // Reductions and vector kernels.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ partials, int n, Scalars* s, int op)
+__device__ __forceinline__ void reduce_body(const double* __restrict__ partials, int n, Scalars* s, int op)
 {
     __shared__ double red[kThreads / 64];
     const bool in_loop = op == RED_CG_ALPHA || op == RED_CG_END || op == RED_STEP_END || op == RED_CHEB_END;
     if (in_loop && s->done) return;
     const double tot = block_sum(sum_partials(partials, n), red);
     if (threadIdx.x == 0) apply_redop(s, op, tot);
+}
+
+__global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ partials, int n, Scalars* s, int op)
+{
+    reduce_body(partials, n, s, op);
+}
+
+// One loop reduction per member of a batch (workgroup m: member m).
+__global__ __launch_bounds__(kThreads) void k_reduce_b(const ReduceArgs* __restrict__ tab, int op)
+{
+    const ReduceArgs& a = tab[blockIdx.x];
+    reduce_body(a.partials, a.n, a.sc, op);
 }
 
 // Start a solver loop: m = 0, done = 0 and the loop's constants (no memset: a plain kernel).
@@ -446,9 +458,9 @@ __global__ __launch_bounds__(kThreads) void k_reduce_multi(const double* __restr
 constexpr int kVecBlocks = 1024;
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_cg_update(long long n, T* __restrict__ x, T* __restrict__ r,
-                                                        const T* __restrict__ p, const T* __restrict__ q,
-                                                        const Scalars* s, double* partials)
+__device__ __forceinline__ void cg_update_body(long long n, T* __restrict__ x, T* __restrict__ r,
+                                               const T* __restrict__ p, const T* __restrict__ q, const Scalars* s,
+                                               double* partials, unsigned bx, unsigned gx)
 {
     __shared__ double red[kThreads / 64];
     if (s->done) return;
@@ -456,8 +468,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(long long n, T* __restri
     double acc = 0.0;
     // four grid-strided points per batch, all loads issued before any use (one memory latency per
     // batch); each thread still visits its points in increasing order
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gx * blockDim.x;
+    long long i = (long long)bx * blockDim.x + threadIdx.x;
     for (; i + 3 * stride < n; i += 4 * stride) {
         T xv[4], pv[4], rv[4], qv[4];
 #pragma unroll
@@ -484,7 +496,23 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(long long n, T* __restri
         acc += double(rv) * double(rv);
     }
     const double tot = block_sum(acc, red);
-    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    if (threadIdx.x == 0) partials[bx] = tot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_update(long long n, T* __restrict__ x, T* __restrict__ r,
+                                                        const T* __restrict__ p, const T* __restrict__ q,
+                                                        const Scalars* s, double* partials)
+{
+    cg_update_body<T>(n, x, r, p, q, s, partials, blockIdx.x, gridDim.x);
+}
+
+// The CG update of every member of a batch: grid (kVecBlocks, members).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_update_b(const UpdateArgs<T>* __restrict__ tab)
+{
+    const UpdateArgs<T>& a = tab[blockIdx.y];
+    cg_update_body<T>(a.n, a.x, a.r, a.p, a.q, a.sc, a.partials, blockIdx.x, gridDim.x);
 }
 
 template <typename T>
@@ -1142,6 +1170,98 @@ static hipError_t v2_axis(const OpPlan& op, const AxisArgs<T>& xa, bool inv, int
     return hipGetLastError();
 }
 
+// ---- batched launches (several plans of one shape): grid y (strided pass: z) over the members
+template <typename T, int D>
+static hipError_t v2_first_b(const OpPlan& op, const FirstArgs<T>* tab, int opc, unsigned nblk, int nb)
+{
+    const size_t lds = op.lds_first_v2;
+    const dim3 grid(nblk, nb);
+    switch (op.ax[D - 1].L) {
+#define C(LL, A1, A2)                                                                   \
+    case LL:                                                                            \
+        LAUNCH_LDS((k2_first_b<T, D, A1, A2>), grid, lds, op.stream, tab, opc);         \
+        break;
+        V2_ROW_CASES(C)
+#undef C
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int D>
+static hipError_t v2_last_b(const OpPlan& op, const LastArgs<T>* tab, int epi, bool fused, unsigned nblk, int nb)
+{
+    const dim3 grid(nblk, nb);
+    // the loops that share launches: CG bodies (last pass with the CG epilogue) and fused
+    // Eyre-Milton bodies
+    if (!fused && epi == EPI_CG) {
+        const size_t lds = op.lds_last_v2;
+        switch (op.ax[D - 1].L) {
+#define C(LL, A1, A2)                                                                          \
+    case LL:                                                                                   \
+        LAUNCH_LDS((k2_last_b<T, D, A1, A2, EPI_CG>), grid, lds, op.stream, tab);              \
+        break;
+            V2_ROW_CASES(C)
+#undef C
+            default: return hipErrorInvalidValue;
+        }
+    } else if (fused && epi == EPI_EM) {
+        const size_t lds = op.lds_fused;
+        switch (op.ax[D - 1].L) {
+#define C(LL, A1, A2)                                                                          \
+    case LL:                                                                                   \
+        LAUNCH_LDS((k2_lastfirst_b<T, D, A1, A2, EPI_EM>), grid, lds, op.stream, tab);         \
+        break;
+            V2_ROW_CASES(C)
+#undef C
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int D>
+static hipError_t v2_middle_b(const OpPlan& op, const MidArgs<T>* tab, int mult, int ntiles, int nb)
+{
+    const size_t lds = op.lds_mid;
+    const dim3 grid(ntiles, nb);
+    switch (op.ax[0].L) {
+#define C(LL, A1, A2)                                                                          \
+    case LL:                                                                                   \
+        if (mult == MULT_G)                                                                    \
+            LAUNCH_LDS((k2_middle_b<T, D, A1, A2, MULT_G>), grid, lds, op.stream, tab);        \
+        else                                                                                   \
+            LAUNCH_LDS((k2_middle_b<T, D, A1, A2, MULT_EM>), grid, lds, op.stream, tab);       \
+        break;
+        V2_COL_CASES(C)
+#undef C
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t v2_axis_b(const OpPlan& op, const AxisArgs<T>* tab, bool inv, int ntiles, int outer, int B, int nb)
+{
+    const dim3 grid(ntiles, outer, op.g.d * nb);
+    const size_t lds = op.lds_axis;
+    switch (op.ax[1].L) {
+#define C(LL, A1, A2)                                                                           \
+    case LL:                                                                                    \
+        if (inv)                                                                                \
+            LAUNCH_LDS((k2_axis_b<T, A1, A2, true>), grid, lds, op.stream, tab, B, op.g.d);     \
+        else                                                                                    \
+            LAUNCH_LDS((k2_axis_b<T, A1, A2, false>), grid, lds, op.stream, tab, B, op.g.d);    \
+        break;
+        V2_COL_CASES(C)
+#undef C
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 static MidArgs<T> mid_args(const OpPlan& op, cpx<T>* buf, const int* done)
 {
@@ -1163,21 +1283,26 @@ static MidArgs<T> mid_args(const OpPlan& op, cpx<T>* buf, const int* done)
     return ma;
 }
 
+// The argument blocks of one application: what the passes read (first pass operator and operand,
+// strided and middle geometry, last-pass epilogue), tile counts and flags.
 template <typename T, int D>
-static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_last)
+static hipError_t build_bundle_d(const OpPlan& op, const ApplyArgs& a, ApplyBundle<T>* bu)
 {
     const Geo& g = op.g;
     const int last = D - 1;
-    hipError_t e;
-    unsigned nblk = (unsigned)((g.rows + op.rpb - 1) / op.rpb);
     cpx<T>* SA = static_cast<cpx<T>*>(op.SA);
     cpx<T>* SB = static_cast<cpx<T>*>(op.SB);
+    bu->op = a.op;
+    bu->mult = a.mult;
+    bu->epi = a.epi;
+    bu->skip_first = a.skip_first;
+    bu->first_only = a.first_only;
 
-    FirstArgs<T> fa;
+    FirstArgs<T>& fa = bu->fa;
     fa.g = g;
     fa.ax = op.ax[last];
     const int rpb1 = op.v2_row ? op.rpb_first : op.rpb;
-    const unsigned nblk1 = (unsigned)((g.rows + rpb1 - 1) / rpb1);
+    bu->nblk1 = (unsigned)((g.rows + rpb1 - 1) / rpb1);
     fa.rpb = rpb1;
     fa.npen = (rpb1 * D + 1) / 2;
     fa.x = static_cast<const T*>(a.x);
@@ -1191,19 +1316,10 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     fa.A = op.A;
     fa.out = SA;
     fa.twg = static_cast<const cpx<T>*>(op.tw[last]);
-    if (!a.skip_first) {
-        const bool prof_PK_FIRST = op.prof && op.prof->wants(PK_FIRST);
-        if (prof_PK_FIRST && (e = op.prof->begin(PK_FIRST)) != hipSuccess) return e;
-        if ((e = op.v2_row ? v2_first<T, D>(op, fa, a.op, nblk1) : launch_first<T, D>(op, fa, a.op, nblk1)) !=
-            hipSuccess)
-            return e;
-        if (prof_PK_FIRST && (e = op.prof->end()) != hipSuccess) return e;
-    }
-    if (a.first_only) return hipSuccess;
 
     cpx<T>* mid = SA;
     if (D == 3) {
-        AxisArgs<T> xa{};
+        AxisArgs<T>& xa = bu->xf;
         xa.ax = op.ax[1];
         xa.nin = g.L[1];
         xa.nout = g.B[1];
@@ -1223,46 +1339,28 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
         // the previous body's deferred loop reduction is completed by this pass's first workgroup
         xa.red_sc = a.defer_redop >= 0 ? op.sc : nullptr;
         xa.partials = op.partials;
-        const bool prof_PK_AXIS_FWD = op.prof && op.prof->wants(PK_AXIS_FWD);
-        if (prof_PK_AXIS_FWD && (e = op.prof->begin(PK_AXIS_FWD)) != hipSuccess) return e;
-        if ((e = op.v2_axis ? v2_axis<T>(op, xa, false, g.L[0], g.B[1]) : launch_axis<T>(op, xa, false, g.L[0])) != hipSuccess)
-            return e;
-        if (prof_PK_AXIS_FWD && (e = op.prof->end()) != hipSuccess) return e;
         mid = SB;
+        AxisArgs<T>& xi = bu->xi;
+        xi.ax = op.ax[1];
+        xi.nin = g.B[1];
+        xi.nout = g.L[1];
+        xi.bin = 1;
+        xi.bout = 0;
+        xi.inner = g.Hb;
+        xi.P = op.P_axis;
+        xi.ntiles = (g.Hb + op.P_axis - 1) / op.P_axis;
+        xi.in_os = (long long)g.B[1] * g.Hb;
+        xi.out_os = (long long)g.L[1] * g.Hb;
+        xi.in_cs = g.s2;
+        xi.out_cs = g.s1;
+        xi.in = SB;
+        xi.out = SA;
+        xi.twg = static_cast<const cpx<T>*>(op.tw[1]);
+        xi.done = done;
     }
+    bu->ma = mid_args<T>(op, mid, done);
 
-    const MidArgs<T> ma = mid_args<T>(op, mid, done);
-    const bool prof_PK_MIDDLE = op.prof && op.prof->wants(PK_MIDDLE);
-    if (prof_PK_MIDDLE && (e = op.prof->begin(PK_MIDDLE)) != hipSuccess) return e;
-    if ((e = op.v2_mid ? v2_middle<T, D>(op, ma, a.mult) : launch_middle<T, D>(op, ma, a.mult)) != hipSuccess) return e;
-    if (prof_PK_MIDDLE && (e = op.prof->end()) != hipSuccess) return e;
-
-    if (D == 3) {
-        AxisArgs<T> xa{};
-        xa.ax = op.ax[1];
-        xa.nin = g.B[1];
-        xa.nout = g.L[1];
-        xa.bin = 1;
-        xa.bout = 0;
-        xa.inner = g.Hb;
-        xa.P = op.P_axis;
-        xa.ntiles = (g.Hb + op.P_axis - 1) / op.P_axis;
-        xa.in_os = (long long)g.B[1] * g.Hb;
-        xa.out_os = (long long)g.L[1] * g.Hb;
-        xa.in_cs = g.s2;
-        xa.out_cs = g.s1;
-        xa.in = SB;
-        xa.out = SA;
-        xa.twg = static_cast<const cpx<T>*>(op.tw[1]);
-        xa.done = done;
-        const bool prof_PK_AXIS_INV = op.prof && op.prof->wants(PK_AXIS_INV);
-        if (prof_PK_AXIS_INV && (e = op.prof->begin(PK_AXIS_INV)) != hipSuccess) return e;
-        if ((e = op.v2_axis ? v2_axis<T>(op, xa, true, g.L[0], g.B[1]) : launch_axis<T>(op, xa, true, g.L[0])) != hipSuccess)
-            return e;
-        if (prof_PK_AXIS_INV && (e = op.prof->end()) != hipSuccess) return e;
-    }
-
-    LastArgs<T> la{};
+    LastArgs<T>& la = bu->la;
     la.g = g;
     la.ax = op.ax[last];
     la.rpb = op.rpb;
@@ -1292,17 +1390,60 @@ static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_las
     if (fused && (!fusable(op) || a.next_op != (a.epi == EPI_EM ? OP_EM : OP_AX) ||
                   (a.epi != EPI_RICH && a.epi != EPI_CHEB && a.epi != EPI_EM)))
         return hipErrorInvalidValue;
+    bu->fused = fused;
+    bu->nblk_last = (unsigned)((g.rows + op.rpb - 1) / op.rpb);
     if (fused) {
         // the fused pass has its own (tuned, even) rows per block
         la.rpb = op.rpb_fused;
         la.npen = (op.rpb_fused * D + 1) / 2;
-        nblk = (unsigned)((g.rows + op.rpb_fused - 1) / op.rpb_fused);
+        bu->nblk_last = (unsigned)((g.rows + op.rpb_fused - 1) / op.rpb_fused);
     }
+    return hipSuccess;
+}
+
+template <typename T, int D>
+static hipError_t apply_d(const OpPlan& op, const ApplyArgs& a, int* nblocks_last)
+{
+    const Geo& g = op.g;
+    ApplyBundle<T> bu{};
+    hipError_t e = build_bundle_d<T, D>(op, a, &bu);
+    if (e != hipSuccess) return e;
+    if (!a.skip_first) {
+        const bool prof_PK_FIRST = op.prof && op.prof->wants(PK_FIRST);
+        if (prof_PK_FIRST && (e = op.prof->begin(PK_FIRST)) != hipSuccess) return e;
+        if ((e = op.v2_row ? v2_first<T, D>(op, bu.fa, a.op, bu.nblk1) : launch_first<T, D>(op, bu.fa, a.op, bu.nblk1)) !=
+            hipSuccess)
+            return e;
+        if (prof_PK_FIRST && (e = op.prof->end()) != hipSuccess) return e;
+    }
+    if (a.first_only) return hipSuccess;
+    if (D == 3) {
+        const bool prof_PK_AXIS_FWD = op.prof && op.prof->wants(PK_AXIS_FWD);
+        if (prof_PK_AXIS_FWD && (e = op.prof->begin(PK_AXIS_FWD)) != hipSuccess) return e;
+        if ((e = op.v2_axis ? v2_axis<T>(op, bu.xf, false, g.L[0], g.B[1]) : launch_axis<T>(op, bu.xf, false, g.L[0])) !=
+            hipSuccess)
+            return e;
+        if (prof_PK_AXIS_FWD && (e = op.prof->end()) != hipSuccess) return e;
+    }
+    const bool prof_PK_MIDDLE = op.prof && op.prof->wants(PK_MIDDLE);
+    if (prof_PK_MIDDLE && (e = op.prof->begin(PK_MIDDLE)) != hipSuccess) return e;
+    if ((e = op.v2_mid ? v2_middle<T, D>(op, bu.ma, a.mult) : launch_middle<T, D>(op, bu.ma, a.mult)) != hipSuccess)
+        return e;
+    if (prof_PK_MIDDLE && (e = op.prof->end()) != hipSuccess) return e;
+    if (D == 3) {
+        const bool prof_PK_AXIS_INV = op.prof && op.prof->wants(PK_AXIS_INV);
+        if (prof_PK_AXIS_INV && (e = op.prof->begin(PK_AXIS_INV)) != hipSuccess) return e;
+        if ((e = op.v2_axis ? v2_axis<T>(op, bu.xi, true, g.L[0], g.B[1]) : launch_axis<T>(op, bu.xi, true, g.L[0])) !=
+            hipSuccess)
+            return e;
+        if (prof_PK_AXIS_INV && (e = op.prof->end()) != hipSuccess) return e;
+    }
+    unsigned nblk = bu.nblk_last;
     const bool prof_PK_LAST = op.prof && op.prof->wants(PK_LAST);
     if (prof_PK_LAST && (e = op.prof->begin(PK_LAST)) != hipSuccess) return e;
-    if ((e = fused        ? v2_lastfirst<T, D>(op, la, a.epi, &nblk)
-             : op.v2_row ? v2_last<T, D>(op, la, a.epi, &nblk)
-                         : launch_last<T, D>(op, la, a.epi, nblk)) != hipSuccess)
+    if ((e = bu.fused      ? v2_lastfirst<T, D>(op, bu.la, a.epi, &nblk)
+             : op.v2_row ? v2_last<T, D>(op, bu.la, a.epi, &nblk)
+                         : launch_last<T, D>(op, bu.la, a.epi, nblk)) != hipSuccess)
         return e;
     if (prof_PK_LAST && (e = op.prof->end()) != hipSuccess) return e;
     if (nblocks_last) *nblocks_last = (int)nblk;
@@ -1512,6 +1653,83 @@ hipError_t run_apply(const OpPlan& op, const ApplyArgs& a, int* nblocks_last)
 }
 template hipError_t run_apply<float>(const OpPlan&, const ApplyArgs&, int*);
 template hipError_t run_apply<double>(const OpPlan&, const ApplyArgs&, int*);
+
+bool batchable(const OpPlan& op) { return op.v2_row && op.v2_mid && (op.g.d == 2 || op.v2_axis); }
+
+template <typename T>
+BatchTables<T> batch_tables(void* region)
+{
+    BatchTables<T> t{};
+    char* base = static_cast<char*>(region);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base + off;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    t.fa = reinterpret_cast<FirstArgs<T>*>(take(kMaxBatch * sizeof(FirstArgs<T>)));
+    t.xf = reinterpret_cast<AxisArgs<T>*>(take(kMaxBatch * sizeof(AxisArgs<T>)));
+    t.xi = reinterpret_cast<AxisArgs<T>*>(take(kMaxBatch * sizeof(AxisArgs<T>)));
+    t.ma = reinterpret_cast<MidArgs<T>*>(take(kMaxBatch * sizeof(MidArgs<T>)));
+    t.la = reinterpret_cast<LastArgs<T>*>(take(kMaxBatch * sizeof(LastArgs<T>)));
+    t.red = reinterpret_cast<ReduceArgs*>(take(kMaxBatch * sizeof(ReduceArgs)));
+    t.red2 = reinterpret_cast<ReduceArgs*>(take(kMaxBatch * sizeof(ReduceArgs)));
+    t.upd = reinterpret_cast<UpdateArgs<T>*>(take(kMaxBatch * sizeof(UpdateArgs<T>)));
+    t.bytes = off;
+    return t;
+}
+template BatchTables<float> batch_tables<float>(void*);
+template BatchTables<double> batch_tables<double>(void*);
+static_assert(kMaxBatch * (sizeof(FirstArgs<double>) + 2 * sizeof(AxisArgs<double>) + sizeof(MidArgs<double>) +
+                           sizeof(LastArgs<double>) + 2 * sizeof(ReduceArgs) + sizeof(UpdateArgs<double>)) +
+                      8 * 256 <=
+                  kBatchSlabBytes,
+              "batch tables exceed their region");
+
+template <typename T>
+hipError_t build_bundle(const OpPlan& op, const ApplyArgs& a, ApplyBundle<T>* out)
+{
+    if (op.g.d == 2) return build_bundle_d<T, 2>(op, a, out);
+    return build_bundle_d<T, 3>(op, a, out);
+}
+template hipError_t build_bundle<float>(const OpPlan&, const ApplyArgs&, ApplyBundle<float>*);
+template hipError_t build_bundle<double>(const OpPlan&, const ApplyArgs&, ApplyBundle<double>*);
+
+template <typename T, int D>
+static hipError_t apply_batch_d(const OpPlan& op, const ApplyBundle<T>& b0, const BatchTables<T>& t, int nb)
+{
+    const Geo& g = op.g;
+    hipError_t e;
+    if (!b0.skip_first && (e = v2_first_b<T, D>(op, t.fa, b0.op, b0.nblk1, nb)) != hipSuccess) return e;
+    if (b0.first_only) return hipSuccess;
+    if (D == 3 && (e = v2_axis_b<T>(op, t.xf, false, b0.xf.ntiles, g.L[0], g.B[1], nb)) != hipSuccess) return e;
+    if ((e = v2_middle_b<T, D>(op, t.ma, b0.mult, b0.ma.ntiles, nb)) != hipSuccess) return e;
+    if (D == 3 && (e = v2_axis_b<T>(op, t.xi, true, b0.xi.ntiles, g.L[0], g.B[1], nb)) != hipSuccess) return e;
+    return v2_last_b<T, D>(op, t.la, b0.epi, b0.fused, b0.nblk_last, nb);
+}
+
+template <>
+hipError_t run_apply_batch<float>(const OpPlan& op0, const ApplyBundle<float>& b0, const BatchTables<float>& t, int nb)
+{
+    if (!batchable(op0) || nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
+    if (op0.g.d == 2) return apply_batch_d<float, 2>(op0, b0, t, nb);
+    return apply_batch_d<float, 3>(op0, b0, t, nb);
+}
+
+hipError_t run_reduce_batch(hipStream_t s, const ReduceArgs* tab, int nb, int redop)
+{
+    hipLaunchKernelGGL(k_reduce_b, dim3(nb), dim3(kThreads), 0, s, tab, redop);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t run_cg_update_batch(hipStream_t s, const UpdateArgs<T>* tab, int nb)
+{
+    hipLaunchKernelGGL(k_cg_update_b<T>, dim3(kVecBlocks, nb), dim3(kThreads), 0, s, tab);
+    return hipGetLastError();
+}
+template hipError_t run_cg_update_batch<float>(hipStream_t, const UpdateArgs<float>*, int);
+
 
 hipError_t run_init_loop(const OpPlan& op, double rr, double alpha, double beta, double thr, double npts,
                          double blowup, double cheb_c, double cheb_delta, int limit)

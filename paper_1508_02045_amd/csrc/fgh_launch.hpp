@@ -4,6 +4,7 @@
 
 #include <vector>
 
+#include "fgh_args.hpp"
 #include "fgh_internal.hpp"
 
 namespace fgh {
@@ -105,6 +106,71 @@ inline bool fusable(const OpPlan& op) { return op.v2_row; }
 
 template <typename T>
 hipError_t run_apply(const OpPlan& op, const ApplyArgs& a, int* nblocks_last);
+
+// ------------------------------------------------------------------------------------------
+// Several plans of one shape in shared launches ("members" of a batch).  Each member keeps its
+// own buffers, coefficients, loop scalars and partial sums; a batched launch runs the same pass
+// for every member, one grid row (or plane) per member, with the member's argument block read
+// from a device table.  A member's workgroups see the block ids of the single-plan launch, so its
+// tile mapping, partial sums and summation order -- hence its results -- are those of the plan
+// alone.  Only the size-specialised passes are batched.
+// ------------------------------------------------------------------------------------------
+// The argument blocks of one application, built exactly as the single-plan launch builds them.
+template <typename T>
+struct ApplyBundle {
+    FirstArgs<T> fa;
+    AxisArgs<T> xf, xi;      // forward and inverse strided passes (3D)
+    MidArgs<T> ma;
+    LastArgs<T> la;
+    unsigned nblk1, nblk_last;
+    int op, mult, epi;
+    bool fused, skip_first, first_only;
+};
+struct ReduceArgs {
+    const double* partials;
+    int n;
+    Scalars* sc;
+};
+template <typename T>
+struct UpdateArgs {
+    long long n;
+    T* x;
+    T* r;
+    const T* p;
+    const T* q;
+    const Scalars* sc;
+    double* partials;
+};
+// Device tables of a batch of up to kMaxBatch members, carved out of a device region of
+// kBatchSlabBytes (struct-of-arrays: the argument blocks of one kind are contiguous).
+constexpr int kMaxBatch = 8;
+constexpr size_t kBatchSlabBytes = 64 * 1024;
+template <typename T>
+struct BatchTables {
+    FirstArgs<T>* fa;
+    AxisArgs<T>* xf;
+    AxisArgs<T>* xi;
+    MidArgs<T>* ma;
+    LastArgs<T>* la;
+    ReduceArgs* red;   // loop reductions of the last pass's partial sums
+    ReduceArgs* red2;  // loop reductions of the CG update's partial sums
+    UpdateArgs<T>* upd;
+    size_t bytes;      // bytes used from the start of the region
+};
+template <typename T>
+BatchTables<T> batch_tables(void* region);
+// The argument blocks of application `a` on plan `op` (no launch).
+template <typename T>
+hipError_t build_bundle(const OpPlan& op, const ApplyArgs& a, ApplyBundle<T>* out);
+// Whether plans of this shape can share launches (size-specialised passes throughout).
+bool batchable(const OpPlan& op);
+// One application per member from the uploaded tables; op0 is any member's plan (shared launch
+// configuration), b0 its bundle (shared flags and tile counts), nb the member count.
+template <typename T>
+hipError_t run_apply_batch(const OpPlan& op0, const ApplyBundle<T>& b0, const BatchTables<T>& t, int nb);
+hipError_t run_reduce_batch(hipStream_t s, const ReduceArgs* tab, int nb, int redop);
+template <typename T>
+hipError_t run_cg_update_batch(hipStream_t s, const UpdateArgs<T>* tab, int nb);
 
 hipError_t run_reduce(const OpPlan& op, int n, int redop, double* host_out);
 

@@ -601,7 +601,7 @@ __device__ __forceinline__ void first_transform_store_ip(const Args& a, long lon
 // First pass with one LDS buffer of npairs packed rows (the stages run in place).
 // LDS: twiddles | Zc (npairs complex rows) | phase table.
 template <typename T, int D, int L1, int L2>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void k2_first(FirstArgs<T> a, int op)
+__device__ __forceinline__ void first_body(const FirstArgs<T>& a, int op, long long b, long long nb)
 {
     if (a.done && *a.done) return;
     constexpr int L = L1 * L2;
@@ -616,7 +616,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
     if ((a.rpb * D) & 1)  // the imaginary half of the last packed row is a zero row
         for (int i = threadIdx.x; i < L; i += blockDim.x) Zc[(npairs - 1) * L + i].y = T(0);
     lds_barrier();
-    const long long row0 = xcd_tile(blockIdx.x, gridDim.x) * a.rpb;
+    const long long row0 = xcd_tile(b, nb) * a.rpb;
     const T beta = (op == OP_AP_CG) ? T(a.sc->beta) : T(0);
     {
         const int total = a.rpb * L;
@@ -633,13 +633,29 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
     first_transform_store_ip<T, D, L1, L2>(a, row0, tw, Zc);
 }
 
+template <typename T, int D, int L1, int L2>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void k2_first(FirstArgs<T> a, int op)
+{
+    first_body<T, D, L1, L2>(a, op, blockIdx.x, gridDim.x);
+}
+
+// Several plans of one shape in one launch: member blockIdx.y with its own argument block; the
+// member's workgroups see the block ids and tile mapping of the single-plan launch.
+template <typename T, int D, int L1, int L2>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void k2_first_b(
+    const FirstArgs<T>* __restrict__ tab, int op)
+{
+    first_body<T, D, L1, L2>(tab[blockIdx.y], op, blockIdx.x, gridDim.x);
+}
+
 // ------------------------------------------------------------------------------------------
 // Strided axis pass (3D axis 1), one component per workgroup, tile of P columns.
 // ------------------------------------------------------------------------------------------
+// b: the workgroup's linear id over the (tile, outer, component) grid gx x gy x gz of one plan.
 template <typename T, int L1, int L2, bool INV>
-__global__ __launch_bounds__(kThreads) void k2_axis(AxisArgs<T> a, int B)
+__device__ __forceinline__ void axis_body(const AxisArgs<T>& a, int B, long long b, int gx, int gy, int gz)
 {
-    if (a.red_sc && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) {
+    if (a.red_sc && b == 0) {
         __shared__ double red[kThreads / 64];
         finish_deferred(a.red_sc, a.partials, red);
     }
@@ -649,11 +665,10 @@ __global__ __launch_bounds__(kThreads) void k2_axis(AxisArgs<T> a, int B)
     cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
     cpx<T>* Y = tw + L;
     const int P = a.P;
-    const long long lin = xcd_tile(blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z),
-                                   (long long)gridDim.x * gridDim.y * gridDim.z);
-    const int tile = (int)(lin % gridDim.x);
-    const int o = (int)((lin / gridDim.x) % gridDim.y);
-    const int c = (int)(lin / ((long long)gridDim.x * gridDim.y));
+    const long long lin = xcd_tile(b, (long long)gx * gy * gz);
+    const int tile = (int)(lin % gx);
+    const int o = (int)((lin / gx) % gy);
+    const int c = (int)(lin / ((long long)gx * gy));
     for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
     lds_barrier();
     const cpx<T>* in = a.in + c * a.in_cs + o * a.in_os;
@@ -703,12 +718,29 @@ __global__ __launch_bounds__(kThreads) void k2_axis(AxisArgs<T> a, int B)
     }
 }
 
+template <typename T, int L1, int L2, bool INV>
+__global__ __launch_bounds__(kThreads) void k2_axis(AxisArgs<T> a, int B)
+{
+    axis_body<T, L1, L2, INV>(a, B, blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z),
+                              gridDim.x, gridDim.y, gridDim.z);
+}
+
+// Several plans of one shape: grid (tiles, outer, d x members), member blockIdx.z / d.
+template <typename T, int L1, int L2, bool INV>
+__global__ __launch_bounds__(kThreads) void k2_axis_b(const AxisArgs<T>* __restrict__ tab, int B, int d)
+{
+    const int m = (int)blockIdx.z / d;
+    const int cz = (int)blockIdx.z - m * d;
+    axis_body<T, L1, L2, INV>(tab[m], B, blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * cz),
+                              gridDim.x, gridDim.y, d);
+}
+
 // ------------------------------------------------------------------------------------------
 // Middle pass along axis 0 (all components, in place): forward step A -> LDS -> forward step B,
 // multiplier and inverse step B in registers -> LDS -> inverse step A.
 // ------------------------------------------------------------------------------------------
 template <typename T, int D, int L1, int L2, int MULT>
-__device__ __forceinline__ void middle_body(const MidArgs<T>& a)
+__device__ __forceinline__ void middle_body(const MidArgs<T>& a, long long b, long long nb)
 {
     if (a.done && *a.done) return;
     constexpr int L = L1 * L2;
@@ -718,7 +750,7 @@ __device__ __forceinline__ void middle_body(const MidArgs<T>& a)
     const int P = a.P;
     const int YS = a.ys;      // LDS stride of a column (L, or L + 1 to spread the banks)
     const int PL = P * YS;
-    const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = (int)xcd_tile(b, nb);
     for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
     lds_barrier();
     // forward step A: jobs (c, n1, p), p fastest
@@ -874,7 +906,13 @@ __device__ __forceinline__ void middle_body(const MidArgs<T>& a)
 template <typename T, int D, int L1, int L2, int MULT>
 __global__ __launch_bounds__(kThreads) void k2_middle(MidArgs<T> a)
 {
-    middle_body<T, D, L1, L2, MULT>(a);
+    middle_body<T, D, L1, L2, MULT>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename T, int D, int L1, int L2, int MULT>
+__global__ __launch_bounds__(kThreads) void k2_middle_b(const MidArgs<T>* __restrict__ tab)
+{
+    middle_body<T, D, L1, L2, MULT>(tab[blockIdx.y], blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -967,7 +1005,7 @@ __device__ __forceinline__ double last_epilogue_tile(const LastArgs<T>& a, const
 }
 
 template <typename T, int D, int L1, int L2, int epi>
-__global__ __launch_bounds__(kThreads) void k2_last(LastArgs<T> a)
+__device__ __forceinline__ void last_body(const LastArgs<T>& a, int b, int nb)
 {
     if (a.done && *a.done) return;
     constexpr int L = L1 * L2;
@@ -981,7 +1019,7 @@ __global__ __launch_bounds__(kThreads) void k2_last(LastArgs<T> a)
     for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = a.twg[m];
     if (epi == EPI_EM && a.A.kind == AK_PHASE)
         for (int m = threadIdx.x; m < kMaxPhases * 6; m += blockDim.x) tab[m] = T(a.A.tab_inv[m / 6][m % 6]);
-    const long long row0 = xcd_tile(blockIdx.x, gridDim.x) * a.rpb;
+    const long long row0 = xcd_tile(b, nb) * a.rpb;
     const int Hb = a.g.Hb;
     {
         // stage L: thread (tq, k) loads frequency k of the real rows q = tq, tq + qstep, ...,
@@ -1018,11 +1056,23 @@ __global__ __launch_bounds__(kThreads) void k2_last(LastArgs<T> a)
     last_transform<T, D, L1, L2>(a, tw, Sx);
     const double acc = last_epilogue_tile<T, D, L, epi>(a, tab, row0, Zr);
     const double tot = block_sum(acc, red);
-    if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
-    if (a.defer_sc && blockIdx.x == 0 && threadIdx.x == 0) {
-        a.defer_sc->pend_n = (int)gridDim.x;
+    if (threadIdx.x == 0) a.partials[b] = tot;
+    if (a.defer_sc && b == 0 && threadIdx.x == 0) {
+        a.defer_sc->pend_n = nb;
         a.defer_sc->pend_op = a.redop;
     }
+}
+
+template <typename T, int D, int L1, int L2, int epi>
+__global__ __launch_bounds__(kThreads) void k2_last(LastArgs<T> a)
+{
+    last_body<T, D, L1, L2, epi>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename T, int D, int L1, int L2, int epi>
+__global__ __launch_bounds__(kThreads) void k2_last_b(const LastArgs<T>* __restrict__ tab)
+{
+    last_body<T, D, L1, L2, epi>(tab[blockIdx.y], blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1164,7 +1214,7 @@ __device__ __forceinline__ double lastfirst_chunk(const LastArgs<T>& a, const T*
 }
 
 template <typename T, int D, int L1, int L2, int epi>
-__global__ __launch_bounds__(kThreads) void k2_lastfirst(LastArgs<T> a)
+__device__ __forceinline__ void lastfirst_body(const LastArgs<T>& a, int b, int nb)
 {
     static_assert(epi == EPI_RICH || epi == EPI_CHEB || epi == EPI_EM, "pointwise updates only");
     if (a.done && *a.done) return;
@@ -1183,7 +1233,7 @@ __global__ __launch_bounds__(kThreads) void k2_lastfirst(LastArgs<T> a)
             tab[m] = T(a.A.tab[m / 6][m % 6]);
             tabinv[m] = T(a.A.tab_inv[m / 6][m % 6]);
         }
-    const long long row0 = xcd_tile(blockIdx.x, gridDim.x) * a.rpb;
+    const long long row0 = xcd_tile(b, nb) * a.rpb;
     const int Hb = a.g.Hb;
     const int nrows = (int)(a.g.rows - row0 < a.rpb ? a.g.rows - row0 : a.rpb);
     {
@@ -1232,11 +1282,23 @@ __global__ __launch_bounds__(kThreads) void k2_lastfirst(LastArgs<T> a)
     lds_barrier();
     first_transform_store_ip<T, D, L1, L2, L + 1>(a, row0, tw, Sx);
     const double tot = block_sum(acc, red);
-    if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
-    if (a.defer_sc && blockIdx.x == 0 && threadIdx.x == 0) {
-        a.defer_sc->pend_n = (int)gridDim.x;
+    if (threadIdx.x == 0) a.partials[b] = tot;
+    if (a.defer_sc && b == 0 && threadIdx.x == 0) {
+        a.defer_sc->pend_n = nb;
         a.defer_sc->pend_op = a.redop;
     }
+}
+
+template <typename T, int D, int L1, int L2, int epi>
+__global__ __launch_bounds__(kThreads) void k2_lastfirst(LastArgs<T> a)
+{
+    lastfirst_body<T, D, L1, L2, epi>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename T, int D, int L1, int L2, int epi>
+__global__ __launch_bounds__(kThreads) void k2_lastfirst_b(const LastArgs<T>* __restrict__ tab)
+{
+    lastfirst_body<T, D, L1, L2, epi>(tab[blockIdx.y], blockIdx.x, gridDim.x);
 }
 
 // Lengths with specialised kernels; their splits L = L1 * L2 (L1 = 5, 7 or 9: the middle pass holds

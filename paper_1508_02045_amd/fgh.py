@@ -38,7 +38,7 @@ SOLVERS = {"richardson": FGH_RICHARDSON, "cg": FGH_CG, "chebyshev": FGH_CHEBYSHE
 
 EXPORTS = ["fgh_plan_workspace", "fgh_plan_create", "fgh_plan_destroy", "fgh_plan_grid_points",
            "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32", "fgh_apply_noalloc", "fgh_ga_coefficients", "fgh_solve",
-           "fgh_solve_fixed", "fgh_effective", "fgh_gani_bound", "fgh_plan_set_history", "fgh_estimate_bounds",
+           "fgh_solve_fixed", "fgh_solve_batch", "fgh_effective", "fgh_gani_bound", "fgh_plan_set_history", "fgh_estimate_bounds",
            "fgh_plan_set_bounds", "fgh_plan_set_profiling", "fgh_plan_read_profile", "fgh_request_footprint", "fgh_server_create", "fgh_server_submit", "fgh_server_poll",
            "fgh_server_wait", "fgh_server_drain", "fgh_server_stats", "fgh_server_destroy",
            "fgh_status_string"]
@@ -81,6 +81,8 @@ class Result(ctypes.Structure):
         return out
 
 
+RETIRE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int)
+
 _lib = None
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -112,6 +114,8 @@ def lib():
                                 ctypes.POINTER(Stats)]
         L.fgh_solve_fixed.argtypes = [_vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _vp,
                                       ctypes.POINTER(Stats)]
+        L.fgh_solve_batch.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int,
+                                      ctypes.POINTER(_vp), ctypes.POINTER(Stats), RETIRE_FN, _vp]
         L.fgh_effective.argtypes = [_vp, _dp, ctypes.c_int, _vp, _dp, _dp]
         L.fgh_gani_bound.argtypes = [_vp, _vp, _dp, _vp, _dp]
         L.fgh_plan_set_history.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]
@@ -134,7 +138,7 @@ def lib():
         L.fgh_status_string.argtypes = [ctypes.c_int]
         L.fgh_status_string.restype = ctypes.c_char_p
         for name in ("fgh_plan_workspace", "fgh_plan_create", "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32", "fgh_apply_noalloc",
-                     "fgh_ga_coefficients", "fgh_solve", "fgh_solve_fixed", "fgh_effective",
+                     "fgh_ga_coefficients", "fgh_solve", "fgh_solve_fixed", "fgh_solve_batch", "fgh_effective",
                      "fgh_gani_bound", "fgh_plan_set_history", "fgh_estimate_bounds", "fgh_plan_set_bounds",
                      "fgh_plan_set_profiling", "fgh_plan_read_profile"):
             getattr(L, name).restype = ctypes.c_int
@@ -229,6 +233,24 @@ def fgh_solve_fixed(plan, solver, E, nrhs, iters, e):
     st = lib().fgh_solve_fixed(ctypes.c_void_p(plan), int(solver), Ep, int(nrhs), int(iters), _ptr(e), stats)
     if st in (FGH_E_INVALID, FGH_E_UNSUPPORTED, FGH_E_DEVICE):
         raise FghError(st, "fgh_solve_fixed")
+    return st, [s.as_dict() for s in stats]
+
+
+def fgh_solve_batch(plans, solver, E, tol, max_iter, e, retire=None):
+    """Solves of one shape together (see include/fgh.h).  plans: plan handles; E: [n][d]; tol: [n];
+    e: device tensors (one per plan); retire: optional callable(k) called as member k finishes.
+    Returns (status, stats list)."""
+    n = len(plans)
+    Ek, Ep = _hostd(np.asarray(E, dtype=np.float64).reshape(n, -1))
+    Tk, Tp = _hostd(np.asarray(tol, dtype=np.float64).reshape(n))
+    hp = (_vp * n)(*[ctypes.c_void_p(h) for h in plans])
+    ep = (_vp * n)(*[ctypes.c_void_p(t.data_ptr()) for t in e])
+    stats = (Stats * n)()
+    cb = RETIRE_FN(lambda user, k: retire(k)) if retire is not None else RETIRE_FN()
+    st = lib().fgh_solve_batch(hp, n, int(SOLVERS.get(solver, solver)), Ep, Tp, int(max_iter), ep, stats, cb, None)
+    del Ek, Tk
+    if st in (FGH_E_INVALID, FGH_E_UNSUPPORTED, FGH_E_DEVICE, FGH_E_WORKSPACE, FGH_E_NOT_SPD):
+        raise FghError(st, "fgh_solve_batch")
     return st, [s.as_dict() for s in stats]
 
 
