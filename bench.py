@@ -342,7 +342,11 @@ def served_section(fgh, inputs, np, n_req, max_active=4, pool_gb=24):
     """Served stream (mixed d, N, rule, contrast, solver, tolerance; see inputs.serving_requests).
     Baseline: the same requests one at a time in plain FP64; its mean service time S sets the
     Poisson arrival rate 1/S (load 1 for the baseline).  Served: FP32 transforms with FP64
-    defect correction, `max_active` concurrent slots, admission by HBM footprint."""
+    defect correction, `max_active` worker slots, admission by HBM footprint, requests of one size
+    class solved together in shared launches.  Capacities (whole stream submitted at once) are
+    also given with shared launches switched off and for plain FP64 in the slots, to separate
+    the gains of batching, of FP32 and of overlap."""
+    import os
     reqs = inputs.serving_requests(n_req, inputs.config_rng(4))
 
     def pack(tables):
@@ -391,7 +395,22 @@ def served_section(fgh, inputs, np, n_req, max_active=4, pool_gb=24):
         span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
         return res, st, {"throughput_solves_per_s": round(n_req / span, 3),
                          "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
-                         "p99_latency_s": round(float(np.percentile(lat, 99)), 4)}
+                         "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+                         "peak_batch": st["peak_batch"], "groups": st["batches"]}
+
+    def capacity(prec, batching=True):
+        if not batching:
+            os.environ["FGH_BATCH"] = "0"
+        try:
+            srv = fgh.Server(int(pool_gb * (1 << 30)), max_active=max_active)
+            cids = [submit(srv, q, prec) for q in reqs]
+            cres = [srv.wait(i) for i in cids]
+            st = srv.stats()
+            srv.close()
+        finally:
+            os.environ.pop("FGH_BATCH", None)
+        span = max(r["t_done"] for r in cres) - min(r["t_submit"] for r in cres)
+        return n_req / span, cres, st
 
     served, seq = {}, {}
     res = st = None
@@ -406,13 +425,11 @@ def served_section(fgh, inputs, np, n_req, max_active=4, pool_gb=24):
         seq[f"at_load_{load:g}"] = {"p50_latency_s": round(float(np.percentile(lat64, 50)), 4),
                                     "p99_latency_s": round(float(np.percentile(lat64, 99)), 4)}
         log(f"[bench] served at load {load:g}: {rec}")
-    # capacity: the whole stream submitted at once
-    srv = fgh.Server(int(pool_gb * (1 << 30)), max_active=max_active)
-    cids = [submit(srv, q, fgh.FGH_FP32_REFINED) for q in reqs]
-    cres = [srv.wait(i) for i in cids]
-    cap_span = max(r["t_done"] for r in cres) - min(r["t_submit"] for r in cres)
-    srv.close()
-    cap = n_req / cap_span
+    cap, cres, cst = capacity(fgh.FGH_FP32_REFINED)
+    cap_nb, _, _ = capacity(fgh.FGH_FP32_REFINED, batching=False)
+    cap64, _, _ = capacity(fgh.FGH_FP64)
+    log(f"[bench] served capacity: FP32 refined {cap:.2f}/s (peak batch {cst['peak_batch']}, {cst['batches']} groups), "
+        f"without shared launches {cap_nb:.2f}/s, FP64 in the slots {cap64:.2f}/s, sequential FP64 {1 / s_mean:.2f}/s")
     rel = np.array([abs(r["energy"] - b["energy"]) / abs(b["energy"]) for r, b in zip(res, res64)])
     ok = sum(1 for r in res if r["status"] == 0)
     ok64 = sum(1 for r in res64 if r["status"] == 0)
@@ -420,7 +437,10 @@ def served_section(fgh, inputs, np, n_req, max_active=4, pool_gb=24):
             "arrival_rate_at_load_1_per_s": round(1.0 / s_mean, 3),
             "served_fp32_refined": {"capacity_solves_per_s": round(cap, 3), **served, "status_ok": ok,
                                     "peak_active": st["peak_active"],
-                                    "peak_pool_GB": round(st["peak_pool_bytes"] / 2 ** 30, 2)},
+                                    "peak_pool_GB": round(st["peak_pool_bytes"] / 2 ** 30, 2),
+                                    "capacity_peak_batch": cst["peak_batch"], "capacity_groups": cst["batches"]},
+            "served_fp32_refined_without_shared_launches": {"capacity_solves_per_s": round(cap_nb, 3)},
+            "served_fp64_in_slots": {"capacity_solves_per_s": round(cap64, 3)},
             "sequential_fp64": {"capacity_solves_per_s": round(1.0 / s_mean, 3), **seq, "status_ok": ok64,
                                 "latency_model": "single FIFO server, measured service times"},
             "capacity_ratio_served_vs_sequential": round(cap * s_mean, 3),

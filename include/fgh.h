@@ -190,9 +190,11 @@ fgh_status fgh_solve_fixed(fgh_plan plan, fgh_solver solver, const double* E, in
  * member's iterates, counts and results are bitwise those of fgh_solve on its plan alone.  Other
  * combinations solve the members one after another.  retire (may be NULL) is called as
  * retire(user, k) on the calling thread as soon as member k's e[k] and stats[k] are final, before
- * the others have finished; after that call plan k is no longer used by this call.  All work runs
- * on plans[0]'s internal stream after every member's stream has drained; blocks until done;
- * plans[0]'s captured loop graph is replaced.  stats: host fgh_stats[n] or NULL.  Returns the
+ * the others have finished; plan k is back on its own stream then, and for k >= 1 it and its
+ * buffers are no longer used by this call (the callback may release them).  Plan 0 hosts the
+ * shared stream and must stay alive until the call returns.  All work runs on plans[0]'s internal
+ * stream after every member's stream has drained; blocks until done; the captured loop graph of
+ * any member may be replaced.  stats: host fgh_stats[n] or NULL.  Returns the
  * worst member status; FGH_E_INVALID for mismatched, repeated or NULL plans, n outside [1, 64]
  * or a tolerance outside (0, 1). */
 typedef void (*fgh_retire_fn)(void* user, int member);
@@ -304,8 +306,12 @@ fgh_status fgh_plan_read_profile(fgh_plan plan, double* ms, int64_t* launches);
  * state of an admitted request stay in HBM until it retires.  A request is admitted (FIFO) once
  * its footprint -- plan workspace, fluctuation field on the integration grid (the 2N-1 grid for
  * Ga), phase map -- fits into the free part of the caller's device pool; concurrently running
- * requests overlap on the device.  Each request's arithmetic is that of fgh_solve on its own plan,
- * so its result does not depend on what else is in flight.  The coefficients of a request are a
+ * requests overlap on the device.  A slot that admits a request whose shape shares launches
+ * (FP32_REFINED CG or Eyre-Milton on a size-specialised grid, see fgh_solve_batch) also admits up
+ * to 7 queued requests of the same size class (d, N, rule, precision, solver, max_iter) that fit
+ * the pool and solves them together; each retires -- result posted, pool memory freed -- as soon
+ * as its own solve has finished.  Each request's arithmetic is that of fgh_solve on its own plan,
+ * so its result does not depend on what else is in flight (bitwise).  The coefficients of a request are a
  * phase map (host uint8, copied at submission) and a phase table, as for FGH_A_PHASE.
  * ------------------------------------------------------------------------------------------ */
 typedef struct fgh_server_s* fgh_server;
@@ -363,6 +369,10 @@ fgh_status fgh_server_drain(fgh_server server);
 
 /* Server clock, peak pool bytes in use and peak number of concurrently active requests. */
 fgh_status fgh_server_stats(fgh_server server, double* now_seconds, size_t* peak_pool_bytes, int* peak_active);
+
+/* Size-class batching: the largest group of requests admitted together and the number of groups
+ * (a request admitted alone counts as a group of one). */
+fgh_status fgh_server_batch_stats(fgh_server server, int* peak_batch, int64_t* batches);
 
 /* Stop the workers after the requests already admitted; requests still queued are discarded: their
  * result has status FGH_E_CANCELLED, and threads blocked in fgh_server_wait on them return it.

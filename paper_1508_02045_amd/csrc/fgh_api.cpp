@@ -18,6 +18,7 @@
 #include "fgh_internal.hpp"
 #include "fgh_launch.hpp"
 #include "fgh_v2.hpp"
+#include "fgh_batch.hpp"
 
 using namespace fgh;
 
@@ -1446,15 +1447,16 @@ ScratchLayout scratch_layout(const Geo& g)
 // results are those of fgh_solve on its plan.
 // ------------------------------------------------------------------------------------------
 struct BatchMember {
-    fgh_plan p;
-    int index;            // position in the caller's arrays
-    const double* E;      // load (host [d])
-    double tol;
-    double* e;            // device [d][grid]
+    fgh_plan p = nullptr;
+    int index = 0;        // position in the caller's arrays
+    const double* E = nullptr;  // load (host [d])
+    double tol = 0.0;
+    double* e = nullptr;  // device [d][grid]
     double normE = 0.0, normb = 0.0, rr = 0.0, res = 0.0, dnorm = 0.0;
     int outer = 0, inner = 0, applies = 0, status = FGH_OK;
     bool done = false;    // stopping test met
     bool active = true;   // still iterating
+    bool restored = false; // the plan has its own streams back (it may have been released)
     double eta = 0.0;     // inner relative tolerance of the current outer step
 };
 
@@ -1687,6 +1689,8 @@ fgh_status refined_batch(std::vector<BatchMember>& ms, fgh_solver solver, int ma
                          fgh_stats* stats, const std::function<void(int)>& retire)
 {
     const auto t0 = std::chrono::steady_clock::now();
+    // a finished member gets its own streams back before it is retired: the retire callback may
+    // release its plan, and nothing here touches it afterwards
     auto finish = [&](BatchMember& m) -> fgh_status {
         if (solver == FGH_EYRE_MILTON) {  // the fluctuation x - E
             fgh_plan p = m.p;
@@ -1703,6 +1707,8 @@ fgh_status refined_batch(std::vector<BatchMember>& ms, fgh_solver solver, int ma
         if (r) return r;
         HIPOK(hipStreamSynchronize(s));
         if (stats) stats[m.index] = st;
+        m.p->stream = m.p->op64.stream = m.p->op32.stream = m.p->caller;
+        m.restored = true;
         if (retire) retire(m.index);
         return FGH_OK;
     };
@@ -2362,6 +2368,29 @@ fgh_status fgh_solve_fixed(fgh_plan p, fgh_solver solver, const double* E, int n
     return solve_common(p, solver, E, nrhs, 0.5, iters, iters, e, stats);
 }
 
+}  // extern "C"
+
+namespace fgh {
+bool batching_enabled()
+{
+    const char* v = std::getenv("FGH_BATCH");
+    return !(v && v[0] == '0');
+}
+
+bool batch_shares_launches(int d, const int32_t* N, int rule, int precision, int solver)
+{
+    if (!batching_enabled()) return false;
+    if (precision != FGH_FP32_REFINED || (solver != FGH_CG && solver != FGH_EYRE_MILTON)) return false;
+    if (solver == FGH_EYRE_MILTON && rule == FGH_GA) return false;
+    Geo g;
+    if (!make_geo(d, N, rule, &g)) return false;
+    const Config c = choose_config(g, 8, 4);
+    return c.v2_row && c.v2_mid && (d == 2 || c.v2_axis);
+}
+}  // namespace fgh
+
+extern "C" {
+
 fgh_status fgh_solve_batch(fgh_plan* plans, int n, fgh_solver solver, const double* E, const double* tol,
                            int max_iter, double* const* e, fgh_stats* stats, fgh_retire_fn retire, void* user)
 {
@@ -2381,7 +2410,7 @@ fgh_status fgh_solve_batch(fgh_plan* plans, int n, fgh_solver solver, const doub
     if (solver == FGH_EYRE_MILTON && plans[0]->rule == FGH_GA) return FGH_E_UNSUPPORTED;
     const int d = plans[0]->d;
     bool shared = plans[0]->prec == FGH_FP32_REFINED && (solver == FGH_CG || solver == FGH_EYRE_MILTON) &&
-                  batchable(plans[0]->op32) && std::getenv("FGH_BATCH") == nullptr;
+                  batchable(plans[0]->op32) && fgh::batching_enabled();
     for (int k = 0; k < n && shared; k++)
         shared = same_launch_shape(plans[0], plans[k]) && !plans[k]->hist_fn && !plans[k]->op32.prof &&
                  !plans[k]->op64.prof;
@@ -2400,19 +2429,21 @@ fgh_status fgh_solve_batch(fgh_plan* plans, int n, fgh_solver solver, const doub
     }
     for (int k = 0; k < n; k++)
         if (hipStreamSynchronize(plans[k]->caller) != hipSuccess) return FGH_E_DEVICE;
-    // every member's work runs on the first member's internal stream (capturable)
+    // every member's work runs on the first member's internal stream (capturable); members that
+    // were not retired get their streams back on every way out
     hipStream_t s = plans[0]->sstream;
+    std::vector<BatchMember> ms(n);
     struct Swap {
-        fgh_plan* P;
-        int n;
+        std::vector<BatchMember>& ms;
+        hipStream_t s;
         ~Swap()
         {
-            (void)hipStreamSynchronize(P[0]->sstream);
-            for (int k = 0; k < n; k++) P[k]->stream = P[k]->op64.stream = P[k]->op32.stream = P[k]->caller;
+            (void)hipStreamSynchronize(s);
+            for (BatchMember& m : ms)
+                if (!m.restored && m.p) m.p->stream = m.p->op64.stream = m.p->op32.stream = m.p->caller;
         }
-    } swap{plans, n};
+    } swap{ms, s};
     for (int k = 0; k < n; k++) plans[k]->stream = plans[k]->op64.stream = plans[k]->op32.stream = s;
-    std::vector<BatchMember> ms(n);
     for (int k = 0; k < n; k++) {
         ms[k].p = plans[k];
         ms[k].index = k;

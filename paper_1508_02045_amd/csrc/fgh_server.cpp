@@ -1,7 +1,10 @@
 // fgh_server.cpp -- serving loop of libfgh: homogenization solves of mixed size, rule, contrast,
 // solver and tolerance submitted as they arrive, admitted by their HBM footprint into a
-// caller-provided device pool, and run concurrently (one HIP stream per active slot), each with
-// its fields and solver state resident in HBM from admission to retirement.
+// caller-provided device pool, and run concurrently (one HIP stream per worker slot), each with
+// its fields and solver state resident in HBM from admission to retirement.  A slot that admits a
+// request whose shape can share launches also admits queued requests of the same size class and
+// solves them together (fgh_solve_batch): one launch per pass for all of them; each retires, and
+// frees its pool memory, as soon as its own solve has finished.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,6 +21,7 @@
 #include <vector>
 
 #include "../../include/fgh.h"
+#include "fgh_batch.hpp"
 
 namespace {
 
@@ -101,6 +105,8 @@ struct fgh_server_s {
     std::chrono::steady_clock::time_point t0;
     size_t peak_used = 0;
     int peak_active = 0;
+    int peak_batch = 0;    // largest group solved together
+    long long batches = 0; // groups admitted
 
     double now() const
     {
@@ -135,40 +141,142 @@ fgh_status footprint(const fgh_request& r, size_t* bytes)
     return FGH_OK;
 }
 
-void run_job(fgh_server_s* sv, Job& job, hipStream_t stream, size_t off, fgh_result* res)
+constexpr int kServeBatch = 8;  // members of one shared-launch batch
+
+// Requests that can be solved together: same grid, rule, precision, solver and iteration cap.
+bool same_class(const fgh_request& a, const fgh_request& b)
 {
-    const fgh_request& r = job.req;
-    char* base = sv->pool + off;
+    if (a.d != b.d || a.rule != b.rule || a.precision != b.precision || a.solver != b.solver ||
+        a.max_iter != b.max_iter)
+        return false;
+    for (int k = 0; k < a.d; k++)
+        if (a.N[k] != b.N[k]) return false;
+    return true;
+}
+
+struct Admitted {
+    Job job;
+    size_t off = 0;
+    double t_admit = 0.0;
+    fgh_plan plan = nullptr;
+    double* e = nullptr;
+    fgh_result res{};
+    bool retired = false;  // fgh_solve_batch finished it (res filled)
+    bool posted = false;
+};
+
+// Finished request: its result is posted and its pool memory released.
+void post(fgh_server_s* sv, Admitted& a)
+{
+    if (a.posted) return;
+    a.res.id = a.job.id;
+    a.res.t_submit = a.job.t_submit;
+    a.res.t_admit = a.t_admit;
+    a.res.t_done = sv->now();
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->alloc.release(a.off, a.job.footprint);
+        sv->active--;
+        sv->results[a.job.id] = a.res;
+    }
+    a.posted = true;
+    sv->cv_work.notify_all();
+    sv->cv_done.notify_all();
+}
+
+// Plan of an admitted request inside its pool block: workspace, fluctuation field, phase map.
+fgh_status make_plan(fgh_server_s* sv, Admitted& a, hipStream_t stream)
+{
+    const fgh_request& r = a.job.req;
+    char* base = sv->pool + a.off;
     size_t ws = 0;
     (void)fgh_plan_workspace(r.d, r.N, (fgh_rule)r.rule, (fgh_precision)r.precision, FGH_A_PHASE, &ws);
-    void* workspace = base;
-    double* e = reinterpret_cast<double*>(base + align_up(ws));
+    a.e = reinterpret_cast<double*>(base + align_up(ws));
     uint8_t* phase = reinterpret_cast<uint8_t*>(base + align_up(ws) + align_up(grid_points(r) * r.d * sizeof(double)));
-    fgh_status st = FGH_OK;
-    if (hipMemcpyAsync(phase, job.phase.data(), job.phase.size(), hipMemcpyHostToDevice, stream) != hipSuccess ||
+    if (hipMemcpyAsync(phase, a.job.phase.data(), a.job.phase.size(), hipMemcpyHostToDevice, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
-        st = FGH_E_DEVICE;
-    fgh_plan plan = nullptr;
-    if (!st)
-        st = fgh_plan_create(&plan, r.d, r.N, (fgh_rule)r.rule, (fgh_precision)r.precision, FGH_A_PHASE, nullptr, phase, job.table.data(),
-                             r.n_phases, r.c_A, r.C_A, workspace, ws, stream);
-    fgh_stats stats{};
-    if (!st) {
-        const fgh_status s2 = fgh_solve(plan, (fgh_solver)r.solver, r.E, 1, r.tol, r.max_iter, e, &stats);
-        st = s2;
-        double bil = 0.0, flux[3] = {0, 0, 0};
-        if (s2 == FGH_OK || s2 == FGH_E_NO_CONVERGENCE) {
-            if (fgh_effective(plan, r.E, 1, e, &bil, flux) != FGH_OK) st = FGH_E_DEVICE;
+        return FGH_E_DEVICE;
+    return fgh_plan_create(&a.plan, r.d, r.N, (fgh_rule)r.rule, (fgh_precision)r.precision, FGH_A_PHASE, nullptr,
+                           phase, a.job.table.data(), r.n_phases, r.c_A, r.C_A, base, ws, stream);
+}
+
+// Result of a finished solve: the effective quantities of its fluctuation.
+void fill_result(Admitted& a, const fgh_stats& st)
+{
+    const fgh_request& r = a.job.req;
+    double bil = 0.0, flux[3] = {0, 0, 0};
+    int status = st.status;
+    if (status == FGH_OK || status == FGH_E_NO_CONVERGENCE)
+        if (fgh_effective(a.plan, r.E, 1, a.e, &bil, flux) != FGH_OK) status = FGH_E_DEVICE;
+    a.res.status = status;
+    a.res.energy = bil;
+    for (int c = 0; c < 3; c++) a.res.flux[c] = flux[c];
+    a.res.iters = st.iters;
+    a.res.outer_iters = st.outer_iters;
+    a.res.rel_res_true = st.rel_res_true;
+    a.res.solve_seconds = st.seconds;
+}
+
+struct BatchRun {
+    fgh_server_s* sv;
+    std::vector<Admitted*> members;  // with a plan, in the order given to fgh_solve_batch
+    std::vector<fgh_stats> stats;
+};
+
+// Called by fgh_solve_batch as member k finishes: result posted, and for k >= 1 its plan and pool
+// memory released at once (member 0 hosts the batch's shared stream until the call returns).
+void retire_member(void* user, int k)
+{
+    BatchRun* br = static_cast<BatchRun*>(user);
+    Admitted& a = *br->members[k];
+    fill_result(a, br->stats[k]);
+    a.retired = true;
+    if (k == 0) return;
+    fgh_plan_destroy(a.plan);
+    a.plan = nullptr;
+    post(br->sv, a);
+}
+
+void run_batch(fgh_server_s* sv, std::vector<Admitted>& B, hipStream_t stream)
+{
+    BatchRun br{sv, {}, {}};
+    for (Admitted& a : B) {
+        const fgh_status st = make_plan(sv, a, stream);
+        if (st) {
+            if (a.plan) fgh_plan_destroy(a.plan);
+            a.plan = nullptr;
+            a.res.status = st;
+            post(sv, a);
+        } else {
+            br.members.push_back(&a);
         }
-        res->energy = bil;
-        for (int c = 0; c < 3; c++) res->flux[c] = flux[c];
-        res->iters = stats.iters;
-        res->outer_iters = stats.outer_iters;
-        res->rel_res_true = stats.rel_res_true;
-        res->solve_seconds = stats.seconds;
     }
-    if (plan) fgh_plan_destroy(plan);
-    res->status = st;
+    const int n = (int)br.members.size();
+    if (n > 0) {
+        const fgh_request& r0 = br.members[0]->job.req;
+        const int d = r0.d;
+        std::vector<fgh_plan> plans(n);
+        std::vector<double> E((size_t)n * d), tol(n);
+        std::vector<double*> e(n);
+        for (int k = 0; k < n; k++) {
+            const Admitted& a = *br.members[k];
+            plans[k] = a.plan;
+            for (int c = 0; c < d; c++) E[(size_t)k * d + c] = a.job.req.E[c];
+            tol[k] = a.job.req.tol;
+            e[k] = a.e;
+        }
+        br.stats.assign(n, fgh_stats{});
+        const fgh_status st = fgh_solve_batch(plans.data(), n, (fgh_solver)r0.solver, E.data(), tol.data(), r0.max_iter,
+                                              e.data(), br.stats.data(), retire_member, &br);
+        for (int k = 0; k < n; k++) {
+            Admitted& a = *br.members[k];
+            if (a.posted) continue;
+            if (!a.retired) a.res.status = st != FGH_OK ? st : FGH_E_DEVICE;  // the batch failed before it finished
+            if (a.plan) fgh_plan_destroy(a.plan);
+            a.plan = nullptr;
+            post(sv, a);
+        }
+    }
 }
 
 void worker_main(fgh_server_s* sv)
@@ -177,14 +285,13 @@ void worker_main(fgh_server_s* sv)
     hipStream_t stream = nullptr;
     const bool have_stream = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess;
     for (;;) {
-        Job job;
-        size_t off = 0;
-        bool admitted = false;
-        double t_admit = 0.0;
+        std::vector<Admitted> batch;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
             // admit the head of the queue once its footprint fits the free pool (FIFO); when
             // nothing runs the whole pool is free, and every queued footprint fits the pool
+            size_t off = 0;
+            bool admitted = false;
             sv->cv_work.wait(lk, [&] {
                 if (sv->stop) return true;
                 if (sv->queue.empty()) return false;
@@ -197,30 +304,42 @@ void worker_main(fgh_server_s* sv)
                 return false;
             });
             if (!admitted) break;
-            job = std::move(sv->queue.front());
+            const double t_admit = sv->now();
+            batch.reserve(kServeBatch);  // members are referenced by address while the group runs
+            batch.emplace_back();
+            batch.back().job = std::move(sv->queue.front());
+            batch.back().off = off;
+            batch.back().t_admit = t_admit;
             sv->queue.pop_front();
-            sv->active++;
+            // queued requests of the head's size class join it while they fit the pool
+            const fgh_request h = batch.front().job.req;
+            if (fgh::batch_shares_launches(h.d, h.N, h.rule, h.precision, h.solver))
+                for (auto it = sv->queue.begin(); it != sv->queue.end() && (int)batch.size() < kServeBatch;) {
+                    size_t o = 0;
+                    if (same_class(it->req, h) && sv->alloc.alloc(it->footprint, &o)) {
+                        batch.emplace_back();
+                        batch.back().job = std::move(*it);
+                        batch.back().off = o;
+                        batch.back().t_admit = t_admit;
+                        it = sv->queue.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+            sv->active += (int)batch.size();
             sv->peak_active = std::max(sv->peak_active, sv->active);
             sv->peak_used = std::max(sv->peak_used, sv->alloc.used());
-            t_admit = sv->now();
+            sv->peak_batch = std::max(sv->peak_batch, (int)batch.size());
+            sv->batches++;
         }
-        fgh_result res{};
-        res.id = job.id;
-        res.t_submit = job.t_submit;
-        res.t_admit = t_admit;
-        if (have_stream)
-            run_job(sv, job, stream, off, &res);
-        else
-            res.status = FGH_E_DEVICE;
-        res.t_done = sv->now();
-        {
-            std::lock_guard<std::mutex> lk(sv->mu);
-            sv->alloc.release(off, job.footprint);
-            sv->active--;
-            sv->results[job.id] = res;
+        if (have_stream) {
+            run_batch(sv, batch, stream);
+        } else {
+            for (Admitted& a : batch) {
+                a.res.status = FGH_E_DEVICE;
+                post(sv, a);
+            }
         }
-        sv->cv_work.notify_all();
-        sv->cv_done.notify_all();
     }
     if (have_stream) (void)hipStreamDestroy(stream);
 }
@@ -342,6 +461,15 @@ fgh_status fgh_server_stats(fgh_server sv, double* now_seconds, size_t* peak_poo
     if (now_seconds) *now_seconds = sv->now();
     if (peak_pool_bytes) *peak_pool_bytes = sv->peak_used;
     if (peak_active) *peak_active = sv->peak_active;
+    return FGH_OK;
+}
+
+fgh_status fgh_server_batch_stats(fgh_server sv, int* peak_batch, int64_t* batches)
+{
+    if (!sv) return FGH_E_INVALID;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (peak_batch) *peak_batch = sv->peak_batch;
+    if (batches) *batches = sv->batches;
     return FGH_OK;
 }
 

@@ -40,7 +40,7 @@ EXPORTS = ["fgh_plan_workspace", "fgh_plan_create", "fgh_plan_destroy", "fgh_pla
            "fgh_plan_bounds", "fgh_apply", "fgh_apply_f32", "fgh_apply_noalloc", "fgh_ga_coefficients", "fgh_solve",
            "fgh_solve_fixed", "fgh_solve_batch", "fgh_effective", "fgh_gani_bound", "fgh_plan_set_history", "fgh_estimate_bounds",
            "fgh_plan_set_bounds", "fgh_plan_set_profiling", "fgh_plan_read_profile", "fgh_request_footprint", "fgh_server_create", "fgh_server_submit", "fgh_server_poll",
-           "fgh_server_wait", "fgh_server_drain", "fgh_server_stats", "fgh_server_destroy",
+           "fgh_server_wait", "fgh_server_drain", "fgh_server_stats", "fgh_server_batch_stats", "fgh_server_destroy",
            "fgh_status_string"]
 PASS_NAMES = ["first", "axis_fwd", "middle", "axis_inv", "last", "cg_update", "reduce"]
 
@@ -130,10 +130,11 @@ def lib():
         L.fgh_server_wait.argtypes = [_vp, ctypes.c_int64, ctypes.POINTER(Result)]
         L.fgh_server_drain.argtypes = [_vp]
         L.fgh_server_stats.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int)]
+        L.fgh_server_batch_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)]
         L.fgh_server_destroy.argtypes = [_vp]
         L.fgh_server_destroy.restype = None
         for name in ("fgh_request_footprint", "fgh_server_create", "fgh_server_submit", "fgh_server_poll",
-                     "fgh_server_wait", "fgh_server_drain", "fgh_server_stats"):
+                     "fgh_server_wait", "fgh_server_drain", "fgh_server_stats", "fgh_server_batch_stats"):
             getattr(L, name).restype = ctypes.c_int
         L.fgh_status_string.argtypes = [ctypes.c_int]
         L.fgh_status_string.restype = ctypes.c_char_p
@@ -529,7 +530,11 @@ class Server:
         peak = ctypes.c_size_t()
         act = ctypes.c_int()
         lib().fgh_server_stats(self.handle, ctypes.byref(now), ctypes.byref(peak), ctypes.byref(act))
-        return {"now": now.value, "peak_pool_bytes": peak.value, "peak_active": act.value}
+        pb = ctypes.c_int()
+        nb = ctypes.c_int64()
+        lib().fgh_server_batch_stats(self.handle, ctypes.byref(pb), ctypes.byref(nb))
+        return {"now": now.value, "peak_pool_bytes": peak.value, "peak_active": act.value, "peak_batch": pb.value,
+                "batches": nb.value}
 
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:

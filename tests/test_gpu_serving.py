@@ -137,3 +137,75 @@ def test_server_rejections():
         srv.submit(rq2)
     assert ei.value.status == fgh.FGH_E_WORKSPACE
     srv.close()
+
+
+def _class_requests(N, solver, count, seed):
+    rng = np.random.default_rng(seed)
+    d = len(N)
+    out = []
+    for k in range(count):
+        ph, _, _ = I.boolean_spheres(N, max(2, round(N[0] / 20)), float(rng.uniform(0.1, 0.4)), rng)
+        rho = float(10 ** rng.uniform(1, 4))
+        E = np.zeros(d)
+        E[0] = 1.0
+        out.append(dict(N=N, d=d, rule=0, solver=solver, tol=[1e-6, 1e-8][k % 2], phase=ph,
+                        tables=I.iso_tables(d, [1.0, rho]), E=E, rho=rho))
+    return out
+
+
+def test_size_classes_share_launches_and_retire_early():
+    """One worker slot and a queue of two size classes: the slot admits the head and the queued
+    requests of its class together (up to 8), solves them in shared launches, and each member
+    retires on its own; every served result equals the same request served alone, bitwise."""
+    fgh = F()
+    qs = _class_requests((45, 45, 45), "cg", 6, 5) + _class_requests((81, 81), "eyre_milton", 5, 6)
+    order = [0, 6, 1, 7, 2, 8, 3, 9, 4, 10, 5]  # the two classes interleaved in the queue
+    alone = []
+    for i in range(len(qs)):
+        srv = fgh.Server(2 << 30, max_active=1)
+        r, keep = _req(fgh, qs[i], fgh.FGH_FP32_REFINED)
+        alone.append(srv.wait(srv.submit(r)))
+        srv.close()
+    srv = fgh.Server(8 << 30, max_active=1)
+    # a slower plain-FP64 135^3 solve at the head keeps the slot busy while the others queue up
+    head = dict(_class_requests((135, 135, 135), "cg", 1, 4)[0], tol=1e-8)
+    rh, kh = _req(fgh, head, fgh.FGH_FP64)
+    hid = srv.submit(rh)
+    keeps, ids = [kh], {}
+    for i in order:
+        r, k = _req(fgh, qs[i], fgh.FGH_FP32_REFINED)
+        keeps.append(k)
+        ids[i] = srv.submit(r)
+    res = {i: srv.wait(ids[i]) for i in order}
+    assert srv.wait(hid)["status"] == 0
+    st = srv.stats()
+    srv.close()
+    # the head alone, then each class as one group
+    assert st["peak_batch"] == 6 and st["batches"] == 3, st
+    for i in order:
+        assert res[i]["status"] == 0 and alone[i]["status"] == 0
+        assert res[i]["energy"] == alone[i]["energy"] and res[i]["flux"] == alone[i]["flux"], i
+        assert res[i]["iters"] == alone[i]["iters"] and res[i]["outer_iters"] == alone[i]["outer_iters"]
+    # members of one group retire at different times (easy ones first)
+    group = [res[i] for i in range(6)]
+    assert len({r["t_admit"] for r in group}) == 1
+    assert max(r["t_done"] for r in group) - min(r["t_done"] for r in group) > 0.0
+
+
+def test_served_generic_729_request_against_oracle():
+    """A 729^2 request (no specialised length: generic kernels, served alone) in FP32 + FP64
+    refinement against the converged FP64 oracle."""
+    fgh = F()
+    q = _class_requests((729, 729), "cg", 1, 11)[0]
+    q["tables"] = I.iso_tables(2, [1.0, 10.0])
+    q["rho"] = 10.0
+    q["tol"] = 1e-8
+    srv = fgh.Server(2 << 30, max_active=2)
+    r, keep = _req(fgh, q, fgh.FGH_FP32_REFINED)
+    res = srv.wait(srv.submit(r))
+    srv.close()
+    assert res["status"] == 0, res
+    A = I.phase_to_full(q["phase"], q["tables"])
+    ro = orc.solve(q["N"], 0, A, q["E"], "cg", 1.0, 10.0, 1e-12, max_iter=20000)
+    en = orc.energy(q["N"], 0, A, q["E"], ro.e)
+    assert abs(res["energy"] - en) <= 1e-8 * en
