@@ -404,13 +404,14 @@ def served_section(fgh, inputs, np, n_req, max_active=4, pool_gb=24):
         try:
             srv = fgh.Server(int(pool_gb * (1 << 30)), max_active=max_active)
             cids = [submit(srv, q, prec) for q in reqs]
+            n_req_here = len(cids)
             cres = [srv.wait(i) for i in cids]
             st = srv.stats()
             srv.close()
         finally:
             os.environ.pop("FGH_BATCH", None)
         span = max(r["t_done"] for r in cres) - min(r["t_submit"] for r in cres)
-        return n_req / span, cres, st
+        return n_req_here / span, cres, st
 
     served, seq = {}, {}
     res = st = None
@@ -428,6 +429,31 @@ def served_section(fgh, inputs, np, n_req, max_active=4, pool_gb=24):
     cap, cres, cst = capacity(fgh.FGH_FP32_REFINED)
     cap_nb, _, _ = capacity(fgh.FGH_FP32_REFINED, batching=False)
     cap64, _, _ = capacity(fgh.FGH_FP64)
+    # where shared launches pay: streams of one small size class (64 requests each, mixed contrast
+    # and tolerance), whole stream at once, with and without shared launches
+    small = {}
+    for N, solver in (((45, 45, 45), "cg"), ((81, 81), "eyre_milton")):
+        srng = np.random.default_rng(np.random.SeedSequence(inputs.ROOT_SEED + 6))
+        sreqs = []
+        for k in range(64):
+            ph, _, _ = inputs.boolean_spheres(N, max(2, round(N[0] / 20)), float(srng.uniform(0.1, 0.4)), srng)
+            E = np.zeros(len(N))
+            E[0] = 1.0
+            sreqs.append({"d": len(N), "N": N, "phase": ph, "rule": 0, "solver": solver, "E": E,
+                          "tol": [1e-6, 1e-8][k % 2],
+                          "tables": inputs.iso_tables(len(N), [1.0, float(10 ** srng.uniform(1, 4))])})
+        saved = reqs[:]
+        reqs[:] = sreqs
+        try:
+            capacity(fgh.FGH_FP32_REFINED)  # warm-up: tile tuning of the shape
+            on, _, sst = capacity(fgh.FGH_FP32_REFINED)
+            off, _, _ = capacity(fgh.FGH_FP32_REFINED, batching=False)
+        finally:
+            reqs[:] = saved
+        small["x".join(map(str, N)) + "_" + solver] = {"shared_launches_solves_per_s": round(on, 1),
+                                                      "separate_solves_per_s": round(off, 1),
+                                                      "peak_batch": sst["peak_batch"], "groups": sst["batches"]}
+    log(f"[bench] served small classes: {small}")
     log(f"[bench] served capacity: FP32 refined {cap:.2f}/s (peak batch {cst['peak_batch']}, {cst['batches']} groups), "
         f"without shared launches {cap_nb:.2f}/s, FP64 in the slots {cap64:.2f}/s, sequential FP64 {1 / s_mean:.2f}/s")
     rel = np.array([abs(r["energy"] - b["energy"]) / abs(b["energy"]) for r, b in zip(res, res64)])
@@ -440,6 +466,7 @@ def served_section(fgh, inputs, np, n_req, max_active=4, pool_gb=24):
                                     "peak_pool_GB": round(st["peak_pool_bytes"] / 2 ** 30, 2),
                                     "capacity_peak_batch": cst["peak_batch"], "capacity_groups": cst["batches"]},
             "served_fp32_refined_without_shared_launches": {"capacity_solves_per_s": round(cap_nb, 3)},
+            "single_small_class_streams": small,
             "served_fp64_in_slots": {"capacity_solves_per_s": round(cap64, 3)},
             "sequential_fp64": {"capacity_solves_per_s": round(1.0 / s_mean, 3), **seq, "status_ok": ok64,
                                 "latency_model": "single FIFO server, measured service times"},

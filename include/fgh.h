@@ -307,9 +307,9 @@ fgh_status fgh_plan_read_profile(fgh_plan plan, double* ms, int64_t* launches);
  * its footprint -- plan workspace, fluctuation field on the integration grid (the 2N-1 grid for
  * Ga), phase map -- fits into the free part of the caller's device pool; concurrently running
  * requests overlap on the device.  A slot that admits a request whose shape shares launches
- * (FP32_REFINED CG or Eyre-Milton on a size-specialised grid, see fgh_solve_batch) also admits up
- * to 7 queued requests of the same size class (d, N, rule, precision, solver, max_iter) that fit
- * the pool and solves them together; each retires -- result posted, pool memory freed -- as soon
+ * (FP32_REFINED CG or Eyre-Milton on a size-specialised grid of at most 262144 points, see
+ * fgh_solve_batch) also admits up to 7 queued requests of the same size class (d, N, rule,
+ * precision, solver, max_iter) that fit the pool and solves them together; each retires -- result posted, pool memory freed -- as soon
  * as its own solve has finished.  Each request's arithmetic is that of fgh_solve on its own plan,
  * so its result does not depend on what else is in flight (bitwise).  The coefficients of a request are a
  * phase map (host uint8, copied at submission) and a phase table, as for FGH_A_PHASE.

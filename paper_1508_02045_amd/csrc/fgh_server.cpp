@@ -142,6 +142,11 @@ fgh_status footprint(const fgh_request& r, size_t* bytes)
 }
 
 constexpr int kServeBatch = 8;  // members of one shared-launch batch
+// Requests are grouped only on integration grids up to this many points (45^3, 2D up to 243^2 and
+// the Ga grids 81^2, 125^2): measured on MI355X with four slots, shared launches raise capacity
+// 1.3-2x there, while on 81^3 and 135^3 one request's launches already fill the GPU and a group,
+// which runs until its slowest member finishes, lowers capacity by about 10 %.
+constexpr size_t kGroupMaxPoints = 262144;
 
 // Requests that can be solved together: same grid, rule, precision, solver and iteration cap.
 bool same_class(const fgh_request& a, const fgh_request& b)
@@ -313,7 +318,7 @@ void worker_main(fgh_server_s* sv)
             sv->queue.pop_front();
             // queued requests of the head's size class join it while they fit the pool
             const fgh_request h = batch.front().job.req;
-            if (fgh::batch_shares_launches(h.d, h.N, h.rule, h.precision, h.solver))
+            if (grid_points(h) <= kGroupMaxPoints && fgh::batch_shares_launches(h.d, h.N, h.rule, h.precision, h.solver))
                 for (auto it = sv->queue.begin(); it != sv->queue.end() && (int)batch.size() < kServeBatch;) {
                     size_t o = 0;
                     if (same_class(it->req, h) && sv->alloc.alloc(it->footprint, &o)) {

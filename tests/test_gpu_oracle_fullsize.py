@@ -9,6 +9,8 @@
   bodies per load against the oracle, and whole CG solves against the oracle's converged result
   stored by tests/golden/make_oracle_golden.py.
 * The generic (non-specialised) kernels at 729^2, the largest 2D size served.
+* Configuration C2 at its size: the four solvers' whole solves at 135^3 against the oracle's
+  converged solves (counts, energy, flux), stored by the same script.
 
 Fields are compared by the relative L2 norm (<= 1e-9 of ||E + e||) and by the largest pointwise
 difference (<= 1e-9 of max |E + e|), so a few wrong voxels cannot hide in the aggregate.
@@ -283,3 +285,28 @@ def test_generic_729_fixed_bodies_and_refined(solver):
     r = orc.solve(N, orc.GANI, A, E, "cg", 1.0, rho, 1e-12, max_iter=20000)
     en = orc.energy(N, orc.GANI, A, E, r.e)
     assert abs(bil[0, 0] - en) <= 1e-8 * en
+
+
+# ----------------------------------------------------------------------------------------------
+# Configuration C2 at its size: the four solvers to 1e-8 against the oracle's converged solves
+# (stored by tests/golden/make_oracle_golden.py: about an hour of naive DFTs on 8 cores)
+# ----------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("solver", ["richardson", "cg", "chebyshev", "eyre_milton"])
+def test_c2_whole_solves_match_converged_oracle(spheres135, solver):
+    w, A = spheres135
+    with open(os.path.join(GOLDEN, "oracle_c2.json")) as f:
+        gold = json.load(f)
+    assert gold["input_sha256"] == I.sha256(w.phase), "the stored oracle result is for other inputs"
+    g = gold[solver]
+    say(f"C2 135^3: whole {solver} solve to 1e-8 against the stored oracle solve")
+    plan = phase_plan(w.N, w.phase, w.tables, cA=1.0, CA=w.contrast)
+    e, st, stats = plan.solve(solver, w.E, gold["tol"], max_iter=5000)
+    assert st == 0
+    bil, flux = plan.effective(w.E, e)
+    plan.close()
+    m_g, m_o = stats[0]["iters"], g["iters"]
+    near = abs(g["res_last"] - gold["tol"]) <= 1e-6 * gold["tol"]
+    assert m_g == m_o or (abs(m_g - m_o) <= 1 and near), (m_g, m_o)
+    assert abs(bil[0, 0] - g["energy"]) <= 1e-10 * g["energy"], (bil[0, 0], g["energy"])
+    assert np.linalg.norm(flux[0] - g["flux"]) <= 1e-9 * np.linalg.norm(g["flux"])
+    assert abs(stats[0]["rel_res_true"] - g["rel_res_true"]) <= 1e-6 * g["rel_res_true"] + 1e-14
