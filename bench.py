@@ -38,10 +38,10 @@ HBM_PEAK_GBS = 8000.0
 SOLVERS = ["richardson", "cg", "chebyshev", "eyre_milton"]
 KINDS = ["first", "axis_fwd", "middle", "axis_inv", "last", "cg_update", "reduce"]
 # kernels of one CG body on a specialised 3D grid, by launch kind
-CG_KERNELS = {"first": "k2_first<double,3> (p = r + beta p, A p, r2c of the last axis)",
+CG_KERNELS = {"first": "k2_first<double,3> (x += alpha p, p = r + beta p, A p, r2c of the last axis)",
               "axis_fwd": "k2_axis<double,forward>", "middle": "k2_middle<double,3,G>",
               "axis_inv": "k2_axis<double,inverse>", "last": "k2_last<double,3,EPI_CG> (c2r, q = C p, (q, p))",
-              "cg_update": "k_cg_update<double> (x += alpha p, r -= alpha q, (r, r))", "reduce": "k_reduce"}
+              "cg_update": "k_cg_update<double> (r -= alpha q, (r, r))", "reduce": "k_reduce"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_243.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1508_02045_amd", "csrc", f) for f in
                   ("fgh_kernels.hip", "fgh_fft.hpp", "fgh_internal.hpp", "fgh_v2.hpp", "fgh_args.hpp")]
@@ -80,12 +80,13 @@ def apply_bytes(N, p_bytes, a_bytes=1):
 
 
 def cg_kind_bytes(N, p_bytes, a_bytes=1):
-    """Algorithmic bytes per launch of each kernel of one CG body (Algorithm 2) with a phase map:
-    first: r, p in, p out, phase, spectrum out; strided / middle: spectrum in and out; last:
-    spectrum and p in, q out; update: x, p, r, q in, x, r out; reduce: the partial sums."""
+    """Algorithmic bytes per launch of each kernel of one CG body (Algorithm 2) with a phase map,
+    the previous body's x += alpha p done by the first pass: first: x, r, p in, x, p out, phase,
+    spectrum out; strided / middle: spectrum in and out; last: spectrum and p in, q out; update:
+    r, q in, r out; reduce: the partial sums."""
     d, npts, F, S = geometry(N, p_bytes)
-    return {"first": 3 * F + a_bytes * npts + S, "axis_fwd": 2 * S, "middle": 2 * S, "axis_inv": 2 * S,
-            "last": S + 2 * F, "cg_update": 6 * F, "reduce": 1024 * 8}
+    return {"first": 5 * F + a_bytes * npts + S, "axis_fwd": 2 * S, "middle": 2 * S, "axis_inv": 2 * S,
+            "last": S + 2 * F, "cg_update": 3 * F, "reduce": 1024 * 8}
 
 
 def phase_table(inputs, np, tables):
@@ -634,6 +635,28 @@ def main():
                 "profiled_step_ms": round(profiled_ms, 1), "kernel_ms_in_profiled_step": round(gpu_ms, 1),
                 "kernels": table}
     log(f"[bench] dominant kernel {dom}: {table[dom]['avg_us']} us, {table[dom]['frac']:.3f} of 8 TB/s")
+    # what streaming reaches on this device at the same working-set size: a device copy of one
+    # 243^3 FP64 vector field (344 MB each way), median of 5 runs of 20 copies
+    src = torch.empty((3,) + w.N, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    cts = []
+    for _ in range(5):
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record()
+        for _ in range(20):
+            dst.copy_(src)
+        c1.record()
+        c1.synchronize()
+        cts.append(c0.elapsed_time(c1) / 20 * 1e-3)
+    copy_gbs = 2 * src.numel() * 8 / statistics.median(cts) / 1e9
+    del src, dst
+    roofline["copy_GBs_same_size"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(table[dom]["alg_GBs"] / copy_gbs, 4)
+    log(f"[bench] device copy of a 344 MB field: {copy_gbs:.0f} GB/s ({copy_gbs / 8000:.3f} of 8 TB/s)")
 
     extra = {}
     fp64_seconds = {rho: statistics.median(seconds[rho]) for rho in rhos}

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
@@ -80,6 +81,13 @@ int env_int(const char* name, int dflt)
     if (!v) return dflt;
     const int x = std::atoi(v);
     return x > 0 ? x : dflt;
+}
+
+// the variable's integer value, zero and negative values included (dflt when unset)
+int env_int_any(const char* name, int dflt)
+{
+    const char* v = std::getenv(name);
+    return v ? std::atoi(v) : dflt;
 }
 
 // Tile choice per pass: the largest tile whose LDS footprint fits the budget (tuning knobs:
@@ -202,6 +210,8 @@ Layout make_layout(const Geo& g, const int32_t* N, int rule, int prec, int akind
         nM *= 2 * N[a] - 1;
     }
     if (rule == FGH_GA && v64 < (size_t)2 * nM * 16) v64 = (size_t)2 * nM * 16;
+    // and a third spectrum for the middle pass's tile timing
+    if (v64 < (size_t)d * sp * 16) v64 = (size_t)d * sp * 16;
     l.vec64 = take(v64);
     l.vec32 = take(prec == FGH_FP32_REFINED ? (size_t)4 * nv * 4 : 0);
     const Config c64 = choose_config(g, 16, 8);
@@ -405,6 +415,13 @@ void fill_opplan(fgh_plan p, OpPlan* op, bool f32)
                    p->stream);
 }
 
+// FGH_TUNE_LOG=1: the tuners print each candidate's time (three launches) to stderr.
+void tune_log(const char* pass, bool f32, int cand, int pad, float ms)
+{
+    static const bool on = env_int("FGH_TUNE_LOG", 0) != 0;
+    if (on) std::fprintf(stderr, "fgh tune %s %s: %d%s %.1f us\n", pass, f32 ? "fp32" : "fp64", cand, pad ? "+pad" : "", ms * 1e3f / 3);
+}
+
 // Tile width of the strided axis-1 passes (3D), measured at plan creation like the middle pass's:
 // powers of two and the widths that split the Hb columns of a half-spectrum row into equal tiles
 // (a ragged last tile leaves most of its workgroup idle).  The per-column arithmetic does not
@@ -455,6 +472,7 @@ fgh_status tune_axis(fgh_plan p, OpPlan* op, bool f32)
         if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
         float ms = 0.0f;
         if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        tune_log("axis", f32, P, 0, ms);
         if (ms < best_ms) {
             best_ms = ms;
             best = P;
@@ -494,7 +512,7 @@ fgh_status tune_middle(fgh_plan p, OpPlan* op, bool f32)
         }
     }
     // 7 is not tried: its 112-byte FP64 row segments split cache lines and add ~9 % written bytes
-    const int cand[] = {6, 8, 9, 10, 12, 16};
+    const int cand[] = {4, 5, 6, 8, 9, 10, 12, 16};
     hipEvent_t e0, e1;
     HIPOK(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -503,6 +521,7 @@ fgh_status tune_middle(fgh_plan p, OpPlan* op, bool f32)
     }
     int best = op->P_mid, best_pad = 0;
     float best_ms = 1e30f;
+    void* const bufs[3] = {g.d == 3 ? op->SB : op->SA, g.d == 3 ? op->SA : op->SB, p->ws + p->lay.vec64};
     hipError_t err = hipSuccess;
     for (int round = 0; round < 2 && err == hipSuccess; round++)
     for (int pad = 0; pad < 2 && err == hipSuccess; pad++)
@@ -513,14 +532,22 @@ fgh_status tune_middle(fgh_plan p, OpPlan* op, bool f32)
             o.mid_pad = pad;
             o.lds_mid = lds_of(P, pad);
             o.prof = nullptr;
-            if ((err = f32 ? run_middle_only<float>(o) : run_middle_only<double>(o)) != hipSuccess) break;
+            // the launches rotate over three buffers (the spectra and the vector storage, scratch
+            // at this point): a pass repeated on one spectrum that fits the last-level cache would
+            // be timed from the cache, not from HBM as in an application
+            auto run_on = [&](int k) {
+                OpPlan oo = o;
+                (g.d == 3 ? oo.SB : oo.SA) = bufs[k % 3];
+                return f32 ? run_middle_only<float>(oo) : run_middle_only<double>(oo);
+            };
+            if ((err = run_on(0)) != hipSuccess) break;
             if ((err = hipEventRecord(e0, o.stream)) != hipSuccess) break;
-            for (int r = 0; r < 3 && err == hipSuccess; r++)
-                err = f32 ? run_middle_only<float>(o) : run_middle_only<double>(o);
+            for (int r = 1; r <= 3 && err == hipSuccess; r++) err = run_on(r);
             if (err != hipSuccess || (err = hipEventRecord(e1, o.stream)) != hipSuccess) break;
             if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
             float ms = 0.0f;
             if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+            tune_log("middle", f32, P, pad, ms);
             if (ms < best_ms) {
                 best_ms = ms;
                 best = P;
@@ -591,6 +618,7 @@ fgh_status tune_first(fgh_plan p, OpPlan* op, bool f32, const void* x)
         if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
         float ms = 0.0f;
         if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        tune_log("first", f32, r, 0, ms);
         if (ms < best_ms) {
             best_ms = ms;
             best = r;
@@ -659,6 +687,7 @@ fgh_status tune_fused(fgh_plan p, OpPlan* op, bool f32, void* x)
         if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
         float ms = 0.0f;
         if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        tune_log("fused", f32, r, 0, ms);
         if (ms < best_ms) {
             best_ms = ms;
             best = r;
@@ -828,14 +857,18 @@ fgh_status run_loop(fgh_plan p, const OpPlan& op, Body body, uint64_t key, bool 
 
 // One body of Algorithm 2: p <- r + beta p (beta = 0 before the first body, p = r), q = C p,
 // alpha = (r, r) / (q, p), x += alpha p, r -= alpha q, beta = (r_new, r_new) / (r, r).  The
-// coefficients are left in the loop's scalar block.
+// coefficients are left in the loop's scalar block.  With defer_x the body's x += alpha p is left
+// to the next body's first pass, which reads p there anyway before replacing it (one vector
+// stream less per body; the same operation on the same values), and the loop's last update to
+// run_cg_x after the loop.
 template <typename T>
-hipError_t cg_body(const OpPlan& op, long long n, T* x, T* r, T* pv, T* q)
+hipError_t cg_body(const OpPlan& op, long long n, T* x, T* r, T* pv, T* q, bool defer_x)
 {
     ApplyArgs a;
     a.op = OP_AP_CG;
     a.p_cg = pv;
     a.r_cg = r;
+    a.x_cg = defer_x ? x : nullptr;
     a.epi = EPI_CG;
     a.eq = q;
     a.ep = pv;
@@ -844,12 +877,16 @@ hipError_t cg_body(const OpPlan& op, long long n, T* x, T* r, T* pv, T* q)
     hipError_t e = run_apply<T>(op, a, &nb);
     if (e != hipSuccess) return e;
     if ((e = run_reduce_async(op, nb, RED_CG_ALPHA)) != hipSuccess) return e;
-    if ((e = run_cg_update<T>(op, n, x, r, pv, q)) != hipSuccess) return e;
+    if ((e = run_cg_update<T>(op, n, defer_x ? nullptr : x, r, pv, q)) != hipSuccess) return e;
     return run_reduce_async(op, vec_blocks(), RED_CG_END);
 }
 
+constexpr double kLastLevelCacheBytes = 256.0 * 1024 * 1024;
+
 // Conjugate gradients (Algorithm 2) for C x = b with b already in r, x = 0 on entry.  Stops when
-// ||r_m|| <= tol_rel ||b|| (recursive residual) or after `fixed` bodies.
+// ||r_m|| <= tol_rel ||b|| (recursive residual) or after `fixed` bodies.  The iterate update is
+// deferred to the next body (cg_body) on large grids unless a history recorder reads x between
+// bodies.
 template <typename T>
 fgh_status cg_core(fgh_plan p, T* x, T* r, T* pv, T* q, double tol_rel, int max_iter, int fixed, SolveOut* out)
 {
@@ -866,10 +903,20 @@ fgh_status cg_core(fgh_plan p, T* x, T* r, T* pv, T* q, double tol_rel, int max_
     }
     const double normb = std::sqrt(bb / S);
     const int limit = fixed > 0 ? fixed : max_iter;
+    // alpha = 0 before the first body: its deferred update leaves x as it is
     HIPOK(run_init_loop(op, bb, 0.0, 0.0, fixed > 0 ? -1.0 : tol_rel * normb, S, 0.0, 0.0, 0.0, limit));
-    auto body = [&]() { return cg_body<T>(op, n, x, r, pv, q); };
-    const uint64_t key = key_of({1, sizeof(T), bits(x), bits(r), bits(pv), bits(q)});
-    return run_loop(p, op, body, key, fixed > 0, normb, out);
+    // deferral saves the update's x stream from HBM; when the loop's four vectors fit the device's
+    // last-level cache (256 MiB) that stream is served from the cache anyway, and the first pass
+    // is faster with its own, larger chunks (FGH_CG_DEFER=1 or 0 forces it on or off)
+    const int force = env_int_any("FGH_CG_DEFER", -1);
+    const bool defer_x =
+        !p->hist_fn && (force >= 0 ? force == 1 : 4.0 * (double)n * sizeof(T) > kLastLevelCacheBytes);
+    auto body = [&]() { return cg_body<T>(op, n, x, r, pv, q, defer_x); };
+    const uint64_t key = key_of({defer_x ? 2u : 1u, sizeof(T), bits(x), bits(r), bits(pv), bits(q)});
+    const fgh_status s = run_loop(p, op, body, key, fixed > 0, normb, out);
+    // the last body's x += alpha p (bodies after the stop return at once and leave alpha and p)
+    if (s == FGH_OK && defer_x) HIPOK(run_cg_x<T>(op, n, x, pv));
+    return s;
 }
 
 // Fused loop bodies (the last pass also runs the next body's first pass; the loop's first body
@@ -1995,12 +2042,14 @@ fgh_status fgh_plan_create(fgh_plan* out, int d, const int32_t* N, fgh_rule rule
     p->p32 = v32 + 2 * nv;
     p->q32 = v32 + 3 * nv;
     if ((s = upload_twiddles(p))) return fail(s);
-    // the tile timings below run the passes on the spectrum buffers and on r64 / r32: give them
-    // defined values (zeros and ones) instead of what the workspace held before
+    // the tile timings below run the passes on the spectrum buffers, on the vector storage (as a
+    // third spectrum) and on r64 / r32: give them defined values (zeros and ones) instead of what
+    // the workspace held before
     {
         const long long sp = std::max(p->g.s1, p->g.s2);
         if (run_fill<double>(p->stream, 2 * d * sp, reinterpret_cast<double*>(p->ws + p->lay.SA), 0.0) != hipSuccess ||
             run_fill<double>(p->stream, 2 * d * sp, reinterpret_cast<double*>(p->ws + p->lay.SB), 0.0) != hipSuccess ||
+            run_fill<double>(p->stream, 2 * d * sp, v64, 0.0) != hipSuccess ||
             run_fill<double>(p->stream, nv, p->r64, 1.0) != hipSuccess ||
             (precision == FGH_FP32_REFINED && run_fill<float>(p->stream, nv, p->r32, 1.0f) != hipSuccess))
             return fail(FGH_E_DEVICE);
@@ -2551,7 +2600,7 @@ fgh_status fgh_estimate_bounds(fgh_plan p, const double* E, int iters, double* e
     const Scalars* h = reinterpret_cast<const Scalars*>(p->host_buf);
     std::vector<double> al, be;
     for (int k = 0; k < iters; k++) {
-        HIPOK(cg_body<double>(op, n, e, p->r64, p->p64, p->q64));
+        HIPOK(cg_body<double>(op, n, e, p->r64, p->p64, p->q64, false));
         HIPOK(hipMemcpyAsync(p->host_buf, op.sc, sizeof(Scalars), hipMemcpyDeviceToHost, op.stream));
         HIPOK(hipStreamSynchronize(op.stream));
         if (!(h->alpha > 0.0) || !std::isfinite(h->alpha)) {

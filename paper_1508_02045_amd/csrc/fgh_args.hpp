@@ -88,6 +88,9 @@ struct FirstArgs {
     const T* x;
     T* p;
     const T* r;
+    // OP_AP_CG with a deferred iterate update: x += alpha p with the loop's current alpha and the
+    // p on entry, before p is replaced (nullptr: x is updated elsewhere)
+    T* xd;
     const Scalars* sc;
     double E[3];
     double omega;

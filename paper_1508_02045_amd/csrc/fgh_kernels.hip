@@ -54,7 +54,9 @@ __global__ __launch_bounds__(kThreads) void k_first(FirstArgs<T> a)
                 else if (OP == OP_E)
                     u[c] = T(a.E[c]);
                 else if (OP == OP_AP_CG) {
-                    const T pn = a.r[c * npts + pt] + beta * a.p[c * npts + pt];
+                    const T po = a.p[c * npts + pt];
+                    if (a.xd) a.xd[c * npts + pt] = fma(T(a.sc->alpha), po, a.xd[c * npts + pt]);
+                    const T pn = a.r[c * npts + pt] + beta * po;
                     a.p[c * npts + pt] = pn;
                     u[c] = pn;
                 } else
@@ -457,6 +459,47 @@ __global__ __launch_bounds__(kThreads) void k_reduce_multi(const double* __restr
 
 constexpr int kVecBlocks = 1024;
 
+// x += alpha p (UX; otherwise the next body's first pass applies it), r -= alpha q; returns this
+// thread's part of (r, r).  Four grid-strided points per batch, all loads issued before any use
+// (one memory latency per batch); each thread visits its points in increasing order.
+template <typename T, bool UX>
+__device__ __forceinline__ double cg_update_loop(long long n, T* __restrict__ x, T* __restrict__ r,
+                                                 const T* __restrict__ p, const T* __restrict__ q, T alpha,
+                                                 unsigned bx, unsigned gx)
+{
+    double acc = 0.0;
+    const long long stride = (long long)gx * blockDim.x;
+    long long i = (long long)bx * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        T xv[4], pv[4], rv[4], qv[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const long long j = i + u * stride;
+            if (UX) {
+                xv[u] = x[j];
+                pv[u] = p[j];
+            }
+            rv[u] = r[j];
+            qv[u] = q[j];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const long long j = i + u * stride;
+            if (UX) x[j] = fma(alpha, pv[u], xv[u]);
+            const T rn = rv[u] - alpha * qv[u];
+            r[j] = rn;
+            acc += double(rn) * double(rn);
+        }
+    }
+    for (; i < n; i += stride) {
+        if (UX) x[i] = fma(alpha, p[i], x[i]);
+        const T rv = r[i] - alpha * q[i];
+        r[i] = rv;
+        acc += double(rv) * double(rv);
+    }
+    return acc;
+}
+
 template <typename T>
 __device__ __forceinline__ void cg_update_body(long long n, T* __restrict__ x, T* __restrict__ r,
                                                const T* __restrict__ p, const T* __restrict__ q, const Scalars* s,
@@ -465,36 +508,8 @@ __device__ __forceinline__ void cg_update_body(long long n, T* __restrict__ x, T
     __shared__ double red[kThreads / 64];
     if (s->done) return;
     const T alpha = T(s->alpha);
-    double acc = 0.0;
-    // four grid-strided points per batch, all loads issued before any use (one memory latency per
-    // batch); each thread still visits its points in increasing order
-    const long long stride = (long long)gx * blockDim.x;
-    long long i = (long long)bx * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n; i += 4 * stride) {
-        T xv[4], pv[4], rv[4], qv[4];
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const long long j = i + u * stride;
-            xv[u] = x[j];
-            pv[u] = p[j];
-            rv[u] = r[j];
-            qv[u] = q[j];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const long long j = i + u * stride;
-            x[j] = xv[u] + alpha * pv[u];
-            const T rn = rv[u] - alpha * qv[u];
-            r[j] = rn;
-            acc += double(rn) * double(rn);
-        }
-    }
-    for (; i < n; i += stride) {
-        x[i] += alpha * p[i];
-        const T rv = r[i] - alpha * q[i];
-        r[i] = rv;
-        acc += double(rv) * double(rv);
-    }
+    const double acc = x ? cg_update_loop<T, true>(n, x, r, p, q, alpha, bx, gx)
+                         : cg_update_loop<T, false>(n, x, r, p, q, alpha, bx, gx);
     const double tot = block_sum(acc, red);
     if (threadIdx.x == 0) partials[bx] = tot;
 }
@@ -515,14 +530,15 @@ __global__ __launch_bounds__(kThreads) void k_cg_update_b(const UpdateArgs<T>* _
     cg_update_body<T>(a.n, a.x, a.r, a.p, a.q, a.sc, a.partials, blockIdx.x, gridDim.x);
 }
 
+// x += alpha p with the loop's last alpha: the update of a CG loop's final body, which the loop
+// leaves to the first pass of a body that does not run.  Not gated by the stop flag.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_cg_p(long long n, T* __restrict__ p, const T* __restrict__ r,
+__global__ __launch_bounds__(kThreads) void k_cg_x(long long n, T* __restrict__ x, const T* __restrict__ p,
                                                    const Scalars* s)
 {
-    if (s->done) return;
-    const T beta = T(s->beta);
+    const T alpha = T(s->alpha);
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        p[i] = r[i] + beta * p[i];
+        x[i] = fma(alpha, p[i], x[i]);
 }
 
 template <typename T>
@@ -1308,6 +1324,7 @@ static hipError_t build_bundle_d(const OpPlan& op, const ApplyArgs& a, ApplyBund
     fa.x = static_cast<const T*>(a.x);
     fa.p = static_cast<T*>(a.p_cg);
     fa.r = static_cast<const T*>(a.r_cg);
+    fa.xd = static_cast<T*>(a.x_cg);
     fa.sc = op.sc;
     const int* done = a.loop ? &op.sc->done : nullptr;
     fa.done = done;
@@ -1789,13 +1806,13 @@ template hipError_t run_cg_update<float>(const OpPlan&, long long, float*, float
 template hipError_t run_cg_update<double>(const OpPlan&, long long, double*, double*, const double*, const double*);
 
 template <typename T>
-hipError_t run_cg_p(const OpPlan& op, long long n, T* p, const T* r)
+hipError_t run_cg_x(const OpPlan& op, long long n, T* x, const T* p)
 {
-    hipLaunchKernelGGL(k_cg_p<T>, dim3(kVecBlocks), dim3(kThreads), 0, op.stream, n, p, r, op.sc);
+    hipLaunchKernelGGL(k_cg_x<T>, dim3(kVecBlocks), dim3(kThreads), 0, op.stream, n, x, p, op.sc);
     return hipGetLastError();
 }
-template hipError_t run_cg_p<float>(const OpPlan&, long long, float*, const float*);
-template hipError_t run_cg_p<double>(const OpPlan&, long long, double*, const double*);
+template hipError_t run_cg_x<float>(const OpPlan&, long long, float*, const float*);
+template hipError_t run_cg_x<double>(const OpPlan&, long long, double*, const double*);
 
 template <typename T>
 hipError_t run_fill(hipStream_t s, long long n, T* x, T v)

@@ -78,6 +78,7 @@ struct ApplyArgs {
     const void* x = nullptr; // first-pass input vector ([d][npts])
     void* p_cg = nullptr;    // OP_AP_CG: p (updated in place)
     const void* r_cg = nullptr;
+    void* x_cg = nullptr;    // OP_AP_CG: x += alpha p before p is replaced (the previous body's update)
     double E[3] = {0, 0, 0};
     double omega = 0.0;      // Eyre-Milton omega, Richardson omega
     double alpha = 0.0, beta = 0.0, sgn = 1.0;
@@ -206,7 +207,7 @@ int vec_blocks();
 template <typename T>
 hipError_t run_cg_update(const OpPlan& op, long long n, T* x, T* r, const T* p, const T* q);
 template <typename T>
-hipError_t run_cg_p(const OpPlan& op, long long n, T* p, const T* r);
+hipError_t run_cg_x(const OpPlan& op, long long n, T* x, const T* p);
 template <typename T>
 hipError_t run_fill(hipStream_t s, long long n, T* x, T v);
 template <typename T>

@@ -238,7 +238,7 @@ constexpr int ku_for(int L)
 
 // Stage 0 of the first pass for kU points starting at this thread's index base + threadIdx.x:
 // z = A(pt) u with u per FirstOp; writes the real rows Zr[(r D + c) L + i].
-template <typename T, int D, int L, int KU, bool IL = false>
+template <typename T, int D, int L, int KU, bool IL = false, bool XD = false>
 __device__ __forceinline__ void first_stage0_chunk(const FirstArgs<T>& a, int op, const T* tab, T beta, int base,
                                                    int total, int lim, long long pt0, T* Zr)
 {
@@ -266,6 +266,19 @@ __device__ __forceinline__ void first_stage0_chunk(const FirstArgs<T>& a, int op
                 rr[u][c] = comp(a.r, c, npts)[pt[u]];
                 pp[u][c] = comp(a.p, c, npts)[pt[u]];
             }
+        if (XD) {  // the previous body's x += alpha p, with p as it was on entry
+            const T al = T(a.sc->alpha);
+            T xx[KU][D];
+#pragma unroll
+            for (int u = 0; u < KU; u++)
+#pragma unroll
+                for (int c = 0; c < D; c++) xx[u][c] = comp(a.xd, c, npts)[pt[u]];
+#pragma unroll
+            for (int u = 0; u < KU; u++)
+#pragma unroll
+                for (int c = 0; c < D; c++)
+                    if (ok[u]) comp(a.xd, c, npts)[pt[u]] = fma(al, pp[u][c], xx[u][c]);
+        }
 #pragma unroll
         for (int u = 0; u < KU; u++)
 #pragma unroll
@@ -526,6 +539,24 @@ __device__ __forceinline__ long long xcd_tile(long long b, long long nb)
 //            B(k) = (X(k) - conj X(L-k)) / 2i, and store k < Hb row by row.
 // LDS: twiddles | Y (npairs rows) | Zr reals (2 npairs rows), reused as X (npairs rows).
 // ------------------------------------------------------------------------------------------
+// Points per lane and chunk of stage 0 of the first pass, per precision and length, from timings
+// of the pass alone: a tile of about two whole chunks keeps the most loads in flight.  Otherwise
+// FP32 chunks of at most 4 points keep four waves per SIMD at the longer rows.
+// kx: the same for CG's first pass with the deferred iterate update (three vectors per point).
+template <typename T, int L>
+struct FirstTune {
+    static constexpr int ku = (sizeof(T) == 4 && ku_for(L) > 4) ? 4 : ku_for(L);
+    static constexpr int kx = ku > 2 ? ku / 2 : ku;
+};
+template <>
+struct FirstTune<float, 243> {
+    static constexpr int ku = 6, kx = 4;  // kx = 6 is as fast but costs a wave per SIMD in every op
+};
+template <>
+struct FirstTune<double, 243> {
+    static constexpr int ku = 6, kx = 6;
+};
+
 // Stages A, B and S of the first pass in place on the packed complex rows Zc (row m holds real
 // rows 2m and 2m+1 as its real and imaginary parts).  Stage A maps all L1 jobs of one row to lanes
 // of one wavefront: the wavefront's lanes read all their inputs before any lane writes (one
@@ -600,7 +631,7 @@ __device__ __forceinline__ void first_transform_store_ip(const Args& a, long lon
 
 // First pass with one LDS buffer of npairs packed rows (the stages run in place).
 // LDS: twiddles | Zc (npairs complex rows) | phase table.
-template <typename T, int D, int L1, int L2>
+template <typename T, int D, int L1, int L2, int KU = FirstTune<T, L1 * L2>::ku, int KX = FirstTune<T, L1 * L2>::kx>
 __device__ __forceinline__ void first_body(const FirstArgs<T>& a, int op, long long b, long long nb)
 {
     if (a.done && *a.done) return;
@@ -623,11 +654,15 @@ __device__ __forceinline__ void first_body(const FirstArgs<T>& a, int op, long l
         const long long pt0 = row0 * L;
         const long long left = a.g.rows * (long long)L - pt0;
         const int lim = left < total ? (int)left : total;
-        // FP32: chunks of at most 4 points keep the pass at four waves per SIMD at the longest rows
-        constexpr int KU = (sizeof(T) == 4 && ku_for(L) > 4) ? 4 : ku_for(L);
-        for (int base = 0; base < total; base += KU * blockDim.x)
-            first_stage0_chunk<T, D, L, KU, true>(a, op, tab, beta, base, total, lim, pt0,
-                                                  reinterpret_cast<T*>(Zc));
+        if (op == OP_AP_CG && a.xd) {
+            for (int base = 0; base < total; base += KX * blockDim.x)
+                first_stage0_chunk<T, D, L, KX, true, true>(a, op, tab, beta, base, total, lim, pt0,
+                                                            reinterpret_cast<T*>(Zc));
+        } else {
+            for (int base = 0; base < total; base += KU * blockDim.x)
+                first_stage0_chunk<T, D, L, KU, true>(a, op, tab, beta, base, total, lim, pt0,
+                                                      reinterpret_cast<T*>(Zc));
+        }
     }
     lds_barrier();
     first_transform_store_ip<T, D, L1, L2>(a, row0, tw, Zc);
@@ -673,6 +708,8 @@ __device__ __forceinline__ void axis_body(const AxisArgs<T>& a, int B, long long
     lds_barrier();
     const cpx<T>* in = a.in + c * a.in_cs + o * a.in_os;
     cpx<T>* out = a.out + c * a.out_cs + o * a.out_os;
+    // a band as long as the axis (GaNi) maps every position to itself: no band test then
+    const bool banded = B != L;
     for (int job = threadIdx.x; job < P * L1; job += blockDim.x) {
         const int n1 = job / P;
         const int p = job - n1 * P;
@@ -683,7 +720,7 @@ __device__ __forceinline__ void axis_body(const AxisArgs<T>& a, int B, long long
             const int pos = n1 + L1 * n2;
             int si = pos;
             bool ok = j < a.inner;
-            if (a.bin) ok = ok && band_index(pos, L, B, &si);
+            if (a.bin && banded) ok = ok && band_index(pos, L, B, &si);
             s[n2] = ok ? in[(unsigned)(si * a.inner + j)] : cpx<T>{T(0), T(0)};
         }
         reg_dft<T, L2, INV>(s);
@@ -711,7 +748,7 @@ __device__ __forceinline__ void axis_body(const AxisArgs<T>& a, int B, long long
             for (int k1 = 0; k1 < L1; k1++) {
                 const int pos = k2 + L2 * k1;
                 int so = pos;
-                if (a.bout && !band_index(pos, L, B, &so)) continue;
+                if (a.bout && banded && !band_index(pos, L, B, &so)) continue;
                 out[(unsigned)(so * a.inner + j)] = s[k1];
             }
         }

@@ -113,3 +113,36 @@ def test_deferred_reduction_equals_separate(solver, N, prec):
         assert st == 0
         out.append((e.cpu().numpy(), stats[0]["iters"]))
     assert f0[0][1] == f1[0][1] == 7 and np.array_equal(f0[0][0], f1[0][0])
+
+
+@pytest.mark.parametrize("N,prec", [((45, 63, 81), 0), ((81, 45, 63), 1), ((63, 81), 0), ((21, 15, 27), 0)])
+def test_cg_deferred_update_equals_in_update(N, prec):
+    """CG's x += alpha p left to the next body's first pass (FGH_CG_DEFER=1; the last one after the
+    loop) against the update kernel doing it (FGH_CG_DEFER=0): the same operation on the same
+    alpha and p, so iterates, counts and residuals are bitwise equal, for the specialised and the
+    generic first pass (21 x 15 x 27), in FP64 and in the FP32 inner solves, and for a fixed
+    number of bodies."""
+    m = F()
+    d = len(N)
+    rng = np.random.default_rng(sum(N) + 11)
+    ph, _, _ = I.boolean_spheres(N, 4.0, 0.3, rng)
+    tab = np.stack([I.sym_pack(t[None])[:, 0] for t in I.iso_tables(d, [1.0, 30.0])])
+    plan = m.Plan(N, precision=prec, phase=torch.from_numpy(ph).cuda(), phase_table=tab)
+    E = np.array([1.0, -0.5, 0.25][:d])
+    print(f"CG deferred vs in-update x N={N} precision={prec}", flush=True)
+    (e0, s0), (e1, s1) = solve_both(plan, "cg", E, 1e-8, switch="FGH_CG_DEFER")
+    assert s0["iters"] == s1["iters"] and s0["outer_iters"] == s1["outer_iters"]
+    assert s0["rel_res_recursive"] == s1["rel_res_recursive"]
+    assert np.array_equal(e0, e1)
+    if prec != 0:
+        return  # fixed-count solves are FP64 only
+    f = []
+    for on in ("0", "1"):
+        os.environ["FGH_CG_DEFER"] = on
+        try:
+            e, st, stats = plan.solve_fixed("cg", E, 5)
+        finally:
+            os.environ.pop("FGH_CG_DEFER", None)
+        assert st == 0
+        f.append((e.cpu().numpy(), stats[0]["iters"]))
+    assert f[0][1] == f[1][1] == 5 and np.array_equal(f[0][0], f[1][0])
