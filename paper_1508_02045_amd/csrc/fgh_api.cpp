@@ -83,6 +83,9 @@ int env_int(const char* name, int dflt)
     return x > 0 ? x : dflt;
 }
 
+// The device's last-level cache (MI355X: 256 MiB of Infinity Cache).
+constexpr double kLastLevelCacheBytes = 256.0 * 1024 * 1024;
+
 // the variable's integer value, zero and negative values included (dflt when unset)
 int env_int_any(const char* name, int dflt)
 {
@@ -393,6 +396,8 @@ void fill_opplan_at(OpPlan* op, const Geo& g, bool f32, char* const tw[3], char*
     op->P_mid = c.P_mid;
     op->lds_first = c.lds_first;
     op->lds_first_v2 = c.lds_first_v2;
+    op->rpb_first_x = c.rpb;
+    op->lds_first_x = c.lds_first_v2;
     op->lds_last_v2 = c.lds_last_v2;
     op->rpb_fused = c.rpb;
     op->lds_fused = c.lds_last_v2 + kMaxPhases * 6 * (f32 ? 4 : 8);
@@ -629,6 +634,96 @@ fgh_status tune_first(fgh_plan p, OpPlan* op, bool f32, const void* x)
     if (err != hipSuccess) return FGH_E_DEVICE;
     op->rpb_first = best;
     op->lds_first_v2 = lds_of(best);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = best;
+    return FGH_OK;
+}
+
+// Whether CG defers its iterate update to the next body's first pass by default: when the loop's
+// four vectors exceed the last-level cache (below it the update's x stream is served from the
+// cache, and the first pass is faster with its own, larger chunks).
+bool cg_defers(long long n, size_t bytes_per_real) { return 4.0 * (double)n * bytes_per_real > kLastLevelCacheBytes; }
+
+// Rows per block of CG's first pass with the deferred iterate update (three vectors in, two out,
+// per point), timed like the first pass's but with the operator itself: once the coefficients are
+// set, on the plan's vectors as scratch, and only where CG defers the update by default.
+fgh_status tune_first_cg(fgh_plan p, OpPlan* op, bool f32)
+{
+    if (!op->v2_row || env_int("FGH_TUNE", 1) == 0 || std::getenv("FGH_RPB")) return FGH_OK;
+    const long long n = (long long)p->d * p->g.npts;
+    if (!cg_defers(n, f32 ? 4 : 8)) return FGH_OK;
+    static std::mutex mu;
+    static std::map<std::vector<long long>, int> cache;
+    const Geo& g = op->g;
+    const std::vector<long long> key = {f32 ? 1 : 0, g.d, g.L[g.d - 1], g.Hb, g.rows, op->A.kind};
+    const size_t cs = f32 ? 8 : 16;
+    const size_t tabb = kMaxPhases * 6 * (f32 ? 4 : 8);
+    const int L = g.L[g.d - 1];
+    auto lds_of = [&](int r) { return (size_t)(L + (size_t)((r * g.d + 1) / 2) * L) * cs + tabb; };
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            op->rpb_first_x = it->second;
+            op->lds_first_x = lds_of(it->second);
+            return FGH_OK;
+        }
+    }
+    // x, r, p: the plan's vectors (scratch until a solve), with defined values; alpha = beta = 0
+    void* xs = f32 ? (void*)p->x32 : (void*)p->q64;
+    void* rs = f32 ? (void*)p->r32 : (void*)p->r64;
+    void* ps = f32 ? (void*)p->p32 : (void*)p->p64;
+    if (f32) {
+        HIPOK(run_fill<float>(p->stream, n, p->x32, 0.0f));
+        HIPOK(run_fill<float>(p->stream, n, p->r32, 1.0f));
+        HIPOK(run_fill<float>(p->stream, n, p->p32, 0.0f));
+    } else {
+        HIPOK(run_fill<double>(p->stream, n, p->q64, 0.0));
+        HIPOK(run_fill<double>(p->stream, n, p->r64, 1.0));
+        HIPOK(run_fill<double>(p->stream, n, p->p64, 0.0));
+    }
+    HIPOK(run_init_loop(*op, 0.0, 0.0, 0.0, -1.0, (double)g.npts, 0.0, 0.0, 0.0, 1));
+    const int cand[] = {4, 6, 8, 10, 12, 16};
+    hipEvent_t e0, e1;
+    HIPOK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return FGH_E_DEVICE;
+    }
+    int best = op->rpb_first_x;
+    float best_ms = 1e30f;
+    hipError_t err = hipSuccess;
+    for (int round = 0; round < 2 && err == hipSuccess; round++)
+    for (int r : cand) {
+        if (lds_of(r) > 128 * 1024 || r > g.rows) continue;
+        OpPlan o = *op;
+        o.rpb_first_x = r;
+        o.lds_first_x = lds_of(r);
+        o.prof = nullptr;
+        auto run = [&]() {
+            return f32 ? run_first_cg_only<float>(o, static_cast<float*>(xs), static_cast<const float*>(rs),
+                                                  static_cast<float*>(ps))
+                       : run_first_cg_only<double>(o, static_cast<double*>(xs), static_cast<const double*>(rs),
+                                                   static_cast<double*>(ps));
+        };
+        if ((err = run()) != hipSuccess) break;
+        if ((err = hipEventRecord(e0, o.stream)) != hipSuccess) break;
+        for (int k = 0; k < 3 && err == hipSuccess; k++) err = run();
+        if (err != hipSuccess || (err = hipEventRecord(e1, o.stream)) != hipSuccess) break;
+        if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.0f;
+        if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        tune_log("first_cg", f32, r, 0, ms);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = r;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return FGH_E_DEVICE;
+    op->rpb_first_x = best;
+    op->lds_first_x = lds_of(best);
     std::lock_guard<std::mutex> lk(mu);
     cache[key] = best;
     return FGH_OK;
@@ -881,8 +976,6 @@ hipError_t cg_body(const OpPlan& op, long long n, T* x, T* r, T* pv, T* q, bool 
     return run_reduce_async(op, vec_blocks(), RED_CG_END);
 }
 
-constexpr double kLastLevelCacheBytes = 256.0 * 1024 * 1024;
-
 // Conjugate gradients (Algorithm 2) for C x = b with b already in r, x = 0 on entry.  Stops when
 // ||r_m|| <= tol_rel ||b|| (recursive residual) or after `fixed` bodies.  The iterate update is
 // deferred to the next body (cg_body) on large grids unless a history recorder reads x between
@@ -905,12 +998,10 @@ fgh_status cg_core(fgh_plan p, T* x, T* r, T* pv, T* q, double tol_rel, int max_
     const int limit = fixed > 0 ? fixed : max_iter;
     // alpha = 0 before the first body: its deferred update leaves x as it is
     HIPOK(run_init_loop(op, bb, 0.0, 0.0, fixed > 0 ? -1.0 : tol_rel * normb, S, 0.0, 0.0, 0.0, limit));
-    // deferral saves the update's x stream from HBM; when the loop's four vectors fit the device's
-    // last-level cache (256 MiB) that stream is served from the cache anyway, and the first pass
-    // is faster with its own, larger chunks (FGH_CG_DEFER=1 or 0 forces it on or off)
+    // deferral saves the update's x stream from HBM, on grids where it reaches HBM (cg_defers;
+    // FGH_CG_DEFER=1 or 0 forces it on or off)
     const int force = env_int_any("FGH_CG_DEFER", -1);
-    const bool defer_x =
-        !p->hist_fn && (force >= 0 ? force == 1 : 4.0 * (double)n * sizeof(T) > kLastLevelCacheBytes);
+    const bool defer_x = !p->hist_fn && (force >= 0 ? force == 1 : cg_defers(n, sizeof(T)));
     auto body = [&]() { return cg_body<T>(op, n, x, r, pv, q, defer_x); };
     const uint64_t key = key_of({defer_x ? 2u : 1u, sizeof(T), bits(x), bits(r), bits(pv), bits(q)});
     const fgh_status s = run_loop(p, op, body, key, fixed > 0, normb, out);
@@ -2192,6 +2283,8 @@ fgh_status fgh_plan_create(fgh_plan* out, int d, const int32_t* N, fgh_rule rule
     // the fused pass multiplies by A: tuned once the operator's coefficients are in place
     if ((s = tune_fused(p, &p->op64, false, p->r64))) return fail(s);
     if (precision == FGH_FP32_REFINED && (s = tune_fused(p, &p->op32, true, p->r32))) return fail(s);
+    if ((s = tune_first_cg(p, &p->op64, false))) return fail(s);
+    if (precision == FGH_FP32_REFINED && (s = tune_first_cg(p, &p->op32, true))) return fail(s);
     if (hipStreamSynchronize(p->stream) != hipSuccess) return fail(FGH_E_DEVICE);
     *out = p;
     return FGH_OK;

@@ -1082,7 +1082,7 @@ static hipError_t launch_axis(const OpPlan& op, const AxisArgs<T>& xa, bool inv,
 template <typename T, int D>
 static hipError_t v2_first(const OpPlan& op, const FirstArgs<T>& fa, int opc, unsigned nblk)
 {
-    const size_t lds = op.lds_first_v2;
+    const size_t lds = fa.xd ? op.lds_first_x : op.lds_first_v2;
     switch (fa.ax.L) {
 #define C(LL, A1, A2) \
     case LL: LAUNCH_LDS((k2_first<T, D, A1, A2>), dim3(nblk), lds, op.stream, fa, opc); break;
@@ -1317,7 +1317,7 @@ static hipError_t build_bundle_d(const OpPlan& op, const ApplyArgs& a, ApplyBund
     FirstArgs<T>& fa = bu->fa;
     fa.g = g;
     fa.ax = op.ax[last];
-    const int rpb1 = op.v2_row ? op.rpb_first : op.rpb;
+    const int rpb1 = op.v2_row ? (a.x_cg ? op.rpb_first_x : op.rpb_first) : op.rpb;
     bu->nblk1 = (unsigned)((g.rows + rpb1 - 1) / rpb1);
     fa.rpb = rpb1;
     fa.npen = (rpb1 * D + 1) / 2;
@@ -1525,6 +1525,30 @@ hipError_t run_first_only(const OpPlan& op, const T* x)
 }
 template hipError_t run_first_only<double>(const OpPlan&, const double*);
 template hipError_t run_first_only<float>(const OpPlan&, const float*);
+
+template <typename T>
+hipError_t run_first_cg_only(const OpPlan& op, T* x, const T* r, T* p)
+{
+    const Geo& g = op.g;
+    const int d = g.d;
+    FirstArgs<T> fa{};
+    fa.done = nullptr;
+    fa.g = g;
+    fa.ax = op.ax[d - 1];
+    fa.rpb = op.rpb_first_x;
+    fa.npen = (op.rpb_first_x * d + 1) / 2;
+    fa.p = p;
+    fa.r = r;
+    fa.xd = x;
+    fa.sc = op.sc;
+    fa.A = op.A;
+    fa.out = static_cast<cpx<T>*>(op.SA);
+    fa.twg = static_cast<const cpx<T>*>(op.tw[d - 1]);
+    const unsigned nblk = (unsigned)((g.rows + op.rpb_first_x - 1) / op.rpb_first_x);
+    return d == 2 ? v2_first<T, 2>(op, fa, OP_AP_CG, nblk) : v2_first<T, 3>(op, fa, OP_AP_CG, nblk);
+}
+template hipError_t run_first_cg_only<double>(const OpPlan&, double*, const double*, double*);
+template hipError_t run_first_cg_only<float>(const OpPlan&, float*, const float*, float*);
 
 template <typename T>
 hipError_t run_fused_only(const OpPlan& op, T* x)

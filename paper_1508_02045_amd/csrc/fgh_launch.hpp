@@ -60,6 +60,8 @@ struct OpPlan {
     int mid_pad;             // specialised middle pass: LDS column stride L + mid_pad (tuned)
     size_t lds_first, lds_axis, lds_mid;
     size_t lds_first_v2;     // the specialised first pass (one row buffer)
+    int rpb_first_x;         // the same for CG's first pass with the deferred iterate update (tuned)
+    size_t lds_first_x;
     size_t lds_last_v2;      // the specialised last pass (one row buffer)
     int rpb_fused;           // the fused last + first pass: rows per block (even or the last pass's; tuned)
     size_t lds_fused;        //   and its LDS (one row buffer, two coefficient tables)
@@ -208,6 +210,10 @@ template <typename T>
 hipError_t run_cg_update(const OpPlan& op, long long n, T* x, T* r, const T* p, const T* q);
 template <typename T>
 hipError_t run_cg_x(const OpPlan& op, long long n, T* x, const T* p);
+// CG's first pass with the deferred iterate update alone (tile timing): x += alpha p,
+// p = r + beta p, A p into SA
+template <typename T>
+hipError_t run_first_cg_only(const OpPlan& op, T* x, const T* r, T* p);
 template <typename T>
 hipError_t run_fill(hipStream_t s, long long n, T* x, T v);
 template <typename T>
