@@ -461,6 +461,7 @@ fgh_status tune_axis(fgh_plan p, OpPlan* op, bool f32)
     }
     int best = op->P_axis;
     float best_ms = 1e30f;
+    void* const bufs[3] = {op->SA, op->SB, p->ws + p->lay.vec64};
     hipError_t err = hipSuccess;
     // two rounds over the candidates: the fastest single timing wins (robust to a noisy first round)
     for (int round = 0; round < 2 && err == hipSuccess; round++)
@@ -470,9 +471,17 @@ fgh_status tune_axis(fgh_plan p, OpPlan* op, bool f32)
         o.P_axis = P;
         o.lds_axis = lds_of(P);
         o.prof = nullptr;
-        if ((err = f32 ? run_axis_only<float>(o) : run_axis_only<double>(o)) != hipSuccess) break;
+        // launches cycle A -> B, C -> A, B -> C over the spectra and the vector storage: each reads
+        // what the last-level cache has had two launches' data to drop since (see tune_middle)
+        auto run_on = [&](int k) {
+            OpPlan oo = o;
+            oo.SA = bufs[(3 - k % 3) % 3];
+            oo.SB = bufs[(4 - k % 3) % 3];
+            return f32 ? run_axis_only<float>(oo) : run_axis_only<double>(oo);
+        };
+        if ((err = run_on(0)) != hipSuccess) break;
         if ((err = hipEventRecord(e0, o.stream)) != hipSuccess) break;
-        for (int r = 0; r < 3 && err == hipSuccess; r++) err = f32 ? run_axis_only<float>(o) : run_axis_only<double>(o);
+        for (int r = 1; r <= 3 && err == hipSuccess; r++) err = run_on(r);
         if (err != hipSuccess || (err = hipEventRecord(e1, o.stream)) != hipSuccess) break;
         if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
         float ms = 0.0f;
@@ -604,6 +613,8 @@ fgh_status tune_first(fgh_plan p, OpPlan* op, bool f32, const void* x)
     }
     int best = op->rpb_first;
     float best_ms = 1e30f;
+    const void* const xs[3] = {x, f32 ? (const void*)p->p32 : (const void*)p->p64,
+                               f32 ? (const void*)p->q32 : (const void*)p->q64};
     hipError_t err = hipSuccess;
     for (int round = 0; round < 2 && err == hipSuccess; round++)
     for (int r : cand) {
@@ -612,13 +623,16 @@ fgh_status tune_first(fgh_plan p, OpPlan* op, bool f32, const void* x)
         o.rpb_first = r;
         o.lds_first_v2 = lds_of(r);
         o.prof = nullptr;
-        auto run = [&]() {
-            return f32 ? run_first_only<float>(o, static_cast<const float*>(x))
-                       : run_first_only<double>(o, static_cast<const double*>(x));
+        // launches cycle over three input vectors and two spectra (see tune_middle)
+        auto run = [&](int k) {
+            OpPlan oo = o;
+            oo.SA = k & 1 ? op->SB : op->SA;
+            return f32 ? run_first_only<float>(oo, static_cast<const float*>(xs[k % 3]))
+                       : run_first_only<double>(oo, static_cast<const double*>(xs[k % 3]));
         };
-        if ((err = run()) != hipSuccess) break;
+        if ((err = run(0)) != hipSuccess) break;
         if ((err = hipEventRecord(e0, o.stream)) != hipSuccess) break;
-        for (int k = 0; k < 3 && err == hipSuccess; k++) err = run();
+        for (int k = 1; k <= 3 && err == hipSuccess; k++) err = run(k);
         if (err != hipSuccess || (err = hipEventRecord(e1, o.stream)) != hipSuccess) break;
         if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
         float ms = 0.0f;
@@ -2140,9 +2154,10 @@ fgh_status fgh_plan_create(fgh_plan* out, int d, const int32_t* N, fgh_rule rule
         const long long sp = std::max(p->g.s1, p->g.s2);
         if (run_fill<double>(p->stream, 2 * d * sp, reinterpret_cast<double*>(p->ws + p->lay.SA), 0.0) != hipSuccess ||
             run_fill<double>(p->stream, 2 * d * sp, reinterpret_cast<double*>(p->ws + p->lay.SB), 0.0) != hipSuccess ||
-            run_fill<double>(p->stream, 2 * d * sp, v64, 0.0) != hipSuccess ||
+            run_fill<double>(p->stream, std::max(3 * nv, 2 * d * sp), v64, 0.0) != hipSuccess ||
             run_fill<double>(p->stream, nv, p->r64, 1.0) != hipSuccess ||
-            (precision == FGH_FP32_REFINED && run_fill<float>(p->stream, nv, p->r32, 1.0f) != hipSuccess))
+            (precision == FGH_FP32_REFINED && (run_fill<float>(p->stream, 4 * nv, v32, 0.0f) != hipSuccess ||
+                                               run_fill<float>(p->stream, nv, p->r32, 1.0f) != hipSuccess)))
             return fail(FGH_E_DEVICE);
     }
     if ((s = tune_middle(p, &p->op64, false))) return fail(s);
