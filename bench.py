@@ -384,11 +384,13 @@ def served_section(fgh, inputs, np, n_req, max_active=4, pool_gb=24):
         srv = fgh.Server(int(pool_gb * (1 << 30)), max_active=max_active)
         t0 = time.perf_counter()
         ids = []
-        for a, q in zip(arrivals, reqs):
+        for k, (a, q) in enumerate(zip(arrivals, reqs)):
             dt = t0 + a - time.perf_counter()
             if dt > 0:
                 time.sleep(dt)
             ids.append(submit(srv, q, fgh.FGH_FP32_REFINED))
+            if (k + 1) % 500 == 0:
+                log(f"[bench] served: {k + 1} of {n_req} requests submitted")
         res = [srv.wait(i) for i in ids]
         st = srv.stats()
         srv.close()
@@ -430,13 +432,16 @@ def served_section(fgh, inputs, np, n_req, max_active=4, pool_gb=24):
     cap, cres, cst = capacity(fgh.FGH_FP32_REFINED)
     cap_nb, _, _ = capacity(fgh.FGH_FP32_REFINED, batching=False)
     cap64, _, _ = capacity(fgh.FGH_FP64)
-    # where shared launches pay: streams of one small size class (64 requests each, mixed contrast
-    # and tolerance), whole stream at once, with and without shared launches
+    # where shared launches pay: streams of one size class (mixed contrast and tolerance), whole
+    # stream at once, with and without shared launches; the larger classes on long runs only
     small = {}
-    for N, solver in (((45, 45, 45), "cg"), ((81, 81), "eyre_milton")):
+    classes = [((45, 45, 45), "cg", 64), ((81, 81), "eyre_milton", 64)]
+    if n_req >= 1000:
+        classes += [((243, 243), "cg", 32), ((81, 81, 81), "cg", 32), ((135, 135, 135), "cg", 16)]
+    for N, solver, count in classes:
         srng = np.random.default_rng(np.random.SeedSequence(inputs.ROOT_SEED + 6))
         sreqs = []
-        for k in range(64):
+        for k in range(count):
             ph, _, _ = inputs.boolean_spheres(N, max(2, round(N[0] / 20)), float(srng.uniform(0.1, 0.4)), srng)
             E = np.zeros(len(N))
             E[0] = 1.0
@@ -451,7 +456,7 @@ def served_section(fgh, inputs, np, n_req, max_active=4, pool_gb=24):
             off, _, _ = capacity(fgh.FGH_FP32_REFINED, batching=False)
         finally:
             reqs[:] = saved
-        small["x".join(map(str, N)) + "_" + solver] = {"shared_launches_solves_per_s": round(on, 1),
+        small[f"{count}x" + "x".join(map(str, N)) + "_" + solver] = {"shared_launches_solves_per_s": round(on, 1),
                                                       "separate_solves_per_s": round(off, 1),
                                                       "peak_batch": sst["peak_batch"], "groups": sst["batches"]}
     log(f"[bench] served small classes: {small}")
