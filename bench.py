@@ -79,14 +79,26 @@ def apply_bytes(N, p_bytes, a_bytes=1):
     return 2 * F + a_bytes * npts + 2 * S + inner * 2 * S
 
 
-def cg_kind_bytes(N, p_bytes, a_bytes=1):
-    """Algorithmic bytes per launch of each kernel of one CG body (Algorithm 2) with a phase map,
-    the previous body's x += alpha p done by the first pass: first: x, r, p in, x, p out, phase,
-    spectrum out; strided / middle: spectrum in and out; last: spectrum and p in, q out; update:
-    r, q in, r out; reduce: the partial sums."""
+LAST_LEVEL_CACHE_BYTES = 256 * 1024 * 1024
+
+
+def cg_defers(N, p_bytes):
+    """Whether the library's CG leaves x += alpha p to the next body's first pass: when its four
+    vectors exceed the device's 256 MiB last-level cache (the library's rule)."""
     d, npts, F, S = geometry(N, p_bytes)
-    return {"first": 5 * F + a_bytes * npts + S, "axis_fwd": 2 * S, "middle": 2 * S, "axis_inv": 2 * S,
-            "last": S + 2 * F, "cg_update": 3 * F, "reduce": 1024 * 8}
+    return 4 * F > LAST_LEVEL_CACHE_BYTES
+
+
+def cg_kind_bytes(N, p_bytes, a_bytes=1):
+    """Algorithmic bytes per launch of each kernel of one CG body (Algorithm 2) with a phase map.
+    With the deferred iterate update (cg_defers): first: x, r, p in, x, p out, phase, spectrum out;
+    update: r, q in, r out.  Otherwise: first: r, p in, p out, phase, spectrum out; update: x, p,
+    r, q in, x, r out.  Strided / middle: spectrum in and out; last: spectrum and p in, q out;
+    reduce: the partial sums."""
+    d, npts, F, S = geometry(N, p_bytes)
+    defer = cg_defers(N, p_bytes)
+    return {"first": (5 if defer else 3) * F + a_bytes * npts + S, "axis_fwd": 2 * S, "middle": 2 * S,
+            "axis_inv": 2 * S, "last": S + 2 * F, "cg_update": (3 if defer else 6) * F, "reduce": 1024 * 8}
 
 
 def phase_table(inputs, np, tables):
@@ -486,9 +498,10 @@ COPY_BYTES = 512 * 1024 * 1024
 
 
 def counters_mode(args, fgh, inputs, torch, np):
-    """Runs for rocprofv3 counter collection at 243^3: `cg64` runs K fixed FP64 CG bodies of the
-    timed workload (rho = 1e3), `apply64` / `apply32` K plain applications; then a plain device
-    copy of COPY_BYTES each way that calibrates the HBM byte counters."""
+    """Runs for rocprofv3 counter collection (243^3 unless --n): `cg64` runs K fixed FP64 CG bodies
+    of the timed workload (rho = 1e3), `rich64` K fixed FP64 Richardson bodies (the fused last +
+    first pass), `apply64` / `apply32` K plain applications; then a plain device copy of
+    COPY_BYTES each way that calibrates the byte counters."""
     n = args.n
     w = inputs.config4(1e3, N=n)
     prec = fgh.FGH_FP32_REFINED if args.counters == "apply32" else fgh.FGH_FP64
@@ -498,6 +511,12 @@ def counters_mode(args, fgh, inputs, torch, np):
         e = plan.field()
         _, st, stats = plan.solve_fixed("cg", w.E, args.counter_reps, e=e)
         kb = cg_kind_bytes(w.N, 8)
+    elif args.counters == "rich64":
+        e = plan.field()
+        _, st, stats = plan.solve_fixed("richardson", w.E, args.counter_reps, e=e)
+        d, npts, F, S = geometry(w.N, 8)
+        # fused last + first: spectrum, x, phase in; x, next spectrum out
+        kb = {"fused": 2 * S + 2 * F + npts, "axis_fwd": 2 * S, "middle": 2 * S, "axis_inv": 2 * S}
     else:
         dt = torch.float64 if prec == fgh.FGH_FP64 else torch.float32
         x = torch.randn((3,) + w.N, dtype=dt, device="cuda")
@@ -530,7 +549,7 @@ def main():
     for name in ("apply", "refined", "c2", "c3", "served", "kappa", "monitors", "adaptive"):
         ap.add_argument(f"--no-{name}", action="store_true", help=f"skip the {name} section")
     ap.add_argument("--served-n", type=int, default=64)
-    ap.add_argument("--counters", choices=["cg64", "apply64", "apply32"], default=None,
+    ap.add_argument("--counters", choices=["cg64", "rich64", "apply64", "apply32"], default=None,
                     help="counter runs for rocprofv3 --pmc: K CG bodies or K applications at 243^3 and a copy "
                          "of known size for calibration, a summary line, nothing else")
     ap.add_argument("--counter-reps", type=int, default=5)
