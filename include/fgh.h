@@ -288,7 +288,8 @@ fgh_status fgh_plan_set_bounds(fgh_plan plan, double c_A, double C_A);
  * -- bit 0 first (A multiply + forward transform of the last axis), bit 1 forward strided axis,
  * bit 2 middle (transform of axis 0 with the Fourier multiplier), bit 3 inverse strided axis,
  * bit 4 last (inverse transform of the last axis + solver epilogue; in fused loops also the next
- * body's first pass), bit 5 CG update (x += alpha p, r -= alpha q, (r, r)), bit 6 single-workgroup
+ * body's first pass), bit 5 CG update (r -= alpha q, (r, r), and x += alpha p unless the next
+ * body's first pass applies it), bit 6 single-workgroup
  * loop reductions; 0 turns timing off.  Every launch of a selected kind is bracketed by HIP events
  * on the stream it runs on and its duration accumulated; solver loops then run without graph
  * replay.  Enabling resets the counters. */
