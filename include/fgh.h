@@ -184,8 +184,8 @@ fgh_status fgh_solve_fixed(fgh_plan plan, fgh_solver solver, const double* E, in
  * (distinct, same d, N, rule and precision) each solve C e = b for the load E[k] (host
  * double[n][d]) to tol[k] with `solver`, as fgh_solve on that plan with nrhs = 1 would; e[k]:
  * device double[d][grid] output of plan k.  For FGH_FP32_REFINED plans of a size-specialised
- * grid (45, 63, 81, 125, 135, 243 along every axis) with conjugate gradients or Eyre-Milton, the
- * inner FP32 loop bodies of up to 8 members run in shared launches (one launch per pass for all
+ * grid (45, 63, 81, 125, 135, 243 along every axis) with conjugate gradients or Eyre-Milton and
+ * n >= 2, the inner FP32 loop bodies of up to 8 members run in shared launches (one launch per pass for all
  * of them, one grid row per member) while each member's outer FP64 steps stay its own; a
  * member's iterates, counts and results are bitwise those of fgh_solve on its plan alone.  Other
  * combinations solve the members one after another.  retire (may be NULL) is called as
@@ -310,8 +310,10 @@ fgh_status fgh_plan_read_profile(fgh_plan plan, double* ms, int64_t* launches);
  * requests overlap on the device.  A slot that admits a request whose shape shares launches
  * (FP32_REFINED CG or Eyre-Milton on a size-specialised grid of at most 262144 points, see
  * fgh_solve_batch) also admits up to 7 queued requests of the same size class (d, N, rule,
- * precision, solver, max_iter) that fit the pool and solves them together; each retires -- result posted, pool memory freed -- as soon
- * as its own solve has finished.  Each request's arithmetic is that of fgh_solve on its own plan,
+ * precision, solver, max_iter) whose predicted work is within a factor 2 of its own (sqrt(C_A /
+ * c_A) log(2 / tol); C_A / c_A from the request or its phase table; a group runs until its
+ * slowest member is done) and that fit the pool, and solves them together; each retires --
+ * result posted, pool memory freed -- as soon as its own solve has finished.  Each request's arithmetic is that of fgh_solve on its own plan,
  * so its result does not depend on what else is in flight (bitwise).  The coefficients of a request are a
  * phase map (host uint8, copied at submission) and a phase table, as for FGH_A_PHASE.
  * ------------------------------------------------------------------------------------------ */

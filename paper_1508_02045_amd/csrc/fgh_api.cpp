@@ -2534,6 +2534,19 @@ bool batching_enabled()
     return !(v && v[0] == '0');
 }
 
+double phase_table_contrast(int d, const double* table, int n_phases)
+{
+    const int nc = d == 2 ? 3 : 6;
+    double lo = 0.0, hi = 0.0;
+    for (int i = 0; i < n_phases; i++) {
+        double l = 0.0, h = 0.0;
+        host_sym_eigs(d, table + (size_t)i * nc, &l, &h);
+        lo = i ? std::min(lo, l) : l;
+        hi = i ? std::max(hi, h) : h;
+    }
+    return lo > 0.0 && std::isfinite(hi) ? hi / lo : 0.0;
+}
+
 bool batch_shares_launches(int d, const int32_t* N, int rule, int precision, int solver)
 {
     if (!batching_enabled()) return false;
@@ -2566,7 +2579,9 @@ fgh_status fgh_solve_batch(fgh_plan* plans, int n, fgh_solver solver, const doub
     }
     if (solver == FGH_EYRE_MILTON && plans[0]->rule == FGH_GA) return FGH_E_UNSUPPORTED;
     const int d = plans[0]->d;
-    bool shared = plans[0]->prec == FGH_FP32_REFINED && (solver == FGH_CG || solver == FGH_EYRE_MILTON) &&
+    // a single member runs as fgh_solve (the shared-launch driver's tables and per-member graphs
+    // only pay when launches are shared)
+    bool shared = n > 1 && plans[0]->prec == FGH_FP32_REFINED && (solver == FGH_CG || solver == FGH_EYRE_MILTON) &&
                   batchable(plans[0]->op32) && fgh::batching_enabled();
     for (int k = 0; k < n && shared; k++)
         shared = same_launch_shape(plans[0], plans[k]) && !plans[k]->hist_fn && !plans[k]->op32.prof &&

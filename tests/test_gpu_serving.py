@@ -139,13 +139,13 @@ def test_server_rejections():
     srv.close()
 
 
-def _class_requests(N, solver, count, seed):
+def _class_requests(N, solver, count, seed, log_rho=(1.0, 4.0)):
     rng = np.random.default_rng(seed)
     d = len(N)
     out = []
     for k in range(count):
         ph, _, _ = I.boolean_spheres(N, max(2, round(N[0] / 20)), float(rng.uniform(0.1, 0.4)), rng)
-        rho = float(10 ** rng.uniform(1, 4))
+        rho = float(10 ** rng.uniform(*log_rho))
         E = np.zeros(d)
         E[0] = 1.0
         out.append(dict(N=N, d=d, rule=0, solver=solver, tol=[1e-6, 1e-8][k % 2], phase=ph,
@@ -155,10 +155,11 @@ def _class_requests(N, solver, count, seed):
 
 def test_size_classes_share_launches_and_retire_early():
     """One worker slot and a queue of two size classes: the slot admits the head and the queued
-    requests of its class together (up to 8), solves them in shared launches, and each member
+    requests of its class together (up to 8; contrasts 100-160 and tolerances 1e-6 / 1e-8, so
+    their predicted work is within a factor 2), solves them in shared launches, and each member
     retires on its own; every served result equals the same request served alone, bitwise."""
     fgh = F()
-    qs = _class_requests((45, 45, 45), "cg", 6, 5) + _class_requests((81, 81), "eyre_milton", 5, 6)
+    qs = _class_requests((45, 45, 45), "cg", 6, 5, (2.0, 2.2)) + _class_requests((81, 81), "eyre_milton", 5, 6, (2.0, 2.2))
     order = [0, 6, 1, 7, 2, 8, 3, 9, 4, 10, 5]  # the two classes interleaved in the queue
     alone = []
     for i in range(len(qs)):
@@ -190,6 +191,34 @@ def test_size_classes_share_launches_and_retire_early():
     group = [res[i] for i in range(6)]
     assert len({r["t_admit"] for r in group}) == 1
     assert max(r["t_done"] for r in group) - min(r["t_done"] for r in group) > 0.0
+
+
+def test_size_class_groups_keep_similar_work_together():
+    """Requests of one size class whose predicted work (sqrt(contrast) log(2/tol)) differs by more
+    than a factor 2 are not grouped: behind a blocking head, three easy (contrast 10) and three
+    hard (contrast 1e4) 45^3 CG requests form two groups of three."""
+    fgh = F()
+    easy = _class_requests((45, 45, 45), "cg", 3, 21, (1.0, 1.0))
+    hard = _class_requests((45, 45, 45), "cg", 3, 22, (4.0, 4.0))
+    srv = fgh.Server(8 << 30, max_active=1)
+    head = dict(_class_requests((135, 135, 135), "cg", 1, 4)[0], tol=1e-8)
+    rh, kh = _req(fgh, head, fgh.FGH_FP64)
+    hid = srv.submit(rh)
+    keeps, ids = [kh], []
+    for q in (easy[0], hard[0], easy[1], hard[1], easy[2], hard[2]):
+        r, k = _req(fgh, q, fgh.FGH_FP32_REFINED)
+        keeps.append(k)
+        ids.append(srv.submit(r))
+    res = [srv.wait(i) for i in ids]
+    assert srv.wait(hid)["status"] == 0
+    st = srv.stats()
+    srv.close()
+    assert all(r["status"] == 0 for r in res)
+    assert st["peak_batch"] == 3 and st["batches"] == 3, st
+    # the easy ones were admitted together, the hard ones together, easy first (queue order)
+    assert len({res[i]["t_admit"] for i in (0, 2, 4)}) == 1
+    assert len({res[i]["t_admit"] for i in (1, 3, 5)}) == 1
+    assert res[0]["t_admit"] < res[1]["t_admit"]
 
 
 def test_served_generic_729_request_against_oracle():
